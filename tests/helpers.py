@@ -1,0 +1,44 @@
+"""Small helpers shared by the tests (input construction and error metrics)."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_1606_04427_amd.synth import ParticleSet, Pose
+
+
+def particles(xyz, h, intensity=None, scalar=None, species=None, absorption=None) -> ParticleSet:
+    xyz = np.asarray(xyz, dtype=np.float32).reshape(-1, 3)
+    n = xyz.shape[0]
+    h = np.broadcast_to(np.asarray(h, dtype=np.float32), (n,)).copy()
+    inten = np.ones(n, np.float32) if intensity is None else np.broadcast_to(
+        np.asarray(intensity, np.float32), (n,)).copy()
+    sc = np.zeros(n, np.float32) if scalar is None else np.broadcast_to(
+        np.asarray(scalar, np.float32), (n,)).copy()
+    sp = np.zeros(n, np.uint8) if species is None else np.asarray(species, np.uint8).copy()
+    ab = None if absorption is None else np.broadcast_to(
+        np.asarray(absorption, np.float32), (n,)).copy()
+    return ParticleSet(xyz[:, 0].copy(), xyz[:, 1].copy(), xyz[:, 2].copy(), h, inten, sc, sp, ab)
+
+
+def axis_camera(width=64, height=64, dist=10.0, fov=90.0, z_near=1e-3) -> Pose:
+    """Camera on the +z axis looking at the origin, up = +y."""
+    return Pose((0.0, 0.0, dist), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), fov, z_near, width, height)
+
+
+def flat_look(rgb=(1.0, 1.0, 1.0), brightness=1.0):
+    return dict(rgb=np.asarray([rgb], np.float32), log10=0, brightness=brightness, lo=0.0, hi=1.0)
+
+
+def rel_l2(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.linalg.norm(ref.ravel())
+    return float(np.linalg.norm((a - ref).ravel()) / (den if den > 0 else 1.0))
+
+
+def random_rotation(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q @ np.diag(np.sign(np.diag(r)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
