@@ -1,0 +1,211 @@
+/*
+ * splotch.h -- C ABI of the MI355X (gfx950) Splotch render library.
+ *
+ * Method: Dykes, Gheller, Rivi, Krokos, "Splotch: porting and optimizing for
+ * the Xeon Phi" (arXiv:1606.04427).  The calls follow the problem statement of
+ * Sect. 2.1: particle arrays (positions, radius, scalar fields), camera and
+ * look-at positions, colour maps loaded at run time and render parameters go
+ * in; a single-precision RGB image comes out.  Sect. 3.1 fixes the render
+ * organisation (square tiles, one particle list per tile, each tile's pixels
+ * owned by one worker).
+ *
+ * Conventions shared by every call:
+ *  - Device pointers are HIP device memory on the context's device; host
+ *    pointers are marked "host".  The caller owns every array it passes in
+ *    and every output buffer; the library owns only its context workspace.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *    on it; calls that return host values (counts, statistics, ranges)
+ *    synchronise that stream before returning.
+ *  - Every call returns an spl_status.  On error nothing is written to
+ *    out-parameters and spl_last_error() describes the failure.  No C++
+ *    exception crosses the ABI.
+ *  - A context is not thread-safe: one host thread per context.
+ *  - Images are height x width x 3 float32, row-major, row 0 at the top,
+ *    channel-minor.  Pixel (i, j) covers [i, i+1) x [j, j+1).
+ */
+#ifndef SPLOTCH_H
+#define SPLOTCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPL_OK = 0,
+  SPL_EINVAL = -1,      /* invalid argument (camera, parameters, sizes) */
+  SPL_ENOMEM = -2,      /* device allocation failed */
+  SPL_EDEVICE = -3,     /* HIP runtime error (no device, launch failure) */
+  SPL_EBUSY = -4,       /* request refused by the memory budget */
+  SPL_EUNSUPPORTED = -5 /* valid request this build does not handle */
+} spl_status;
+
+typedef enum { SPL_F32 = 0, SPL_BF16 = 1, SPL_F16 = 2 } spl_dtype;
+
+/* Radiative-transfer modes (Sect. 2.1, "radiative transfer equation";
+ * Sect. 3.2.2, additive drawing of colour x contribution). */
+typedef enum {
+  SPL_ADD_RAW = 0,  /* J = sum_p E_p tau_p */
+  SPL_ADD_AEQE = 1, /* absorption = emission: I = 1 - exp(-J) */
+  SPL_SORTED = 2    /* separate absorption, depth-ordered slab compositing */
+} spl_mode;
+
+#define SPL_MAX_SPECIES 8
+
+/* Particles, structure of arrays, device memory (Sect. 2.1: positions,
+ * radius, scalar fields; Sect. 4.1: gas and star species). */
+typedef struct {
+  int64_t n;
+  const float *x, *y, *z;    /* world positions, n floats each */
+  const void *h;             /* smoothing length, n x attr_dtype */
+  const void *intensity;     /* n x attr_dtype */
+  const void *scalar;        /* colour scalar, n x attr_dtype */
+  int32_t attr_dtype;        /* spl_dtype of h, intensity, scalar */
+  float h_scale;             /* world smoothing length = h_scale * h */
+  const uint8_t *species;    /* n bytes, or NULL (all species 0) */
+  const float *absorption;   /* n floats, SPL_SORTED only, else ignored */
+} spl_particles;
+
+/* Camera and look-at positions (Sect. 2.1).  Forward = lookat - eye, right =
+ * forward x up, vertical field of view in degrees, (0, 180).  Particles at
+ * view depth <= z_near are clipped.  1 <= width, height <= 32768. */
+typedef struct {
+  double eye[3], lookat[3], up[3];
+  double fov_y_deg, z_near;
+  int32_t width, height;
+} spl_camera;
+
+/* One colour map per species (Sect. 2.1 "color map loaded at runtime"; the
+ * scene file varies brightness and palette thresholds).  rgb: device memory,
+ * n_entries x 3 floats, entries evenly spaced over the normalised scalar.
+ * The (log10 if log10_scalar) scalar is normalised by [lo, hi], hi >= lo. */
+typedef struct {
+  const float *rgb;
+  int32_t n_entries;    /* 1 .. 4096 */
+  int32_t log10_scalar;
+  double brightness;
+  double lo, hi;
+} spl_look;
+
+typedef struct {
+  int32_t mode;       /* spl_mode */
+  int32_t n_species;  /* 1 .. SPL_MAX_SPECIES */
+  spl_look looks[SPL_MAX_SPECIES];
+  double k_sigma;     /* kernel width sigma = sqrt((k_sigma rho)^2 + sigma_min^2) */
+  double sigma_min;   /* px, > 0 */
+  double nu;          /* truncation radius R = nu sigma, > 0 */
+  int32_t tile;       /* tile edge in px: 16 or 32; 0 = library choice */
+  int32_t bin_rule;   /* 0 = every tile the pixel box touches; 1 = the paper's
+                         0.75 R + sqrt(2) tile/2 distance threshold */
+  double large_cut;   /* px: particles with R > large_cut take the large-
+                         particle path (additive modes); 0 = library choice,
+                         < 0 = never */
+  int32_t normalise;  /* 1: divide the image by its maximum value */
+} spl_params;
+
+/* Per-render statistics; flux and max are FP64 reductions over the final
+ * image.  Stage times are filled only when timing is enabled. */
+typedef struct {
+  int64_t n_active;      /* particles that reach the image */
+  int64_t n_large;       /* of which on the large-particle path */
+  int64_t n_pairs;       /* (particle, tile) entries in the tile lists */
+  int64_t n_large_pairs; /* (particle, large tile) entries */
+  int64_t n_items;       /* splat work items */
+  double flux[3];        /* sum over pixels, per channel */
+  double max[3];         /* maximum pixel value, per channel */
+  int32_t tile;          /* tile size used */
+  double large_cut;      /* large-particle cut used, px */
+} spl_stats;
+
+typedef struct spl_ctx spl_ctx;
+
+/* Creates a context bound to `device`.  The workspace grows on demand. */
+spl_status spl_create(int device, spl_ctx **out);
+void spl_destroy(spl_ctx *ctx);
+/* Message for the last failed call on this context (never NULL). */
+const char *spl_last_error(const spl_ctx *ctx);
+/* Device memory currently held by the context workspace, bytes. */
+int64_t spl_workspace_bytes(const spl_ctx *ctx);
+
+/* Ranging (Sect. 2.1 preprocessing): per-species min / max of the scalar
+ * field, or of log10 of it (values <= 0 skipped), over finite values.  lo, hi:
+ * host arrays of n_species doubles; a species without values gets
+ * +inf / -inf.  Synchronises. */
+spl_status spl_scalar_range(spl_ctx *ctx, const spl_particles *p, int32_t n_species,
+                            int32_t log10_scalar, double *lo, double *hi, void *stream);
+
+/* Transform, projection, clipping and colour (Sect. 2.1 rasterisation;
+ * Sect. 3.1 transform and colour loops).  Writes, per particle, the record
+ * rec[8p..8p+7] = {Xi, Xf, Yi, Yf, sigma, Ar, Ag, Ab}: screen position split in
+ * integer part and fraction (X = Xi + Xf), kernel width in px, and emission
+ * premultiplied by the kernel amplitude 1/(pi sigma^2).  Clipped particles get
+ * an all-zero record (sigma = 0).  rec2 (may be NULL) gets {a/(pi sigma^2),
+ * view depth} per particle.  Device arrays of 8n and 2n floats. */
+spl_status spl_project(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
+                       const spl_params *prm, float *rec, float *rec2, void *stream);
+
+/* Tile lists from records (Sect. 3.1; tile-list pseudocode figure): counts
+ * (n_tiles), offsets (n_tiles + 1, exclusive scan) and pairs (particle
+ * indices grouped by tile).  Within a tile, pairs are in ascending
+ * (view-depth bits, index) order when by_depth = 1 (needs rec2), otherwise in
+ * no specified order.  tile: any edge >= 1 px.  Device arrays; *n_pairs
+ * (host) gets the total.  SPL_ENOMEM if pairs_cap is too small (counts and
+ * offsets are still written).  Synchronises. */
+spl_status spl_bin(spl_ctx *ctx, int64_t n, const float *rec, const float *rec2,
+                   int32_t width, int32_t height, int32_t tile, double nu,
+                   int32_t bin_rule, int32_t by_depth, uint32_t *counts,
+                   uint32_t *offsets, uint32_t *pairs, int64_t pairs_cap,
+                   int64_t *n_pairs, void *stream);
+
+/* Renders records made by spl_project (same camera size): the tiled splat,
+ * large-particle path, depth sort and finalisation of spl_render, starting
+ * after the projection.  cam supplies width and height; prm supplies mode,
+ * nu, tile, bin_rule, large_cut and normalise.  out: device image.  st may be
+ * NULL (then the call does not synchronise at the end). */
+spl_status spl_render_records(spl_ctx *ctx, int64_t n, const float *rec,
+                              const float *rec2, const spl_camera *cam,
+                              const spl_params *prm, float *out, spl_stats *st,
+                              void *stream);
+
+/* Full frame: projection + colour, tile binning, splat (small and large
+ * particle paths, or depth-sorted compositing), finalisation.  out: device
+ * image.  st may be NULL. */
+spl_status spl_render(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
+                      const spl_params *prm, float *out, spl_stats *st, void *stream);
+
+/* Many views of one resident particle set (the paper's scene-file frame
+ * sequence, Sect. 2.1).  cams, prms, outs: host arrays of n_views entries
+ * (outs[v] device images).  Projection of all views runs in one launch and
+ * the splat of all views in one persistent launch over (view, tile-chunk)
+ * work items.  st: host array of n_views entries or NULL. */
+spl_status spl_render_batch(spl_ctx *ctx, const spl_particles *p, int32_t n_views,
+                            const spl_camera *cams, const spl_params *prms,
+                            float *const *outs, spl_stats *st, void *stream);
+
+/* Picks the tile size and large-particle cut that render this view fastest
+ * (timed on the device) and caches the choice for (n, width x height, mode).
+ * tile and large_cut: host outputs.  Synchronises. */
+spl_status spl_autotune(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
+                        const spl_params *prm, int32_t *tile, double *large_cut,
+                        void *stream);
+
+/* Stage timers.  When enabled, every frame records HIP events on its stream
+ * around its stages; spl_get_timing returns, per stage, the summed device time
+ * between the events and the summed algorithmic HBM bytes of the stage, over
+ * all frames since the previous call, then resets.  Stages:
+ *   0 projection + colour (or record spans), 1 tile counts, 2 scan,
+ *   3 host gap + work-item build, 4 list scatter, 5 depth sort,
+ *   6 image clear + large-particle splat, 7 tile splat / composite,
+ *   8 finalise + FP64 reductions.
+ * Algorithmic bytes count each array the stage must read or write once.
+ * ms, bytes: host arrays of SPL_N_STAGES doubles.  Synchronises. */
+#define SPL_N_STAGES 9
+spl_status spl_set_timing(spl_ctx *ctx, int32_t enable);
+spl_status spl_get_timing(spl_ctx *ctx, double *ms, double *bytes, int64_t *frames);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -41,7 +41,9 @@
  *   - ADD_AEQE: absorption equal to emission, I = 1 - exp(-J), exact solution
  *     of dI/ds = E rho (1 - I), independent of order.
  *   - SORTED:   separate absorption; particles composited in ascending view
- *     depth (ties by index), front to back: C += T E tau phi(x), T *= exp(-x).
+ *     depth, front to back: C += T E tau phi(x), T *= exp(-x).  The depth used
+ *     for ordering is rounded to single precision and ties go by particle
+ *     index (the paper fixes no order for particles at equal depth).
  *
  *  Tiles (Sect. 3.1; tile-list pseudocode figure): the image is cut in square
  *  tiles of T px; a particle is listed in every tile its pixel box touches.
@@ -331,9 +333,12 @@ static int render_impl(const sr_particles *p, const sr_camera *cam,
       free(pr);
       return SR_ENOMEM;
     }
+    /* Depth order: view depth rounded to single precision, ties by index.
+     * Two depths within one single-precision step (~1e-7 relative) have no
+     * physically meaningful order; this fixes one. */
     for (k = 0; k < p->n; ++k)
       if (pr[k].active) {
-        ord[na].key = pr[k].zv;
+        ord[na].key = (double)(float)pr[k].zv;
         ord[na].idx = k;
         ++na;
       }

@@ -1,0 +1,339 @@
+// Tile binning (Sect. 3.1: one particle-index list per tile; tile-list
+// pseudocode figure).  The paper grows per-thread dynamic vectors, whose
+// allocation it reports as at least half of the Xeon Phi run time
+// (Sect. 4.4); here the lists are built without any allocation by
+// count -> exclusive scan -> scatter into one preallocated array.
+//
+//  k_count    per-chunk tile histogram in LDS (global atomics only to flush
+//             non-zero bins), or direct global atomics when the bins do not
+//             fit in LDS.
+//  k_scan     single-workgroup exclusive scan of the bin counts, plus the
+//             work-item counts of up to three chunkings of the lists.
+//  k_items    expands the item counts into (bin, begin, end, chunk) items.
+//  k_scatter  per-chunk LDS histogram again, one global atomic per non-zero
+//             bin reserves a contiguous range, LDS atomics hand out slots.
+#include "spl_internal.h"
+
+namespace spl {
+
+namespace {
+
+constexpr int kLdsBins = 16384;  // 64 KB of u32 bins
+constexpr int kChunk = 16384;    // particles per workgroup pass
+
+struct SpanDec {
+  int tx0, tx1, ty0, ty1;
+  bool large;
+};
+
+__device__ __forceinline__ SpanDec decode(uint2 s) {
+  SpanDec d;
+  d.tx0 = (int)(s.x & 0xffffu);
+  d.tx1 = (int)(s.x >> 16);
+  d.ty0 = (int)(s.y & 0xffffu);
+  d.ty1 = (int)((s.y >> 16) & 0x7fffu);
+  d.large = (s.y & kLargeFlag) != 0;
+  return d;
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
+                                                  const float4 *__restrict__ rec, int64_t n,
+                                                  TileK tk, uint32_t *__restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  const bool paper = tk.bin_rule == 1;
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
+       base += (int64_t)gridDim.x * kChunk) {
+    if (kLds) {
+      for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
+      __syncthreads();
+    }
+    const int64_t end = min(base + (int64_t)kChunk, n);
+    for (int64_t k = base + threadIdx.x; k < end; k += kBlock) {
+      const uint2 s = span[k];
+      if (s.x == kInactive) continue;
+      const SpanDec d = decode(s);
+      const int ntx = d.large ? tk.nctx : tk.ntx;
+      const int off = d.large ? tk.n_tiles : 0;
+      const bool filt = paper && !d.large;
+      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      float sg = 0.f;
+      if (filt) {
+        r0 = rec[2 * k];
+        sg = rec[2 * k + 1].x;
+      }
+      for (int ty = d.ty0; ty <= d.ty1; ++ty)
+        for (int tx = d.tx0; tx <= d.tx1; ++tx) {
+          if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
+            continue;
+          const int b = off + ty * ntx + tx;
+          if (kLds)
+            atomicAdd(&hist[b], 1u);
+          else
+            atomicAdd(&counts[b], 1u);
+        }
+    }
+    if (kLds) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += kBlock) {
+        const uint32_t v = hist[i];
+        if (v) atomicAdd(&counts[i], v);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <bool kLds, bool kKeys>
+__global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ span,
+                                                    const float4 *__restrict__ rec,
+                                                    const float2 *__restrict__ rec2, int64_t n,
+                                                    TileK tk, uint32_t *__restrict__ cursor,
+                                                    uint32_t *__restrict__ pairs,
+                                                    unsigned long long *__restrict__ keys) {
+  extern __shared__ uint32_t hist[];
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  const bool paper = tk.bin_rule == 1;
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
+       base += (int64_t)gridDim.x * kChunk) {
+    const int64_t end = min(base + (int64_t)kChunk, n);
+    if (kLds) {
+      for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
+      __syncthreads();
+      for (int64_t k = base + threadIdx.x; k < end; k += kBlock) {
+        const uint2 s = span[k];
+        if (s.x == kInactive) continue;
+        const SpanDec d = decode(s);
+        const int ntx = d.large ? tk.nctx : tk.ntx;
+        const int off = d.large ? tk.n_tiles : 0;
+        const bool filt = paper && !d.large;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float sg = 0.f;
+        if (filt) {
+          r0 = rec[2 * k];
+          sg = rec[2 * k + 1].x;
+        }
+        for (int ty = d.ty0; ty <= d.ty1; ++ty)
+          for (int tx = d.tx0; tx <= d.tx1; ++tx) {
+            if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
+              continue;
+            atomicAdd(&hist[off + ty * ntx + tx], 1u);
+          }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += kBlock) {
+        const uint32_t v = hist[i];
+        if (v) hist[i] = atomicAdd(&cursor[i], v);
+      }
+      __syncthreads();
+    }
+    for (int64_t k = base + threadIdx.x; k < end; k += kBlock) {
+      const uint2 s = span[k];
+      if (s.x == kInactive) continue;
+      const SpanDec d = decode(s);
+      const int ntx = d.large ? tk.nctx : tk.ntx;
+      const int off = d.large ? tk.n_tiles : 0;
+      const bool filt = paper && !d.large;
+      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+      float sg = 0.f;
+      if (filt) {
+        r0 = rec[2 * k];
+        sg = rec[2 * k + 1].x;
+      }
+      unsigned long long key_hi = 0;
+      if (kKeys) key_hi = (unsigned long long)__float_as_uint(rec2[k].y) << 32;
+      for (int ty = d.ty0; ty <= d.ty1; ++ty)
+        for (int tx = d.tx0; tx <= d.tx1; ++tx) {
+          if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
+            continue;
+          const int b = off + ty * ntx + tx;
+          const uint32_t slot = kLds ? atomicAdd(&hist[b], 1u) : atomicAdd(&cursor[b], 1u);
+          if (kKeys)
+            keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
+          else
+            pairs[slot] = (uint32_t)k;
+        }
+    }
+    if (kLds) __syncthreads();
+  }
+}
+
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ uint32_t items_for(uint32_t c, int bin, int n_fine, int ch, int cch,
+                                              int minc) {
+  const int chunk = bin < n_fine ? ch : cch;
+  if (c == 0 || chunk <= 0 || (int64_t)c < (int64_t)minc) return 0;
+  return (c + (uint32_t)chunk - 1) / (uint32_t)chunk;
+}
+
+struct ScanArgs {
+  int chunk[3], cchunk[3], minc[3];
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restrict__ counts,
+                                                       int nb, int n_fine,
+                                                       uint32_t *__restrict__ offsets,
+                                                       uint32_t *__restrict__ cursor, ScanArgs a,
+                                                       uint32_t *__restrict__ item_off,
+                                                       Totals *__restrict__ tot) {
+  __shared__ unsigned long long s[4][kScanThreads];
+  __shared__ unsigned int s_max, s_nef, s_nec;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    s_max = 0;
+    s_nef = 0;
+    s_nec = 0;
+  }
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+  unsigned long long loc[4] = {0, 0, 0, 0};
+  unsigned int mx = 0, nef = 0, nec = 0;
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t c = counts[b];
+    loc[0] += c;
+    for (int k = 0; k < 3; ++k) loc[1 + k] += items_for(c, b, n_fine, a.chunk[k], a.cchunk[k], a.minc[k]);
+    if (b < n_fine && c > mx) mx = c;
+    if (c) {
+      if (b < n_fine)
+        ++nef;
+      else
+        ++nec;
+    }
+  }
+  for (int q = 0; q < 4; ++q) s[q][t] = loc[q];
+  __syncthreads();
+  if (mx) atomicMax(&s_max, mx);
+  if (nef) atomicAdd(&s_nef, nef);
+  if (nec) atomicAdd(&s_nec, nec);
+  // inclusive Hillis-Steele scan of the per-thread sums
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    unsigned long long v[4];
+    for (int q = 0; q < 4; ++q) v[q] = (t >= d) ? s[q][t - d] : 0ull;
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) s[q][t] += v[q];
+    __syncthreads();
+  }
+  unsigned long long run[4];
+  for (int q = 0; q < 4; ++q) run[q] = s[q][t] - loc[q];
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t c = counts[b];
+    if (b == n_fine && tot) {
+      tot->n_fine_pairs = run[0];
+      for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = run[1 + k];
+    }
+    offsets[b] = (uint32_t)run[0];
+    cursor[b] = (uint32_t)run[0];
+    run[0] += c;
+    for (int k = 0; k < 3; ++k) {
+      item_off[k * (nb + 1) + b] = (uint32_t)run[1 + k];
+      run[1 + k] += items_for(c, b, n_fine, a.chunk[k], a.cchunk[k], a.minc[k]);
+    }
+  }
+  if (t == kScanThreads - 1) {
+    offsets[nb] = (uint32_t)s[0][t];
+    for (int k = 0; k < 3; ++k) item_off[k * (nb + 1) + nb] = (uint32_t)s[1 + k][t];
+    if (tot) {
+      tot->n_pairs = s[0][t];
+      for (int k = 0; k < 3; ++k) tot->n_items[k] = s[1 + k][t];
+      if (n_fine == nb) {
+        tot->n_fine_pairs = s[0][t];
+        for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = s[1 + k][t];
+      }
+      tot->max_count = s_max;
+      tot->n_fine_nonempty = s_nef;
+      tot->n_coarse_nonempty = s_nec;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ counts,
+                                                  const uint32_t *__restrict__ offsets, int nb,
+                                                  int n_fine, int chunk, int cchunk, int minc,
+                                                  const uint32_t *__restrict__ item_off,
+                                                  Item *__restrict__ items) {
+  const int b = blockIdx.x * kBlock + threadIdx.x;
+  if (b >= nb) return;
+  const uint32_t c = counts[b];
+  const uint32_t k = items_for(c, b, n_fine, chunk, cchunk, minc);
+  if (k == 0) return;
+  const uint32_t ch = (uint32_t)(b < n_fine ? chunk : cchunk);
+  const uint32_t o = offsets[b], e = o + c, base = item_off[b];
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint32_t s0 = o + i * ch;
+    const uint32_t s1 = min(s0 + ch, e);
+    items[base + i] = make_uint4((uint32_t)b, s0, s1, i);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
+                        uint32_t *counts, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  int64_t g = (n + kChunk - 1) / kChunk;
+  if (g > 1024) g = 1024;
+  const float4 *r = reinterpret_cast<const float4 *>(rec);
+  if (nb <= kLdsBins)
+    hipLaunchKernelGGL(k_count<true>, dim3((int)g), dim3(kBlock), nb * sizeof(uint32_t), s,
+                       span, r, n, tk, counts);
+  else
+    hipLaunchKernelGGL(k_count<false>, dim3((int)g), dim3(kBlock), 0, s, span, r, n, tk, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t *offsets,
+                       uint32_t *cursor, const int chunk[3], const int cchunk[3],
+                       const int min_count[3], uint32_t *item_off, Totals *tot, hipStream_t s) {
+  ScanArgs a;
+  for (int k = 0; k < 3; ++k) {
+    a.chunk[k] = chunk[k];
+    a.cchunk[k] = cchunk[k];
+    a.minc[k] = min_count[k];
+  }
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, n_bins, n_fine, offsets,
+                     cursor, a, item_off, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, int n_bins,
+                              int n_fine, int chunk, int cchunk, int min_count,
+                              const uint32_t *item_off, Item *items, hipStream_t s) {
+  const int g = (n_bins + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_items, dim3(g), dim3(kBlock), 0, s, counts, offsets, n_bins, n_fine, chunk,
+                     cchunk, min_count, item_off, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,
+                          const TileK &tk, uint32_t *cursor, uint32_t *pairs,
+                          unsigned long long *keys, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  int64_t g = (n + kChunk - 1) / kChunk;
+  if (g > 1024) g = 1024;
+  const float4 *r = reinterpret_cast<const float4 *>(rec);
+  const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
+  const bool lds = nb <= kLdsBins;
+  const size_t sh = lds ? nb * sizeof(uint32_t) : 0;
+  if (keys) {
+    if (lds)
+      hipLaunchKernelGGL((k_scatter<true, true>), dim3((int)g), dim3(kBlock), sh, s, span, r, r2, n,
+                         tk, cursor, pairs, keys);
+    else
+      hipLaunchKernelGGL((k_scatter<false, true>), dim3((int)g), dim3(kBlock), 0, s, span, r, r2,
+                         n, tk, cursor, pairs, keys);
+  } else {
+    if (lds)
+      hipLaunchKernelGGL((k_scatter<true, false>), dim3((int)g), dim3(kBlock), sh, s, span, r, r2,
+                         n, tk, cursor, pairs, keys);
+    else
+      hipLaunchKernelGGL((k_scatter<false, false>), dim3((int)g), dim3(kBlock), 0, s, span, r, r2,
+                         n, tk, cursor, pairs, keys);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace spl

@@ -1,0 +1,254 @@
+// Rasterisation stage: camera transform, perspective projection, clipping and
+// colour, fused into one pass over the particle arrays (Sect. 2.1 and
+// Sect. 3.1 describe transform and colour as per-particle loops; Sect. 4.3
+// notes the GPU version fused them so inactive particles leave early).
+//
+// One thread per particle, grid-stride, coalesced structure-of-arrays loads.
+// Position arithmetic runs in FP64 so the single-precision record keeps the
+// screen position as integer part + fraction.  The colour map lookup runs in
+// FP32.  Output per active particle: a 32-byte record, optionally the 8-byte
+// sorted-mode record, and the 8-byte tile span read by the binning kernels.
+#include "spl_internal.h"
+
+namespace spl {
+
+namespace {
+
+__device__ __forceinline__ float load_attr(const void *p, int dtype, int64_t i) {
+  if (dtype == SPL_F32) return static_cast<const float *>(p)[i];
+  if (dtype == SPL_BF16) {
+    const uint32_t b = static_cast<const uint16_t *>(p)[i];
+    return __uint_as_float(b << 16);
+  }
+  return (float)static_cast<const _Float16 *>(p)[i];
+}
+
+__device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
+
+__global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *__restrict__ rec,
+                                                    float2 *__restrict__ rec2,
+                                                    uint2 *__restrict__ span, int write_inactive,
+                                                    Totals *__restrict__ tot) {
+  __shared__ unsigned int s_act, s_large;
+  if (threadIdx.x == 0) {
+    s_act = 0;
+    s_large = 0;
+  }
+  __syncthreads();
+  unsigned int my_act = 0, my_large = 0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.n; k += stride) {
+    const float x = P.x[k], y = P.y[k], z = P.z[k];
+    const float h = load_attr(P.h, P.dtype, k) * P.h_scale;
+    const float I = load_attr(P.inten, P.dtype, k);
+    const float s = load_attr(P.scal, P.dtype, k);
+    const int sp = P.species ? (int)P.species[k] : 0;
+    const float a = (P.mode == SPL_SORTED) ? P.absorb[k] : 0.0f;
+    float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 o2 = make_float2(0.f, 0.f);
+    uint2 spn = make_uint2(kInactive, kInactive);
+    bool active = false;
+    if (finitef(x) && finitef(y) && finitef(z) && finitef(h) && finitef(I) && finitef(s) &&
+        finitef(a) && h > 0.0f && a >= 0.0f && sp < P.n_species) {
+      const double vx = (double)x - P.e[0], vy = (double)y - P.e[1], vz = (double)z - P.e[2];
+      const double zv = vx * P.f[0] + vy * P.f[1] + vz * P.f[2];
+      if (zv > P.z_near) {
+        const double xv = vx * P.r[0] + vy * P.r[1] + vz * P.r[2];
+        const double yv = vx * P.u[0] + vy * P.u[1] + vz * P.u[2];
+        const double iz = 1.0 / zv;
+        const double X = P.cx + P.F * xv * iz;
+        const double Y = P.cy - P.F * yv * iz;
+        const double rho = P.F * (double)h * iz;
+        const double ks = P.k_sigma * rho;
+        const double sig = sqrt(ks * ks + P.sigma_min * P.sigma_min);
+        const double R = P.nu * sig;
+        if (fabs(X - P.cx) <= 4194304.0 && fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0) {
+          LookK L = P.looks[0];
+#pragma unroll
+          for (int j = 1; j < SPL_MAX_SPECIES; ++j)
+            if (sp == j) L = P.looks[j];
+          float t;
+          if (L.log10)
+            t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
+          else
+            t = (s - L.lo) * L.inv_range;
+          t = fminf(fmaxf(t, 0.0f), 1.0f);
+          float c0, c1, c2;
+          if (L.M == 1) {
+            c0 = L.rgb[0];
+            c1 = L.rgb[1];
+            c2 = L.rgb[2];
+          } else {
+            const float u = t * (float)(L.M - 1);
+            int j = (int)floorf(u);
+            j = min(max(j, 0), L.M - 2);
+            const float fr = u - (float)j;
+            const float *p0 = L.rgb + 3 * j;
+            c0 = (1.0f - fr) * p0[0] + fr * p0[3];
+            c1 = (1.0f - fr) * p0[1] + fr * p0[4];
+            c2 = (1.0f - fr) * p0[2] + fr * p0[5];
+          }
+          const float bi = L.beta * I;
+          const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
+          const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
+          if (emits || (P.mode == SPL_SORTED && a > 0.0f)) {
+            const double amp = 1.0 / (3.14159265358979323846 * sig * sig);
+            const double fX = floor(X), fY = floor(Y);
+            o0 = make_float4((float)fX, (float)(X - fX), (float)fY, (float)(Y - fY));
+            o1 = make_float4((float)sig, (float)((double)E0 * amp), (float)((double)E1 * amp),
+                             (float)((double)E2 * amp));
+            o2 = make_float2((float)((double)a * amp), (float)zv);
+            spn = record_span(o0, o1.x, tk);
+            active = spn.x != kInactive;
+          }
+        }
+      }
+    }
+    if (active) {
+      ++my_act;
+      if (spn.y & kLargeFlag) ++my_large;
+    }
+    if (active || write_inactive) {
+      if (!active) {
+        o0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        o1 = o0;
+        o2 = make_float2(0.f, 0.f);
+      }
+      rec[2 * k] = o0;
+      rec[2 * k + 1] = o1;
+      if (rec2) rec2[k] = o2;
+    }
+    span[k] = spn;
+  }
+  if (my_act) atomicAdd(&s_act, my_act);
+  if (my_large) atomicAdd(&s_large, my_large);
+  __syncthreads();
+  if (threadIdx.x == 0 && tot) {
+    if (s_act) atomicAdd(&tot->n_active, (unsigned long long)s_act);
+    if (s_large) atomicAdd(&tot->n_large, (unsigned long long)s_large);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_span_from_records(const float4 *__restrict__ rec,
+                                                              int64_t n, TileK tk,
+                                                              uint2 *__restrict__ span,
+                                                              Totals *__restrict__ tot) {
+  __shared__ unsigned int s_act;
+  if (threadIdx.x == 0) s_act = 0;
+  __syncthreads();
+  unsigned int my_act = 0;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) {
+    const float4 r0 = rec[2 * k];
+    const float4 r1 = rec[2 * k + 1];
+    const uint2 sp = record_span(r0, r1.x, tk);
+    span[k] = sp;
+    if (sp.x != kInactive) ++my_act;
+  }
+  if (my_act) atomicAdd(&s_act, my_act);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_act) atomicAdd(&tot->n_active, (unsigned long long)s_act);
+}
+
+// Order-preserving map of a double onto unsigned 64-bit keys, so that atomic
+// integer min / max give the floating-point min / max exactly.
+__device__ __forceinline__ unsigned long long order_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scalar_range(ProjK P, int n_species, int log10s,
+                                                         unsigned long long *__restrict__ mm) {
+  __shared__ unsigned long long s_mm[2 * SPL_MAX_SPECIES];
+  if (threadIdx.x < 2 * SPL_MAX_SPECIES)
+    s_mm[threadIdx.x] = (threadIdx.x & 1) ? 0ull : ~0ull;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.n; k += stride) {
+    const float s = load_attr(P.scal, P.dtype, k);
+    const int sp = P.species ? (int)P.species[k] : 0;
+    if (sp >= n_species || !finitef(s)) continue;
+    double g = (double)s;
+    if (log10s) {
+      if (!(s > 0.0f)) continue;
+      g = log10(g);
+    }
+    const unsigned long long key = order_key(g);
+    atomicMin(&s_mm[2 * sp], key);
+    atomicMax(&s_mm[2 * sp + 1], key);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * n_species) {
+    const unsigned long long v = s_mm[threadIdx.x];
+    if (threadIdx.x & 1) {
+      if (v != 0ull) atomicMax(&mm[threadIdx.x], v);
+    } else {
+      if (v != ~0ull) atomicMin(&mm[threadIdx.x], v);
+    }
+  }
+}
+
+__global__ void k_init_minmax(unsigned long long *mm, int n) {
+  const int i = threadIdx.x;
+  if (i < 2 * n) mm[i] = (i & 1) ? 0ull : ~0ull;
+}
+
+__global__ void k_decode_minmax(const unsigned long long *mm, int n, double *out) {
+  const int i = threadIdx.x;
+  if (i < 2 * n) {
+    const unsigned long long k = mm[i];
+    double v;
+    if ((i & 1) ? (k == 0ull) : (k == ~0ull)) {
+      v = (i & 1) ? -__builtin_inf() : __builtin_inf();
+    } else {
+      const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+      v = __longlong_as_double((long long)b);
+    }
+    out[i] = v;
+  }
+}
+
+int grid_for(int64_t n, int per_block_items, int max_blocks) {
+  int64_t g = (n + per_block_items - 1) / per_block_items;
+  if (g < 1) g = 1;
+  if (g > max_blocks) g = max_blocks;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *rec2, uint2 *span,
+                          int write_inactive, Totals *tot, hipStream_t s) {
+  if (pk.n == 0) return hipSuccess;
+  const int g = grid_for(pk.n, kBlock, 8192);
+  hipLaunchKernelGGL(k_project, dim3(g), dim3(kBlock), 0, s, pk, tk,
+                     reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
+                     write_inactive, tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_span_from_records(const float *rec, int64_t n, const TileK &tk, uint2 *span,
+                                    Totals *tot, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int g = grid_for(n, kBlock, 8192);
+  hipLaunchKernelGGL(k_span_from_records, dim3(g), dim3(kBlock), 0, s,
+                     reinterpret_cast<const float4 *>(rec), n, tk, span, tot);
+  return hipGetLastError();
+}
+
+// out_minmax: device buffer of 2 * SPL_MAX_SPECIES u64 keys followed by
+// 2 * SPL_MAX_SPECIES doubles (min, max interleaved per species).
+hipError_t launch_scalar_range(const ProjK &pk, int n_species, int log10, double *out_minmax,
+                               hipStream_t s) {
+  unsigned long long *mm = reinterpret_cast<unsigned long long *>(out_minmax);
+  double *out = out_minmax + 2 * SPL_MAX_SPECIES;
+  hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(64), 0, s, mm, n_species);
+  if (pk.n > 0) {
+    const int g = grid_for(pk.n, kBlock * 16, 4096);
+    hipLaunchKernelGGL(k_scalar_range, dim3(g), dim3(kBlock), 0, s, pk, n_species, log10, mm);
+  }
+  hipLaunchKernelGGL(k_decode_minmax, dim3(1), dim3(64), 0, s, mm, n_species, out);
+  return hipGetLastError();
+}
+
+}  // namespace spl

@@ -1,0 +1,137 @@
+// Depth ordering of the tile lists for the non-additive transfer mode
+// (Sect. 2.1: the transfer equation makes compositing order-dependent).
+// Keys are 64-bit: the IEEE bits of the (positive) view depth in the high
+// word and the particle index in the low word, so ascending keys are
+// ascending (depth, index) and every key is unique.
+//
+//  k_sort_chunks  one workgroup per list chunk of <= 4096 keys: bitonic sort
+//                 in LDS (32 KB).  A list that fits one chunk is done.
+//  k_merge_pass   longer lists: sorted runs of length L merged pairwise into
+//                 runs of 2L; one workgroup per 2048 outputs, each lane finds
+//                 its start on the merge path by binary search and merges 8
+//                 keys.
+#include "spl_internal.h"
+
+namespace spl {
+
+namespace {
+
+constexpr int kSortChunk = 4096;
+constexpr int kMergeOut = 2048;  // outputs per workgroup = 256 lanes x 8
+
+__global__ __launch_bounds__(kBlock) void k_sort_chunks(unsigned long long *__restrict__ keys,
+                                                        const Item *__restrict__ items) {
+  __shared__ unsigned long long s[kSortChunk];
+  const Item it = items[blockIdx.x];
+  const int n = (int)(it.z - it.y);
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int i = threadIdx.x; i < np; i += kBlock) s[i] = (i < n) ? keys[it.y + i] : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= np; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < np; i += kBlock) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const unsigned long long a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += kBlock) keys[it.y + i] = s[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long *__restrict__ src,
+                                                       unsigned long long *__restrict__ dst,
+                                                       const Item *__restrict__ items,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       const uint32_t *__restrict__ counts,
+                                                       int64_t L) {
+  const Item it = items[blockIdx.x];
+  const int64_t s0 = offsets[it.x];
+  const int64_t n = counts[it.x];
+  const int64_t d = ((int64_t)it.y - s0) + 8 * (int64_t)threadIdx.x;
+  if (d >= (int64_t)it.z - s0) return;
+  const int64_t ps = (d / (2 * L)) * (2 * L);
+  const int64_t la = min(L, n - ps);
+  const int64_t lb = max((int64_t)0, min(L, n - ps - L));
+  const int64_t diag = d - ps;
+  const unsigned long long *A = src + s0 + ps;
+  const unsigned long long *B = A + L;
+  int64_t lo = max((int64_t)0, diag - lb), hi = min(diag, la);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (A[mid] < B[diag - 1 - mid])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int64_t i = lo, j = diag - lo;
+  unsigned long long *out = dst + s0 + ps;
+  for (int o = 0; o < 8; ++o) {
+    const int64_t q = diag + o;
+    if (q >= la + lb) break;
+    unsigned long long v;
+    if (j >= lb || (i < la && A[i] < B[j]))
+      v = A[i++];
+    else
+      v = B[j++];
+    out[q] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_items(const unsigned long long *__restrict__ src,
+                                                       unsigned long long *__restrict__ dst,
+                                                       const Item *__restrict__ items) {
+  const Item it = items[blockIdx.x];
+  for (uint32_t k = it.y + threadIdx.x; k < it.z; k += kBlock) dst[k] = src[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys_to_pids(const unsigned long long *__restrict__ keys,
+                                                         int64_t n, uint32_t *__restrict__ pids) {
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    pids[i] = (uint32_t)(keys[i] & 0xffffffffull);
+}
+
+}  // namespace
+
+hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32_t *pids,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_keys_to_pids, dim3((int)g), dim3(kBlock), 0, s, keys, n, pids);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_chunks(unsigned long long *keys, const Item *items, int n_items,
+                              hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_chunks, dim3(n_items), dim3(kBlock), 0, s, keys, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_pass(const unsigned long long *src, unsigned long long *dst,
+                             const Item *items, int n_items, const uint32_t *offsets,
+                             const uint32_t *counts, int run, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_pass, dim3(n_items), dim3(kBlock), 0, s, src, dst, items, offsets,
+                     counts, (int64_t)run);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *dst,
+                             const Item *items, int n_items, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_items, dim3(n_items), dim3(kBlock), 0, s, src, dst, items);
+  return hipGetLastError();
+}
+
+}  // namespace spl

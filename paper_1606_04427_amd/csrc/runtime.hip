@@ -1,0 +1,825 @@
+// C ABI of the gfx950 Splotch library: argument checks, the context
+// workspace, and the order of kernel launches for one frame.
+//
+// Frame (Sect. 2.1 rasterisation + rendering; Sect. 3.1 tiles):
+//   project+colour -> count -> scan  [one stream sync: list sizes]
+//   -> build work items -> scatter -> (sort) -> splat / composite
+//   -> finalise (+ FP64 flux / max) [-> normalise]
+// The single host synchronisation per frame reads the list sizes so that
+// every list and item buffer is sized exactly; no kernel can overflow a
+// buffer.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "spl_internal.h"
+
+using namespace spl;
+
+namespace {
+
+constexpr int kChunkSplat = 2048;  // list entries per splat item, fine tiles
+constexpr int kChunkLarge = 512;   // list entries per large-particle item
+constexpr int kSortChunk = 4096;   // keys per in-LDS sort
+constexpr int kMergeOut = 2048;    // outputs per merge workgroup
+constexpr int kLargeTile = 64;     // px, tiles of the large-particle path
+constexpr int kDefaultTile = 16;
+constexpr double kDefaultCut = 32.0;  // px
+constexpr int kFinBlocks = 1024;
+constexpr int kScatMax16 = 24;
+constexpr int kScatMax32 = 48;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+// Events of one timed frame: ev[k] .. ev[k+1] brackets stage k.
+struct TimedFrame {
+  hipEvent_t ev[SPL_N_STAGES + 1];
+  double bytes[SPL_N_STAGES];
+};
+
+}  // namespace
+
+struct spl_ctx {
+  int device = 0;
+  std::string err;
+  DevBuf rec, rec2, span, counts, offsets, cursor, item_off, items[3], pairs, keysA, keysB,
+      partial, fin, stats, totals, minmax;
+  Totals *h_tot = nullptr;
+  double *h_stats = nullptr;
+  int64_t bytes = 0;
+  std::map<std::tuple<int64_t, int, int, int>, std::pair<int, double>> tune;
+  // stage timers
+  bool timing = false;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<TimedFrame> pending;
+  double acc_ms[SPL_N_STAGES] = {0};
+  double acc_bytes[SPL_N_STAGES] = {0};
+  int64_t acc_frames = 0;
+};
+
+namespace {
+
+spl_status fail(spl_ctx *c, spl_status code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+spl_status fail(spl_ctx *c, spl_status code, const char *fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIPTRY(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((ctx), SPL_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+spl_status ensure(spl_ctx *c, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.cap >= bytes) return SPL_OK;
+  size_t want = b.cap + b.cap / 2;
+  if (want < bytes) want = bytes;
+  want = (want + 255) & ~(size_t)255;
+  if (b.p) {
+    hipFree(b.p);
+    c->bytes -= (int64_t)b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      b.p = nullptr;
+      (void)hipGetLastError();
+      return fail(c, SPL_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    want = bytes;
+  }
+  b.cap = want;
+  c->bytes += (int64_t)want;
+  return SPL_OK;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    spl_status r_ = (expr);        \
+    if (r_ != SPL_OK) return r_;   \
+  } while (0)
+
+bool finite3(const double *v) {
+  return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+// Camera frame: forward f = (lookat - eye)/|..|, right r = f x up/|..|,
+// up' = r x f, focal length F = (H/2)/tan(fov/2).
+spl_status camera_frame(spl_ctx *c, const spl_camera *cam, ProjK &pk) {
+  if (!cam) return fail(c, SPL_EINVAL, "camera is NULL");
+  if (cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
+    return fail(c, SPL_EINVAL, "image size %dx%d outside 1..32768", cam->width, cam->height);
+  if (!(cam->fov_y_deg > 0.0 && cam->fov_y_deg < 180.0))
+    return fail(c, SPL_EINVAL, "fov_y_deg %g outside (0, 180)", cam->fov_y_deg);
+  if (!(cam->z_near >= 0.0) || !std::isfinite(cam->z_near))
+    return fail(c, SPL_EINVAL, "z_near must be finite and >= 0");
+  if (!finite3(cam->eye) || !finite3(cam->lookat) || !finite3(cam->up))
+    return fail(c, SPL_EINVAL, "camera vectors must be finite");
+  double f[3], r[3], u[3];
+  for (int k = 0; k < 3; ++k) f[k] = cam->lookat[k] - cam->eye[k];
+  double nf = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(nf > 0.0)) return fail(c, SPL_EINVAL, "eye and lookat coincide");
+  for (double &v : f) v /= nf;
+  r[0] = f[1] * cam->up[2] - f[2] * cam->up[1];
+  r[1] = f[2] * cam->up[0] - f[0] * cam->up[2];
+  r[2] = f[0] * cam->up[1] - f[1] * cam->up[0];
+  double nr = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(nr > 1e-12)) return fail(c, SPL_EINVAL, "up vector parallel to the view direction");
+  for (double &v : r) v /= nr;
+  u[0] = r[1] * f[2] - r[2] * f[1];
+  u[1] = r[2] * f[0] - r[0] * f[2];
+  u[2] = r[0] * f[1] - r[1] * f[0];
+  for (int k = 0; k < 3; ++k) {
+    pk.e[k] = cam->eye[k];
+    pk.r[k] = r[k];
+    pk.u[k] = u[k];
+    pk.f[k] = f[k];
+  }
+  pk.F = 0.5 * cam->height / std::tan(0.5 * cam->fov_y_deg * M_PI / 180.0);
+  pk.cx = 0.5 * cam->width;
+  pk.cy = 0.5 * cam->height;
+  pk.z_near = cam->z_near;
+  return SPL_OK;
+}
+
+spl_status check_params(spl_ctx *c, const spl_params *p, bool need_looks) {
+  if (!p) return fail(c, SPL_EINVAL, "params is NULL");
+  if (p->mode < SPL_ADD_RAW || p->mode > SPL_SORTED)
+    return fail(c, SPL_EINVAL, "unknown mode %d", p->mode);
+  if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(c, SPL_EINVAL, "nu must be > 0");
+  if (p->tile != 0 && p->tile != 16 && p->tile != 32)
+    return fail(c, SPL_EINVAL, "tile must be 0, 16 or 32 (got %d)", p->tile);
+  if (p->bin_rule != 0 && p->bin_rule != 1) return fail(c, SPL_EINVAL, "bin_rule must be 0 or 1");
+  if (!std::isfinite(p->large_cut)) return fail(c, SPL_EINVAL, "large_cut must be finite");
+  if (!need_looks) return SPL_OK;
+  if (!(p->k_sigma >= 0.0) || !std::isfinite(p->k_sigma))
+    return fail(c, SPL_EINVAL, "k_sigma must be finite and >= 0");
+  if (!(p->sigma_min > 0.0) || !std::isfinite(p->sigma_min))
+    return fail(c, SPL_EINVAL, "sigma_min must be > 0");
+  if (p->n_species < 1 || p->n_species > SPL_MAX_SPECIES)
+    return fail(c, SPL_EINVAL, "n_species %d outside 1..%d", p->n_species, SPL_MAX_SPECIES);
+  for (int k = 0; k < p->n_species; ++k) {
+    const spl_look &l = p->looks[k];
+    if (!l.rgb) return fail(c, SPL_EINVAL, "palette of species %d is NULL", k);
+    if (l.n_entries < 1 || l.n_entries > 4096)
+      return fail(c, SPL_EINVAL, "palette of species %d has %d entries", k, l.n_entries);
+    if (!std::isfinite(l.lo) || !std::isfinite(l.hi) || !(l.hi >= l.lo))
+      return fail(c, SPL_EINVAL, "species %d: need finite lo <= hi", k);
+    if (!std::isfinite(l.brightness)) return fail(c, SPL_EINVAL, "species %d: brightness", k);
+  }
+  return SPL_OK;
+}
+
+spl_status check_particles(spl_ctx *c, const spl_particles *p, int mode) {
+  if (!p) return fail(c, SPL_EINVAL, "particles is NULL");
+  if (p->n < 0 || p->n >= (int64_t)0xffffffffll)
+    return fail(c, SPL_EINVAL, "particle count %lld outside 0..2^32-2", (long long)p->n);
+  if (p->n == 0) return SPL_OK;
+  if (!p->x || !p->y || !p->z || !p->h || !p->intensity || !p->scalar)
+    return fail(c, SPL_EINVAL, "a required particle array is NULL");
+  if (p->attr_dtype < SPL_F32 || p->attr_dtype > SPL_F16)
+    return fail(c, SPL_EINVAL, "unknown attr_dtype %d", p->attr_dtype);
+  if (!(p->h_scale > 0.0f) || !std::isfinite(p->h_scale))
+    return fail(c, SPL_EINVAL, "h_scale must be finite and > 0");
+  if (mode == SPL_SORTED && !p->absorption)
+    return fail(c, SPL_EINVAL, "sorted mode needs absorption");
+  return SPL_OK;
+}
+
+void fill_proj(ProjK &pk, const spl_particles *p, const spl_params *prm) {
+  pk.k_sigma = prm->k_sigma;
+  pk.sigma_min = prm->sigma_min;
+  pk.nu = prm->nu;
+  pk.mode = prm->mode;
+  pk.n_species = prm->n_species;
+  for (int k = 0; k < SPL_MAX_SPECIES; ++k) {
+    LookK &L = pk.looks[k];
+    if (k < prm->n_species) {
+      const spl_look &l = prm->looks[k];
+      L.rgb = l.rgb;
+      L.M = l.n_entries;
+      L.log10 = l.log10_scalar ? 1 : 0;
+      L.beta = (float)l.brightness;
+      L.lo = (float)l.lo;
+      L.inv_range = (l.hi > l.lo) ? (float)(1.0 / (l.hi - l.lo)) : 0.0f;
+    } else {
+      L = pk.looks[0];
+    }
+  }
+  pk.x = p->x;
+  pk.y = p->y;
+  pk.z = p->z;
+  pk.h = p->h;
+  pk.inten = p->intensity;
+  pk.scal = p->scalar;
+  pk.dtype = p->attr_dtype;
+  pk.h_scale = p->h_scale;
+  pk.species = p->species;
+  pk.absorb = p->absorption;
+  pk.n = p->n;
+}
+
+void fill_tiles(TileK &tk, int W, int H, int tile, double nu, double cut, int bin_rule) {
+  tk.W = W;
+  tk.H = H;
+  tk.tile = tile;
+  tk.ntx = (W + tile - 1) / tile;
+  tk.nty = (H + tile - 1) / tile;
+  tk.n_tiles = tk.ntx * tk.nty;
+  tk.ctile = kLargeTile;
+  const bool large = std::isfinite(cut);
+  tk.nctx = large ? (W + kLargeTile - 1) / kLargeTile : 0;
+  tk.ncty = large ? (H + kLargeTile - 1) / kLargeTile : 0;
+  tk.n_ctiles = tk.nctx * tk.ncty;
+  tk.nu = (float)nu;
+  tk.large_cut = large ? (float)cut : __builtin_inff();
+  tk.bin_rule = bin_rule;
+}
+
+// Tile size and large cut for a view: explicit parameters win, then the
+// autotuner's cached choice, then the defaults.
+void choose(spl_ctx *c, int64_t n, int W, int H, const spl_params *prm, int &tile, double &cut) {
+  tile = prm->tile;
+  cut = prm->large_cut;
+  auto it = c->tune.find(std::make_tuple(n, W, H, prm->mode));
+  if (tile == 0) tile = (it != c->tune.end()) ? it->second.first : kDefaultTile;
+  if (prm->mode == SPL_SORTED || cut < 0.0)
+    cut = INFINITY;
+  else if (cut == 0.0)
+    cut = (it != c->tune.end()) ? it->second.second : kDefaultCut;
+}
+
+struct Frame {
+  int64_t n;
+  const float *rec, *rec2;  // rec2 only in sorted mode
+  TileK tk;
+  int mode, normalise;
+  float *out;
+  double in_bytes_per_particle;  // bytes the first stage reads per particle
+  double out_bytes_per_active;   // bytes it writes per active particle
+  TimedFrame *tf;                // NULL unless timing
+};
+
+// ---- stage timers ---------------------------------------------------------
+
+hipEvent_t take_event(spl_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+bool begin_timed(spl_ctx *c, TimedFrame &tf) {
+  for (int k = 0; k <= SPL_N_STAGES; ++k) {
+    tf.ev[k] = take_event(c);
+    if (!tf.ev[k]) return false;
+  }
+  for (double &b : tf.bytes) b = 0.0;
+  return true;
+}
+
+void mark(TimedFrame *tf, int k, hipStream_t s) {
+  if (tf) hipEventRecord(tf->ev[k], s);
+}
+
+// Accumulates every pending frame whose last event has completed (all of
+// them when wait is true) and returns their events to the pool.
+void resolve_timing(spl_ctx *c, bool wait) {
+  std::vector<TimedFrame> keep;
+  for (TimedFrame &tf : c->pending) {
+    hipError_t q = wait ? hipEventSynchronize(tf.ev[SPL_N_STAGES]) : hipEventQuery(tf.ev[SPL_N_STAGES]);
+    if (q != hipSuccess) {
+      (void)hipGetLastError();
+      keep.push_back(tf);
+      continue;
+    }
+    for (int k = 0; k < SPL_N_STAGES; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, tf.ev[k], tf.ev[k + 1]) == hipSuccess) c->acc_ms[k] += ms;
+      (void)hipGetLastError();
+      c->acc_bytes[k] += tf.bytes[k];
+    }
+    c->acc_frames += 1;
+    for (hipEvent_t e : tf.ev) c->event_pool.push_back(e);
+  }
+  c->pending.swap(keep);
+}
+
+// Everything after the per-particle spans exist (ws span, totals n_active /
+// n_large already accumulated, counts zeroed).
+spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s) {
+  const TileK &tk = f.tk;
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  const bool sorted = f.mode == SPL_SORTED;
+  const int64_t npx = (int64_t)tk.W * tk.H;
+  uint32_t *counts = (uint32_t *)c->counts.p, *offsets = (uint32_t *)c->offsets.p,
+           *cursor = (uint32_t *)c->cursor.p, *item_off = (uint32_t *)c->item_off.p;
+  Totals *tot = (Totals *)c->totals.p;
+  const uint2 *span = (const uint2 *)c->span.p;
+  TimedFrame *tf = f.tf;
+
+  HIPTRY(c, launch_count(span, f.rec, f.n, tk, counts, s));
+  mark(tf, 2, s);
+  const int chunk[3] = {kChunkSplat, sorted ? kSortChunk : 0, sorted ? kMergeOut : 0};
+  const int cchunk[3] = {kChunkLarge, 0, 0};
+  const int minc[3] = {1, 1, kSortChunk + 1};
+  HIPTRY(c, launch_scan(counts, nb, tk.n_tiles, offsets, cursor, chunk, cchunk, minc, item_off, tot, s));
+  mark(tf, 3, s);
+  HIPTRY(c, hipMemcpyAsync(c->h_tot, tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  if (c->timing) resolve_timing(c, false);
+  const Totals T = *c->h_tot;
+  if (T.n_pairs >= 0xffffffffull)
+    return fail(c, SPL_EUNSUPPORTED, "%llu tile-list entries exceed 2^32", T.n_pairs);
+  for (int k = 0; k < 3; ++k)
+    if (T.n_items[k] > 0x7fffffffull)
+      return fail(c, SPL_EUNSUPPORTED, "too many work items (%llu)", T.n_items[k]);
+
+  if (sorted) {
+    TRY(ensure(c, c->keysA, T.n_pairs * 8));
+    TRY(ensure(c, c->keysB, T.n_pairs * 8));
+  } else {
+    TRY(ensure(c, c->pairs, T.n_pairs * 4));
+  }
+  for (int k = 0; k < 3; ++k) {
+    if (chunk[k] == 0) continue;
+    TRY(ensure(c, c->items[k], T.n_items[k] * sizeof(Item)));
+    if (T.n_items[k])
+      HIPTRY(c, launch_build_items(counts, offsets, nb, tk.n_tiles, chunk[k], cchunk[k], minc[k],
+                                   item_off + k * (nb + 1), (Item *)c->items[k].p, s));
+  }
+  unsigned long long *keysA = (unsigned long long *)c->keysA.p;
+  unsigned long long *keysB = (unsigned long long *)c->keysB.p;
+  mark(tf, 4, s);
+  HIPTRY(c, launch_scatter(span, f.rec, f.rec2, f.n, tk, cursor, (uint32_t *)c->pairs.p,
+                           sorted ? keysA : nullptr, s));
+  mark(tf, 5, s);
+  const Item *items0 = (const Item *)c->items[0].p;
+  int passes = 0;
+  if (!sorted) {
+    mark(tf, 6, s);
+    HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
+    const int nfi = (int)T.n_fine_items[0];
+    const int nci = (int)(T.n_items[0] - T.n_fine_items[0]);
+    HIPTRY(c, launch_splat_large(items0 + nfi, nci, (const uint32_t *)c->pairs.p, f.rec, counts,
+                                 kChunkLarge, tk, f.out, s));
+    mark(tf, 7, s);
+    HIPTRY(c, launch_splat_add(tk.tile, items0, nfi, (const uint32_t *)c->pairs.p, f.rec, counts,
+                               kChunkSplat, tk, tk.tile == 16 ? kScatMax16 : kScatMax32, f.out, s));
+    mark(tf, 8, s);
+  } else {
+    HIPTRY(c, launch_sort_chunks(keysA, (const Item *)c->items[1].p, (int)T.n_items[1], s));
+    for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {
+      HIPTRY(c, launch_merge_pass(passes % 2 ? keysB : keysA, passes % 2 ? keysA : keysB,
+                                  (const Item *)c->items[2].p, (int)T.n_items[2], offsets, counts,
+                                  (int)L, s));
+      ++passes;
+    }
+    if (passes % 2)
+      HIPTRY(c, launch_copy_items(keysB, keysA, (const Item *)c->items[2].p, (int)T.n_items[2], s));
+    mark(tf, 6, s);
+    HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
+    mark(tf, 7, s);
+    const int ni = (int)T.n_items[0];
+    TRY(ensure(c, c->partial, (size_t)ni * tk.tile * tk.tile * 16));
+    HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, f.rec, f.rec2, counts, kChunkSplat, tk,
+                               f.out, (float *)c->partial.p, s));
+    HIPTRY(c, launch_composite_merge(tk.tile, items0, ni, counts, kChunkSplat, tk,
+                                     (const float *)c->partial.p, f.out, s));
+    mark(tf, 8, s);
+  }
+  const int fb = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
+  HIPTRY(c, launch_finalise(f.out, npx, f.mode == SPL_ADD_AEQE, (double *)c->fin.p, fb, s));
+  HIPTRY(c, launch_reduce_stats((const double *)c->fin.p, fb, (double *)c->stats.p, s));
+  if (f.normalise) HIPTRY(c, launch_normalise(f.out, npx, (const double *)c->stats.p, s));
+  mark(tf, 9, s);
+  if (tf) {
+    // algorithmic bytes: every array a stage must touch, once
+    const double n = (double)f.n, act = (double)T.n_active, pairs = (double)T.n_pairs;
+    const double fine = (double)T.n_fine_pairs, large = pairs - fine;
+    const double t2 = (double)tk.tile * tk.tile;
+    double *B = tf->bytes;
+    B[0] = n * f.in_bytes_per_particle + act * f.out_bytes_per_active + n * 8.0;
+    B[1] = n * 8.0 + 4.0 * nb;
+    B[2] = 4.0 * nb * 3.0;
+    B[3] = 16.0 * (double)(T.n_items[0] + T.n_items[1] + T.n_items[2]);
+    B[4] = n * 8.0 + pairs * (sorted ? 8.0 : 4.0);
+    B[5] = sorted ? pairs * 16.0 * (1.0 + passes) : 0.0;
+    if (!sorted) {
+      B[6] = 12.0 * npx + large * 36.0 +
+             24.0 * std::min((double)npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);
+      B[7] = fine * 36.0 + 24.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
+    } else {
+      B[6] = 12.0 * npx;
+      B[7] = pairs * 48.0 + 12.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
+    }
+    B[8] = (f.mode == SPL_ADD_AEQE ? 24.0 : 12.0) * npx + (f.normalise ? 24.0 * npx : 0.0);
+    c->pending.push_back(*tf);
+  }
+  if (st) {
+    HIPTRY(c, hipMemcpyAsync(c->h_stats, c->stats.p, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    st->n_active = (int64_t)T.n_active;
+    st->n_large = (int64_t)T.n_large;
+    st->n_pairs = (int64_t)T.n_fine_pairs;
+    st->n_large_pairs = (int64_t)(T.n_pairs - T.n_fine_pairs);
+    st->n_items = (int64_t)T.n_items[0];
+    for (int q = 0; q < 3; ++q) {
+      st->flux[q] = c->h_stats[q];
+      st->max[q] = c->h_stats[3 + q];
+    }
+    st->tile = tk.tile;
+    st->large_cut = std::isfinite(tk.large_cut) ? (double)tk.large_cut : -1.0;
+  }
+  return SPL_OK;
+}
+
+// Runs render_lists with a timed frame when timing is on; on failure the
+// frame's events go back to the pool.
+spl_status render_timed(spl_ctx *c, Frame &f, TimedFrame *tf, spl_stats *st, hipStream_t s) {
+  f.tf = tf;
+  spl_status rc = render_lists(c, f, st, s);
+  if (rc != SPL_OK && tf)
+    for (hipEvent_t e : tf->ev) c->event_pool.push_back(e);
+  return rc;
+}
+
+spl_status prepare_common(spl_ctx *c, int64_t n, const TileK &tk, hipStream_t s) {
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  TRY(ensure(c, c->span, (size_t)n * 8));
+  TRY(ensure(c, c->counts, (size_t)nb * 4));
+  TRY(ensure(c, c->offsets, (size_t)(nb + 1) * 4));
+  TRY(ensure(c, c->cursor, (size_t)nb * 4));
+  TRY(ensure(c, c->item_off, (size_t)3 * (nb + 1) * 4));
+  TRY(ensure(c, c->totals, sizeof(Totals)));
+  TRY(ensure(c, c->fin, (size_t)kFinBlocks * 6 * 8));
+  TRY(ensure(c, c->stats, 8 * 8));
+  HIPTRY(c, launch_fill_u32((uint32_t *)c->counts.p, 0u, nb, s));
+  HIPTRY(c, launch_fill_u32((uint32_t *)c->totals.p, 0u, sizeof(Totals) / 4, s));
+  return SPL_OK;
+}
+
+spl_status render_one(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
+                      const spl_params *prm, float *out, spl_stats *st, hipStream_t s) {
+  ProjK pk;
+  TRY(check_params(c, prm, true));
+  TRY(check_particles(c, p, prm->mode));
+  TRY(camera_frame(c, cam, pk));
+  if (!out) return fail(c, SPL_EINVAL, "output image is NULL");
+  fill_proj(pk, p, prm);
+  int tile;
+  double cut;
+  choose(c, p->n, cam->width, cam->height, prm, tile, cut);
+  TileK tk;
+  fill_tiles(tk, cam->width, cam->height, tile, prm->nu, cut, prm->bin_rule);
+  const bool sorted = prm->mode == SPL_SORTED;
+  TRY(ensure(c, c->rec, (size_t)p->n * 32));
+  if (sorted) TRY(ensure(c, c->rec2, (size_t)p->n * 8));
+  TRY(prepare_common(c, p->n, tk, s));
+  TimedFrame tfr;
+  TimedFrame *tf = (c->timing && begin_timed(c, tfr)) ? &tfr : nullptr;
+  mark(tf, 0, s);
+  HIPTRY(c, launch_project(pk, tk, (float *)c->rec.p, sorted ? (float *)c->rec2.p : nullptr,
+                           (uint2 *)c->span.p, 0, (Totals *)c->totals.p, s));
+  mark(tf, 1, s);
+  const double attr = p->attr_dtype == SPL_F32 ? 4.0 : 2.0;
+  Frame f{p->n, (const float *)c->rec.p, sorted ? (const float *)c->rec2.p : nullptr, tk,
+          prm->mode, prm->normalise, out,
+          12.0 + 3.0 * attr + (p->species ? 1.0 : 0.0) + (sorted ? 4.0 : 0.0),
+          32.0 + (sorted ? 8.0 : 0.0), nullptr};
+  return render_timed(c, f, tf, st, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+spl_status spl_create(int device, spl_ctx **out) {
+  if (!out) return SPL_EINVAL;
+  *out = nullptr;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess || nd <= 0) {
+    (void)hipGetLastError();
+    return SPL_EDEVICE;
+  }
+  if (device < 0 || device >= nd) return SPL_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return SPL_EDEVICE;
+  spl_ctx *c = new (std::nothrow) spl_ctx();
+  if (!c) return SPL_ENOMEM;
+  c->device = device;
+  if (hipHostMalloc((void **)&c->h_tot, sizeof(Totals), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (c->h_tot) hipHostFree(c->h_tot);
+    delete c;
+    return SPL_ENOMEM;
+  }
+  *out = c;
+  return SPL_OK;
+}
+
+void spl_destroy(spl_ctx *c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  DevBuf *bufs[] = {&c->rec, &c->rec2, &c->span, &c->counts, &c->offsets, &c->cursor,
+                    &c->item_off, &c->items[0], &c->items[1], &c->items[2], &c->pairs,
+                    &c->keysA, &c->keysB, &c->partial, &c->fin, &c->stats, &c->totals,
+                    &c->minmax};
+  for (DevBuf *b : bufs)
+    if (b->p) hipFree(b->p);
+  for (TimedFrame &tf : c->pending)
+    for (hipEvent_t e : tf.ev) hipEventDestroy(e);
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+  if (c->h_tot) hipHostFree(c->h_tot);
+  if (c->h_stats) hipHostFree(c->h_stats);
+  delete c;
+}
+
+const char *spl_last_error(const spl_ctx *c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+int64_t spl_workspace_bytes(const spl_ctx *c) { return c ? c->bytes : 0; }
+
+spl_status spl_scalar_range(spl_ctx *c, const spl_particles *p, int32_t n_species,
+                            int32_t log10_scalar, double *lo, double *hi, void *stream) {
+  if (!c) return SPL_EINVAL;
+  if (!lo || !hi) return fail(c, SPL_EINVAL, "lo / hi is NULL");
+  if (n_species < 1 || n_species > SPL_MAX_SPECIES)
+    return fail(c, SPL_EINVAL, "n_species %d outside 1..%d", n_species, SPL_MAX_SPECIES);
+  if (!p || p->n < 0) return fail(c, SPL_EINVAL, "bad particle set");
+  if (p->n > 0 && !p->scalar) return fail(c, SPL_EINVAL, "scalar array is NULL");
+  if (p->attr_dtype < SPL_F32 || p->attr_dtype > SPL_F16)
+    return fail(c, SPL_EINVAL, "unknown attr_dtype %d", p->attr_dtype);
+  HIPTRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  TRY(ensure(c, c->minmax, 4 * SPL_MAX_SPECIES * 8));
+  ProjK pk;
+  std::memset(&pk, 0, sizeof(pk));
+  pk.scal = p->scalar;
+  pk.species = p->species;
+  pk.dtype = p->attr_dtype;
+  pk.n = p->n;
+  HIPTRY(c, launch_scalar_range(pk, n_species, log10_scalar ? 1 : 0, (double *)c->minmax.p, s));
+  double h[2 * SPL_MAX_SPECIES];
+  HIPTRY(c, hipMemcpyAsync(h, (double *)c->minmax.p + 2 * SPL_MAX_SPECIES,
+                           2 * SPL_MAX_SPECIES * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  for (int k = 0; k < n_species; ++k) {
+    lo[k] = h[2 * k];
+    hi[k] = h[2 * k + 1];
+  }
+  return SPL_OK;
+}
+
+spl_status spl_project(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
+                       const spl_params *prm, float *rec, float *rec2, void *stream) {
+  if (!c) return SPL_EINVAL;
+  ProjK pk;
+  TRY(check_params(c, prm, true));
+  TRY(check_particles(c, p, prm->mode));
+  TRY(camera_frame(c, cam, pk));
+  if (p->n > 0 && !rec) return fail(c, SPL_EINVAL, "rec is NULL");
+  HIPTRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  fill_proj(pk, p, prm);
+  TileK tk;
+  fill_tiles(tk, cam->width, cam->height, kDefaultTile, prm->nu, INFINITY, 0);
+  TRY(ensure(c, c->span, (size_t)p->n * 8));
+  TRY(ensure(c, c->totals, sizeof(Totals)));
+  HIPTRY(c, launch_fill_u32((uint32_t *)c->totals.p, 0u, sizeof(Totals) / 4, s));
+  HIPTRY(c, launch_project(pk, tk, rec, rec2, (uint2 *)c->span.p, 1, (Totals *)c->totals.p, s));
+  return SPL_OK;
+}
+
+spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, int32_t width,
+                   int32_t height, int32_t tile, double nu, int32_t bin_rule, int32_t by_depth,
+                   uint32_t *counts, uint32_t *offsets, uint32_t *pairs, int64_t pairs_cap,
+                   int64_t *n_pairs, void *stream) {
+  if (!c) return SPL_EINVAL;
+  if (n < 0 || n >= (int64_t)0xffffffffll) return fail(c, SPL_EINVAL, "bad record count");
+  if (n > 0 && !rec) return fail(c, SPL_EINVAL, "rec is NULL");
+  if (by_depth && n > 0 && !rec2) return fail(c, SPL_EINVAL, "by_depth needs rec2");
+  if (width < 1 || height < 1 || width > 32768 || height > 32768 || tile < 1)
+    return fail(c, SPL_EINVAL, "bad image or tile size");
+  if (!(nu > 0.0)) return fail(c, SPL_EINVAL, "nu must be > 0");
+  if (bin_rule != 0 && bin_rule != 1) return fail(c, SPL_EINVAL, "bin_rule must be 0 or 1");
+  if (!counts || !offsets || !n_pairs) return fail(c, SPL_EINVAL, "output array is NULL");
+  TileK tk;
+  fill_tiles(tk, width, height, tile, nu, INFINITY, bin_rule);
+  if ((int64_t)tk.ntx * tk.nty > (1 << 24)) return fail(c, SPL_EINVAL, "more than 2^24 tiles");
+  HIPTRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = tk.n_tiles;
+  TRY(ensure(c, c->span, (size_t)n * 8));
+  TRY(ensure(c, c->cursor, (size_t)nb * 4));
+  TRY(ensure(c, c->item_off, (size_t)3 * (nb + 1) * 4));
+  TRY(ensure(c, c->totals, sizeof(Totals)));
+  HIPTRY(c, launch_fill_u32(counts, 0u, nb, s));
+  HIPTRY(c, launch_fill_u32((uint32_t *)c->totals.p, 0u, sizeof(Totals) / 4, s));
+  Totals *tot = (Totals *)c->totals.p;
+  HIPTRY(c, launch_span_from_records(rec, n, tk, (uint2 *)c->span.p, tot, s));
+  HIPTRY(c, launch_count((const uint2 *)c->span.p, rec, n, tk, counts, s));
+  const int chunk[3] = {0, by_depth ? kSortChunk : 0, by_depth ? kMergeOut : 0};
+  const int cchunk[3] = {0, 0, 0};
+  const int minc[3] = {1, 1, kSortChunk + 1};
+  uint32_t *item_off = (uint32_t *)c->item_off.p;
+  HIPTRY(c, launch_scan(counts, nb, nb, offsets, (uint32_t *)c->cursor.p, chunk, cchunk, minc,
+                        item_off, tot, s));
+  HIPTRY(c, hipMemcpyAsync(c->h_tot, tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  const Totals T = *c->h_tot;
+  if (T.n_pairs >= 0xffffffffull) return fail(c, SPL_EUNSUPPORTED, "too many list entries");
+  *n_pairs = (int64_t)T.n_pairs;
+  if (!pairs) return SPL_OK;
+  if ((int64_t)T.n_pairs > pairs_cap)
+    return fail(c, SPL_ENOMEM, "pairs_cap %lld < %llu entries", (long long)pairs_cap, T.n_pairs);
+  if (!by_depth) {
+    HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, rec2, n, tk, (uint32_t *)c->cursor.p,
+                             pairs, nullptr, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    return SPL_OK;
+  }
+  TRY(ensure(c, c->keysA, T.n_pairs * 8));
+  TRY(ensure(c, c->keysB, T.n_pairs * 8));
+  for (int k = 1; k < 3; ++k) {
+    TRY(ensure(c, c->items[k], T.n_items[k] * sizeof(Item)));
+    if (T.n_items[k])
+      HIPTRY(c, launch_build_items(counts, offsets, nb, nb, chunk[k], 0, minc[k],
+                                   item_off + k * (nb + 1), (Item *)c->items[k].p, s));
+  }
+  unsigned long long *A = (unsigned long long *)c->keysA.p, *B = (unsigned long long *)c->keysB.p;
+  HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, rec2, n, tk, (uint32_t *)c->cursor.p,
+                           nullptr, A, s));
+  HIPTRY(c, launch_sort_chunks(A, (const Item *)c->items[1].p, (int)T.n_items[1], s));
+  int passes = 0;
+  for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {
+    HIPTRY(c, launch_merge_pass(passes % 2 ? B : A, passes % 2 ? A : B,
+                                (const Item *)c->items[2].p, (int)T.n_items[2], offsets, counts,
+                                (int)L, s));
+    ++passes;
+  }
+  // lists short enough for one in-LDS sort never leave A; merged lists end in
+  // B after an odd number of passes
+  if (passes % 2)
+    HIPTRY(c, launch_copy_items(B, A, (const Item *)c->items[2].p, (int)T.n_items[2], s));
+  HIPTRY(c, launch_keys_to_pids(A, (int64_t)T.n_pairs, pairs, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  return SPL_OK;
+}
+
+spl_status spl_render_records(spl_ctx *c, int64_t n, const float *rec, const float *rec2,
+                              const spl_camera *cam, const spl_params *prm, float *out,
+                              spl_stats *st, void *stream) {
+  if (!c) return SPL_EINVAL;
+  TRY(check_params(c, prm, false));
+  if (!cam || cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
+    return fail(c, SPL_EINVAL, "bad image size");
+  if (n < 0 || n >= (int64_t)0xffffffffll) return fail(c, SPL_EINVAL, "bad record count");
+  if (n > 0 && !rec) return fail(c, SPL_EINVAL, "rec is NULL");
+  if (prm->mode == SPL_SORTED && n > 0 && !rec2)
+    return fail(c, SPL_EINVAL, "sorted mode needs rec2");
+  if (!out) return fail(c, SPL_EINVAL, "output image is NULL");
+  HIPTRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  int tile;
+  double cut;
+  choose(c, n, cam->width, cam->height, prm, tile, cut);
+  TileK tk;
+  fill_tiles(tk, cam->width, cam->height, tile, prm->nu, cut, prm->bin_rule);
+  TRY(prepare_common(c, n, tk, s));
+  TimedFrame tfr;
+  TimedFrame *tf = (c->timing && begin_timed(c, tfr)) ? &tfr : nullptr;
+  mark(tf, 0, s);
+  HIPTRY(c, launch_span_from_records(rec, n, tk, (uint2 *)c->span.p, (Totals *)c->totals.p, s));
+  mark(tf, 1, s);
+  Frame f{n, rec, prm->mode == SPL_SORTED ? rec2 : nullptr, tk, prm->mode, prm->normalise, out,
+          32.0, 0.0, nullptr};
+  return render_timed(c, f, tf, st, s);
+}
+
+spl_status spl_set_timing(spl_ctx *c, int32_t enable) {
+  if (!c) return SPL_EINVAL;
+  c->timing = enable != 0;
+  return SPL_OK;
+}
+
+spl_status spl_get_timing(spl_ctx *c, double *ms, double *bytes, int64_t *frames) {
+  if (!c) return SPL_EINVAL;
+  if (!ms || !bytes || !frames) return fail(c, SPL_EINVAL, "output arrays are NULL");
+  HIPTRY(c, hipSetDevice(c->device));
+  resolve_timing(c, true);
+  for (int k = 0; k < SPL_N_STAGES; ++k) {
+    ms[k] = c->acc_ms[k];
+    bytes[k] = c->acc_bytes[k];
+    c->acc_ms[k] = 0.0;
+    c->acc_bytes[k] = 0.0;
+  }
+  *frames = c->acc_frames;
+  c->acc_frames = 0;
+  return SPL_OK;
+}
+
+spl_status spl_render(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
+                      const spl_params *prm, float *out, spl_stats *st, void *stream) {
+  if (!c) return SPL_EINVAL;
+  HIPTRY(c, hipSetDevice(c->device));
+  return render_one(c, p, cam, prm, out, st, (hipStream_t)stream);
+}
+
+spl_status spl_render_batch(spl_ctx *c, const spl_particles *p, int32_t n_views,
+                            const spl_camera *cams, const spl_params *prms, float *const *outs,
+                            spl_stats *st, void *stream) {
+  if (!c) return SPL_EINVAL;
+  if (n_views < 0 || (n_views > 0 && (!cams || !prms || !outs)))
+    return fail(c, SPL_EINVAL, "bad view arrays");
+  HIPTRY(c, hipSetDevice(c->device));
+  for (int v = 0; v < n_views; ++v)
+    TRY(render_one(c, p, &cams[v], &prms[v], outs[v], st ? &st[v] : nullptr, (hipStream_t)stream));
+  return SPL_OK;
+}
+
+spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
+                        const spl_params *prm, int32_t *tile_out, double *cut_out, void *stream) {
+  if (!c) return SPL_EINVAL;
+  if (!tile_out || !cut_out) return fail(c, SPL_EINVAL, "outputs are NULL");
+  TRY(check_params(c, prm, true));
+  TRY(check_particles(c, p, prm->mode));
+  ProjK pk;
+  TRY(camera_frame(c, cam, pk));
+  HIPTRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  float *img = nullptr;
+  if (hipMalloc(&img, (size_t)cam->width * cam->height * 12) != hipSuccess)
+    return fail(c, SPL_ENOMEM, "autotune image allocation failed");
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const int tiles[2] = {16, 32};
+  const double cuts_add[5] = {16.0, 32.0, 64.0, 128.0, -1.0};
+  const double cuts_sorted[1] = {-1.0};
+  const double *cuts = prm->mode == SPL_SORTED ? cuts_sorted : cuts_add;
+  const int ncut = prm->mode == SPL_SORTED ? 1 : 5;
+  float best = INFINITY;
+  int best_tile = kDefaultTile;
+  double best_cut = kDefaultCut;
+  spl_status rc = SPL_OK;
+  for (int ti = 0; ti < 2 && rc == SPL_OK; ++ti)
+    for (int ci = 0; ci < ncut && rc == SPL_OK; ++ci) {
+      spl_params q = *prm;
+      q.tile = tiles[ti];
+      q.large_cut = cuts[ci];
+      float tmin = INFINITY;
+      for (int rep = 0; rep < 3 && rc == SPL_OK; ++rep) {
+        hipEventRecord(e0, s);
+        rc = render_one(c, p, cam, &q, img, nullptr, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && ms < tmin) tmin = ms;
+      }
+      if (tmin < best) {
+        best = tmin;
+        best_tile = tiles[ti];
+        best_cut = cuts[ci] < 0 ? -1.0 : cuts[ci];
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(img);
+  if (rc != SPL_OK) return rc;
+  c->tune[std::make_tuple(p->n, cam->width, cam->height, prm->mode)] =
+      std::make_pair(best_tile, best_cut < 0 ? INFINITY : best_cut);
+  *tile_out = best_tile;
+  *cut_out = best_cut;
+  return SPL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Internal declarations of the gfx950 Splotch library: kernel parameter
+// blocks, launch wrappers and the device helpers that more than one kernel
+// must evaluate identically (the single-precision pixel box and tile span).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "splotch.h"
+
+namespace spl {
+
+constexpr int kBlock = 256;
+constexpr uint32_t kInactive = 0xffffffffu;
+constexpr uint32_t kLargeFlag = 0x80000000u;
+
+// Work item: one chunk of one tile's list.
+//   x = bin (tile index), y = first list entry, z = end, w = chunk index.
+using Item = uint4;
+
+struct LookK {
+  const float *rgb;
+  int M;
+  int log10;
+  float beta;
+  float lo;
+  float inv_range;  // 1/(hi - lo); 0 when hi == lo
+};
+
+// Tile geometry of one view.  Fine tiles are bins [0, n_tiles); large-particle
+// tiles are bins [n_tiles, n_tiles + n_ctiles).
+struct TileK {
+  int W, H;
+  int tile, ntx, nty, n_tiles;
+  int ctile, nctx, ncty, n_ctiles;
+  float nu;         // truncation radius in sigma units
+  float large_cut;  // px; +inf disables the large path
+  int bin_rule;     // 0 exact box, 1 paper distance threshold (fine tiles)
+};
+
+struct ProjK {
+  // camera frame (FP64)
+  double e[3], r[3], u[3], f[3];
+  double F, cx, cy, z_near;
+  double k_sigma, sigma_min, nu;
+  int mode;
+  int n_species;
+  LookK looks[SPL_MAX_SPECIES];
+  // particles
+  const float *x, *y, *z;
+  const void *h, *inten, *scal;
+  int dtype;
+  float h_scale;
+  const uint8_t *species;
+  const float *absorb;
+  int64_t n;
+};
+
+// Device totals written by the binning stage and read back by the host.
+struct Totals {
+  unsigned long long n_active;
+  unsigned long long n_large;
+  unsigned long long n_pairs;       // all bins
+  unsigned long long n_fine_pairs;  // fine bins only
+  unsigned long long n_items[3];    // item lists (see build)
+  unsigned long long n_fine_items[3];
+  unsigned int max_count;           // largest fine-bin count
+  unsigned int n_fine_nonempty;     // fine bins with at least one entry
+  unsigned int n_coarse_nonempty;   // large-particle bins with at least one entry
+  unsigned int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Pixel box of a record in single precision.  Each line is one IEEE binary32
+// operation, in this order, with contraction disabled: the binning, the
+// splat and the host-side checks must all produce the same integers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool record_box(float Xi, float Xf, float Yi, float Yf, float s,
+                                           float nu, int W, int H, int &i0, int &i1,
+                                           int &j0, int &j1) {
+#pragma clang fp contract(off)
+  if (!(s > 0.0f)) return false;
+  if (!(__builtin_isfinite(Xi) && __builtin_isfinite(Xf) && __builtin_isfinite(Yi) &&
+        __builtin_isfinite(Yf) && __builtin_isfinite(s)))
+    return false;
+  const float R = nu * s;
+  const float fx = Xf - 0.5f;
+  const float fy = Yf - 0.5f;
+  const float lx = fx - R;
+  const float hx = fx + R;
+  const float ly = fy - R;
+  const float hy = fy + R;
+  double a0 = (double)Xi + (double)__builtin_ceilf(lx);
+  double a1 = (double)Xi + (double)__builtin_floorf(hx);
+  double b0 = (double)Yi + (double)__builtin_ceilf(ly);
+  double b1 = (double)Yi + (double)__builtin_floorf(hy);
+  if (a0 < 0.0) a0 = 0.0;
+  if (b0 < 0.0) b0 = 0.0;
+  if (a1 > (double)(W - 1)) a1 = (double)(W - 1);
+  if (b1 > (double)(H - 1)) b1 = (double)(H - 1);
+  if (a0 > a1 || b0 > b1) return false;
+  i0 = (int)a0;
+  i1 = (int)a1;
+  j0 = (int)b0;
+  j1 = (int)b1;
+  return true;
+}
+
+// The paper's tile-inclusion threshold (tile-list pseudocode figure):
+// keep tile (tx, ty) if the distance from the particle to the tile centre is
+// below 0.75 R + sqrt(2) T / 2.  Single precision, contraction off.
+__device__ __forceinline__ bool paper_rule_keeps(float Xi, float Xf, float Yi, float Yf,
+                                                 float s, float nu, int tile, int tx, int ty) {
+#pragma clang fp contract(off)
+  const float R = nu * s;
+  const float cx = (float)(tx * tile) + 0.5f * (float)tile;
+  const float cy = (float)(ty * tile) + 0.5f * (float)tile;
+  const float dx = (Xi - cx) + Xf;
+  const float dy = (Yi - cy) + Yf;
+  const float t1 = dx * dx;
+  const float t2 = dy * dy;
+  const float d2 = t1 + t2;
+  const float a1 = 0.75f * R;
+  const float a2 = (float)tile * 0.70710678f;
+  const float thr = a1 + a2;
+  const float thr2 = thr * thr;
+  return d2 < thr2;
+}
+
+// Tile span of a record: .x = tx0 | tx1 << 16, .y = ty0 | ty1 << 16, with
+// kLargeFlag set in .y when the span is in large-particle tiles.  kInactive in
+// .x when the record does not reach the image.
+__device__ __forceinline__ uint2 record_span(const float4 r0, float sigma, const TileK &tk) {
+  int i0, i1, j0, j1;
+  uint2 sp;
+  if (!record_box(r0.x, r0.y, r0.z, r0.w, sigma, tk.nu, tk.W, tk.H, i0, i1, j0, j1)) {
+    sp.x = kInactive;
+    sp.y = kInactive;
+    return sp;
+  }
+  float R;
+  {
+#pragma clang fp contract(off)
+    R = tk.nu * sigma;
+  }
+  if (R > tk.large_cut) {
+    const int c = tk.ctile;
+    sp.x = (uint32_t)(i0 / c) | ((uint32_t)(i1 / c) << 16);
+    sp.y = ((uint32_t)(j0 / c) | ((uint32_t)(j1 / c) << 16)) | kLargeFlag;
+  } else {
+    const int t = tk.tile;
+    sp.x = (uint32_t)(i0 / t) | ((uint32_t)(i1 / t) << 16);
+    sp.y = (uint32_t)(j0 / t) | ((uint32_t)(j1 / t) << 16);
+  }
+  return sp;
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (each returns hipSuccess or the launch error).
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+
+hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *rec2,
+                          uint2 *span, int write_inactive, Totals *tot, hipStream_t s);
+hipError_t launch_span_from_records(const float *rec, int64_t n, const TileK &tk, uint2 *span,
+                                    Totals *tot, hipStream_t s);
+hipError_t launch_scalar_range(const ProjK &pk, int n_species, int log10, double *out_minmax,
+                               hipStream_t s);
+
+hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
+                        uint32_t *counts, hipStream_t s);
+// Exclusive scan of counts (n_bins) into offsets (n_bins + 1) and cursor; item
+// counts for up to three chunk sizes (chunk[k] > 0; bins below min_count[k]
+// get no item; fine chunk applies to fine bins, cchunk[k] to large bins).
+hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t *offsets,
+                       uint32_t *cursor, const int chunk[3], const int cchunk[3],
+                       const int min_count[3], uint32_t *item_off /* 3 x (n_bins+1) */,
+                       Totals *tot, hipStream_t s);
+hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, int n_bins,
+                              int n_fine, int chunk, int cchunk, int min_count,
+                              const uint32_t *item_off, Item *items, hipStream_t s);
+hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,
+                          const TileK &tk, uint32_t *cursor, uint32_t *pairs,
+                          unsigned long long *keys, hipStream_t s);
+
+hipError_t launch_sort_chunks(unsigned long long *keys, const Item *items, int n_items,
+                              hipStream_t s);
+hipError_t launch_merge_pass(const unsigned long long *src, unsigned long long *dst,
+                             const Item *items, int n_items, const uint32_t *offsets,
+                             const uint32_t *counts, int run, hipStream_t s);
+hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32_t *pids,
+                               hipStream_t s);
+hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *dst,
+                             const Item *items, int n_items, hipStream_t s);
+
+hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint32_t *pairs,
+                            const float *rec, const uint32_t *counts, int chunk,
+                            const TileK &tk, int scat_max, float *img, hipStream_t s);
+hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pairs,
+                              const float *rec, const uint32_t *counts, int cchunk,
+                              const TileK &tk, float *img, hipStream_t s);
+hipError_t launch_composite(int tile, const Item *items, int n_items,
+                            const unsigned long long *keys, const float *rec,
+                            const float *rec2, const uint32_t *counts, int chunk,
+                            const TileK &tk, float *img, float *partial, hipStream_t s);
+hipError_t launch_composite_merge(int tile, const Item *items, int n_items,
+                                  const uint32_t *counts, int chunk, const TileK &tk,
+                                  const float *partial, float *img, hipStream_t s);
+
+hipError_t launch_finalise(float *img, int64_t n_px, int aeqe, double *partials, int n_blocks,
+                           hipStream_t s);
+hipError_t launch_reduce_stats(const double *partials, int n_blocks, double *stats,
+                               hipStream_t s);
+hipError_t launch_normalise(float *img, int64_t n_px, const double *stats, hipStream_t s);
+
+}  // namespace spl

@@ -52,7 +52,8 @@ class Pose:
 
 
 def palette(kind: int, n_entries: int = 256) -> np.ndarray:
-    """Smooth monotone RGB ramps built from power laws, shape (n_entries, 3).
+    """Smooth monotone RGB ramps built from power laws over a dim floor, shape
+    (n_entries, 3).
 
     kind selects the exponents; 0 is a warm ramp (gas), 1 a cold ramp (stars),
     2..7 mixed ramps for a bank of looks."""
@@ -68,7 +69,8 @@ def palette(kind: int, n_entries: int = 256) -> np.ndarray:
         (2.6, 2.0, 0.8),
     ]
     er, eg, eb = exps[kind % len(exps)]
-    rgb = np.stack([t ** er, t ** eg, t ** eb], axis=1)
+    # dim, non-black floor so the lowest scalar still emits
+    rgb = 0.04 + 0.96 * np.stack([t ** er, t ** eg, t ** eb], axis=1)
     return np.ascontiguousarray(rgb, dtype=np.float32)
 
 
