@@ -19,7 +19,7 @@ namespace spl {
 namespace {
 
 constexpr int kLdsBins = 16384;  // 64 KB of u32 bins
-constexpr int kChunk = 16384;    // particles per workgroup pass
+constexpr int kChunk = 4096;     // particles per workgroup pass
 
 struct SpanDec {
   int tx0, tx1, ty0, ty1;
@@ -36,6 +36,23 @@ __device__ __forceinline__ SpanDec decode(uint2 s) {
   return d;
 }
 
+// Run-length aggregation inside a wave: consecutive lanes whose particle
+// covers exactly one tile, the same one, form a run; the run's first lane
+// (head) does one atomic for the whole run.  Returns the run length at the
+// head (0 elsewhere); *head_of gets the lane index of the lane's run head.
+__device__ __forceinline__ int wave_runs(bool single, int key, int &head_of) {
+  const int lane = __lane_id();
+  const int prev = __shfl_up(key, 1);
+  const bool head = single && (lane == 0 || prev != key);
+  const unsigned long long brk = __ballot(!single || head);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = (lane == 63) ? heads : (heads & ((2ull << lane) - 1ull));
+  head_of = upto ? 63 - __builtin_clzll(upto) : lane;
+  if (!head) return 0;
+  const unsigned long long after = (lane == 63) ? 0ull : (brk >> (lane + 1));
+  return after ? (__builtin_ctzll(after) + 1) : (64 - lane);
+}
+
 template <bool kLds>
 __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
                                                   const float4 *__restrict__ rec, int64_t n,
@@ -43,6 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
   extern __shared__ uint32_t hist[];
   const int nb = tk.n_tiles + tk.n_ctiles;
   const bool paper = tk.bin_rule == 1;
+  uint32_t *bins = kLds ? hist : counts;
   for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
        base += (int64_t)gridDim.x * kChunk) {
     if (kLds) {
@@ -50,29 +68,33 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
       __syncthreads();
     }
     const int64_t end = min(base + (int64_t)kChunk, n);
-    for (int64_t k = base + threadIdx.x; k < end; k += kBlock) {
-      const uint2 s = span[k];
-      if (s.x == kInactive) continue;
+    for (int64_t kb = base; kb < end; kb += kBlock) {  // uniform trip count
+      const int64_t k = kb + threadIdx.x;
+      const uint2 s = (k < end) ? span[k] : make_uint2(kInactive, kInactive);
+      const bool act = s.x != kInactive;
       const SpanDec d = decode(s);
       const int ntx = d.large ? tk.nctx : tk.ntx;
       const int off = d.large ? tk.n_tiles : 0;
       const bool filt = paper && !d.large;
-      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      float sg = 0.f;
-      if (filt) {
-        r0 = rec[2 * k];
-        sg = rec[2 * k + 1].x;
-      }
-      for (int ty = d.ty0; ty <= d.ty1; ++ty)
-        for (int tx = d.tx0; tx <= d.tx1; ++tx) {
-          if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
-            continue;
-          const int b = off + ty * ntx + tx;
-          if (kLds)
-            atomicAdd(&hist[b], 1u);
-          else
-            atomicAdd(&counts[b], 1u);
+      const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
+      const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
+      int head_of;
+      const int len = wave_runs(single, key, head_of);
+      if (len) atomicAdd(&bins[key], (uint32_t)len);
+      if (act && !single) {
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+        float sg = 0.f;
+        if (filt) {
+          r0 = rec[2 * k];
+          sg = rec[2 * k + 1].x;
         }
+        for (int ty = d.ty0; ty <= d.ty1; ++ty)
+          for (int tx = d.tx0; tx <= d.tx1; ++tx) {
+            if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
+              continue;
+            atomicAdd(&bins[off + ty * ntx + tx], 1u);
+          }
+      }
     }
     if (kLds) {
       __syncthreads();
@@ -95,19 +117,74 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
   extern __shared__ uint32_t hist[];
   const int nb = tk.n_tiles + tk.n_ctiles;
   const bool paper = tk.bin_rule == 1;
+  uint32_t *bins = kLds ? hist : cursor;
   for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
        base += (int64_t)gridDim.x * kChunk) {
     const int64_t end = min(base + (int64_t)kChunk, n);
     if (kLds) {
+      // local counts of this chunk, then one global reservation per bin
       for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
       __syncthreads();
-      for (int64_t k = base + threadIdx.x; k < end; k += kBlock) {
-        const uint2 s = span[k];
-        if (s.x == kInactive) continue;
+      for (int64_t kb = base; kb < end; kb += kBlock) {
+        const int64_t k = kb + threadIdx.x;
+        const uint2 s = (k < end) ? span[k] : make_uint2(kInactive, kInactive);
+        const bool act = s.x != kInactive;
         const SpanDec d = decode(s);
         const int ntx = d.large ? tk.nctx : tk.ntx;
         const int off = d.large ? tk.n_tiles : 0;
         const bool filt = paper && !d.large;
+        const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
+        const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
+        int head_of;
+        const int len = wave_runs(single, key, head_of);
+        if (len) atomicAdd(&hist[key], (uint32_t)len);
+        if (act && !single) {
+          float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+          float sg = 0.f;
+          if (filt) {
+            r0 = rec[2 * k];
+            sg = rec[2 * k + 1].x;
+          }
+          for (int ty = d.ty0; ty <= d.ty1; ++ty)
+            for (int tx = d.tx0; tx <= d.tx1; ++tx) {
+              if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
+                continue;
+              atomicAdd(&hist[off + ty * ntx + tx], 1u);
+            }
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < nb; i += kBlock) {
+        const uint32_t v = hist[i];
+        if (v) hist[i] = atomicAdd(&cursor[i], v);
+      }
+      __syncthreads();
+    }
+    for (int64_t kb = base; kb < end; kb += kBlock) {
+      const int64_t k = kb + threadIdx.x;
+      const uint2 s = (k < end) ? span[k] : make_uint2(kInactive, kInactive);
+      const bool act = s.x != kInactive;
+      const SpanDec d = decode(s);
+      const int ntx = d.large ? tk.nctx : tk.ntx;
+      const int off = d.large ? tk.n_tiles : 0;
+      const bool filt = paper && !d.large;
+      const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
+      const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
+      unsigned long long key_hi = 0;
+      if (kKeys && act) key_hi = (unsigned long long)__float_as_uint(rec2[k].y) << 32;
+      int head_of;
+      const int len = wave_runs(single, key, head_of);
+      uint32_t rb = 0;
+      if (len) rb = atomicAdd(&bins[key], (uint32_t)len);
+      // every lane takes part in the shuffle; run members read their head's base
+      const uint32_t hb = (uint32_t)__shfl((int)rb, head_of);
+      if (single) {
+        const uint32_t slot = hb + (uint32_t)(__lane_id() - head_of);
+        if (kKeys)
+          keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
+        else
+          pairs[slot] = (uint32_t)k;
+      } else if (act) {
         float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
         float sg = 0.f;
         if (filt) {
@@ -118,42 +195,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
           for (int tx = d.tx0; tx <= d.tx1; ++tx) {
             if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
               continue;
-            atomicAdd(&hist[off + ty * ntx + tx], 1u);
+            const uint32_t slot = atomicAdd(&bins[off + ty * ntx + tx], 1u);
+            if (kKeys)
+              keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
+            else
+              pairs[slot] = (uint32_t)k;
           }
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < nb; i += kBlock) {
-        const uint32_t v = hist[i];
-        if (v) hist[i] = atomicAdd(&cursor[i], v);
-      }
-      __syncthreads();
-    }
-    for (int64_t k = base + threadIdx.x; k < end; k += kBlock) {
-      const uint2 s = span[k];
-      if (s.x == kInactive) continue;
-      const SpanDec d = decode(s);
-      const int ntx = d.large ? tk.nctx : tk.ntx;
-      const int off = d.large ? tk.n_tiles : 0;
-      const bool filt = paper && !d.large;
-      float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-      float sg = 0.f;
-      if (filt) {
-        r0 = rec[2 * k];
-        sg = rec[2 * k + 1].x;
-      }
-      unsigned long long key_hi = 0;
-      if (kKeys) key_hi = (unsigned long long)__float_as_uint(rec2[k].y) << 32;
-      for (int ty = d.ty0; ty <= d.ty1; ++ty)
-        for (int tx = d.tx0; tx <= d.tx1; ++tx) {
-          if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
-            continue;
-          const int b = off + ty * ntx + tx;
-          const uint32_t slot = kLds ? atomicAdd(&hist[b], 1u) : atomicAdd(&cursor[b], 1u);
-          if (kKeys)
-            keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
-          else
-            pairs[slot] = (uint32_t)k;
-        }
     }
     if (kLds) __syncthreads();
   }

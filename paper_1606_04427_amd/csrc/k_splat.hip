@@ -6,15 +6,17 @@
 // atomics (additive) or by an ordered merge of partial (colour,
 // transmittance) tiles (sorted).
 //
-// k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of 256
-//                  list entries is loaded once, one entry per lane.  Entries
-//                  whose box covers few of the tile's pixels are scattered by
-//                  their own lane into an LDS accumulator with LDS float
-//                  atomics; larger ones are staged in LDS and gathered by all
-//                  lanes, one pixel per lane, skipping (wave-uniformly) the
-//                  ones that miss a wave's rows.  After every batch the LDS
-//                  and register partials are folded into per-pixel
-//                  Neumaier-compensated sums.
+// k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of list
+//                  entries is loaded once, one entry per lane, and each
+//                  entry's box inside the tile is cut into 4 x 4 windows
+//                  listed in LDS (offsets from a prefix sum, no atomics).
+//                  16-lane groups take the windows round-robin, one pixel per
+//                  lane, keep running sums while a group's consecutive
+//                  windows coincide (dense cluster cores) and add them into a
+//                  64-bit fixed-point LDS accumulator with integer atomics
+//                  (LDS FP32 atomics are ~40x slower on this hardware).  After
+//                  every batch the accumulator is folded into per-pixel
+//                  Neumaier-compensated FP32 sums.
 // k_splat_large    the large-particle path: 64 x 64 px tiles, 512 lanes, 8
 //                  pixels per lane, gather only (a large particle covers most
 //                  of the pixels it is tested against).
@@ -40,48 +42,58 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
   return (uint32_t)a0 | ((uint32_t)a1 << 8) | ((uint32_t)b0 << 16) | ((uint32_t)b1 << 24);
 }
 
-template <int T>
+// One list entry's box inside a tile is cut into 4 x 4 windows.  A window
+// work item is a 16-bit word: entry slot in the batch (8 bits), window row and
+// column inside the entry's box (4 bits each).
+//
+// Accumulation is in 64-bit fixed point: per batch, the scale 2^S is chosen so
+// that the batch's summed amplitude stays below 2^61, so no pixel sum can
+// overflow; LDS 64-bit integer atomics are cheap on this hardware, LDS FP32
+// atomics are not.  Integer sums are also independent of the order in which
+// the groups add.
+template <int T, int BATCH>
 __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ items,
                                                       const uint32_t *__restrict__ pairs,
                                                       const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ counts,
-                                                      int chunk, TileK tk, int scat_max,
+                                                      int chunk, TileK tk,
                                                       float *__restrict__ img) {
   constexpr int NP = T * T;
-  constexpr int PX = NP / kBlock;
-  constexpr int WROWS = (64 / T) * PX;  // rows covered by one wave
-  __shared__ float acc[3 * NP];
-  __shared__ float g_ox[kBlock], g_fx[kBlock], g_oy[kBlock], g_fy[kBlock], g_is2[kBlock];
-  __shared__ float g_a0[kBlock], g_a1[kBlock], g_a2[kBlock];
-  __shared__ uint32_t g_box[kBlock];
-  __shared__ int g_count;
+  constexpr int PX = NP / kBlock;            // pixels per lane in the fold
+  constexpr int MAXWIN = (T / 4) * (T / 4);  // windows of a box that fills the tile
+  constexpr int NLW = BATCH / 64;            // waves that load entries
+  constexpr float kLog2e = 1.4426950408889634f;
+  __shared__ unsigned long long acc[3 * NP];
+  __shared__ float4 s_geo[BATCH];  // x offset, y offset, log2(e)/sigma^2, -
+  __shared__ float4 s_col[BATCH];  // premultiplied colour, packed box in .w
+  __shared__ uint16_t s_win[BATCH * MAXWIN];
+  __shared__ int s_wsum[4];
+  __shared__ float s_asum[4];
 
   const Item it = items[blockIdx.x];
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
-  const int tid = threadIdx.x;
-  const int pc = tid % T;
-  const int pr0 = (tid / T) * PX;
-  const int wr0 = (tid / 64) * WROWS, wr1 = wr0 + WROWS - 1;
-  const float nu2 = tk.nu * tk.nu;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = tid >> 4, kx = tid & 3, ky = (tid >> 2) & 3;
+  const float qmax = tk.nu * tk.nu * kLog2e;
 
-  float sum[PX][3], comp[PX][3], bs[PX][3];
+  float sum[PX][3], comp[PX][3];
 #pragma unroll
   for (int m = 0; m < PX; ++m)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       sum[m][c] = 0.f;
       comp[m][c] = 0.f;
-      bs[m][c] = 0.f;
     }
-  for (int i = tid; i < 3 * NP; i += kBlock) acc[i] = 0.f;
+  for (int i = tid; i < 3 * NP; i += kBlock) acc[i] = 0ull;
 
-  for (uint32_t base = it.y; base < it.z; base += kBlock) {
-    if (tid == 0) g_count = 0;
-    __syncthreads();
+  for (uint32_t base = it.y; base < it.z; base += BATCH) {
+    // phase 1: one list entry per loading lane -> box in the tile, constants
     const uint32_t k = base + tid;
-    if (k < it.z) {
+    int nwin = 0, nwx = 1;
+    float amax = 0.f;
+    if (tid < BATCH && k < it.z) {
       const uint32_t pid = pairs[k];
       const float4 r0 = rec[2 * (size_t)pid];
       const float4 r1 = rec[2 * (size_t)pid + 1];
@@ -90,81 +102,105 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
         const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
         const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
         if (li0 <= li1 && lj0 <= lj1) {
-          const float ox = r0.x - (float)x0, fx = 0.5f - r0.y;
-          const float oy = r0.z - (float)y0, fy = 0.5f - r0.w;
-          const float is2 = 1.0f / (r1.x * r1.x);
-          const int area = (li1 - li0 + 1) * (lj1 - lj0 + 1);
-          if (area <= scat_max) {
-            for (int jj = lj0; jj <= lj1; ++jj) {
-              const float dy = ((float)jj - oy) + fy;
-              for (int ii = li0; ii <= li1; ++ii) {
-                const float dx = ((float)ii - ox) + fx;
-                const float q = (dx * dx + dy * dy) * is2;
-                if (q <= nu2) {
-                  const float g = __expf(-q);
-                  const int pix = jj * T + ii;
-                  atomicAdd(&acc[pix], r1.y * g);
-                  atomicAdd(&acc[NP + pix], r1.z * g);
-                  atomicAdd(&acc[2 * NP + pix], r1.w * g);
-                }
-              }
-            }
-          } else {
-            const int slot = atomicAdd(&g_count, 1);
-            g_ox[slot] = ox;
-            g_fx[slot] = fx;
-            g_oy[slot] = oy;
-            g_fy[slot] = fy;
-            g_is2[slot] = is2;
-            g_a0[slot] = r1.y;
-            g_a1[slot] = r1.z;
-            g_a2[slot] = r1.w;
-            g_box[slot] = pack_box(li0, li1, lj0, lj1);
+          // offset of pixel centre (li0 + u, lj0 + v) from the particle is
+          // (cx + u, cy + v); the integer parts subtract exactly
+          const float cx = ((float)(li0 + x0) - r0.x) + (0.5f - r0.y);
+          const float cy = ((float)(lj0 + y0) - r0.z) + (0.5f - r0.w);
+          s_geo[tid] = make_float4(cx, cy, kLog2e / (r1.x * r1.x), 0.f);
+          s_col[tid] = make_float4(r1.y, r1.z, r1.w, __uint_as_float(pack_box(li0, li1, lj0, lj1)));
+          nwx = (li1 - li0) / 4 + 1;
+          nwin = nwx * ((lj1 - lj0) / 4 + 1);
+          amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
+        }
+      }
+    }
+    // window offsets: inclusive scan inside each wave, wave totals in LDS;
+    // batch amplitude bound: sum of each entry's largest channel
+    int incl = nwin;
+    float asum = amax;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+      asum += __shfl_xor(asum, d);
+    }
+    if (wave < NLW && lane == 63) s_wsum[wave] = incl;
+    if (wave < NLW && lane == 0) s_asum[wave] = asum;
+    __syncthreads();
+    int woff = 0, total = 0;
+    float amp_sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < NLW; ++w) {
+      if (w < wave) woff += s_wsum[w];
+      total += s_wsum[w];
+      amp_sum += s_asum[w];
+    }
+    int ex = 0;
+    (void)frexpf(amp_sum, &ex);  // amp_sum <= 2^ex
+    const int S = 61 - ex;       // batch sums stay below 2^61
+    for (int w = 0, o = woff + incl - nwin; w < nwin; ++w, ++o)
+      s_win[o] = (uint16_t)((tid << 8) | ((w / nwx) << 4) | (w % nwx));
+    __syncthreads();
+
+    // phase 2: 16-lane groups take windows round-robin, one pixel per lane,
+    // and keep running sums while a group's consecutive windows coincide
+    {
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      int cur = -1;  // the lane's pixel in the current window; NP = outside
+      for (int e = grp; e < total; e += 16) {
+        const uint32_t w = s_win[e];
+        const int slot = (int)(w >> 8);
+        const float4 g = s_geo[slot];
+        const float4 col = s_col[slot];
+        const uint32_t bx = __float_as_uint(col.w);
+        const int li0 = bx & 0xff, li1 = (bx >> 8) & 0xff, lj0 = (bx >> 16) & 0xff,
+                  lj1 = bx >> 24;
+        const int u = 4 * (int)(w & 15u) + kx, v = 4 * (int)((w >> 4) & 15u) + ky;
+        const int px = li0 + u, py = lj0 + v;
+        const int pix = (px < T && py < T) ? py * T + px : NP;
+        if (pix != cur) {
+          if (cur >= 0 && cur < NP) {
+            atomicAdd(&acc[cur], (unsigned long long)(long long)rintf(ldexpf(a0, S)));
+            atomicAdd(&acc[NP + cur], (unsigned long long)(long long)rintf(ldexpf(a1, S)));
+            atomicAdd(&acc[2 * NP + cur], (unsigned long long)(long long)rintf(ldexpf(a2, S)));
+          }
+          cur = pix;
+          a0 = a1 = a2 = 0.f;
+        }
+        if (px <= li1 && py <= lj1) {
+          const float dx = g.x + (float)u, dy = g.y + (float)v;
+          const float q = (dx * dx + dy * dy) * g.z;
+          if (q <= qmax) {
+            const float e2 = exp2f(-q);
+            a0 += col.x * e2;
+            a1 += col.y * e2;
+            a2 += col.z * e2;
           }
         }
       }
-    }
-    __syncthreads();
-    const int ng = g_count;
-    for (int g = 0; g < ng; ++g) {
-      const uint32_t bx = g_box[g];
-      const int li0 = bx & 0xff, li1 = (bx >> 8) & 0xff, lj0 = (bx >> 16) & 0xff,
-                lj1 = bx >> 24;
-      if (lj1 < wr0 || lj0 > wr1) continue;  // uniform across the wave
-      if (pc < li0 || pc > li1) continue;
-      const float dx = ((float)pc - g_ox[g]) + g_fx[g];
-      const float dx2 = dx * dx;
-      const float is2 = g_is2[g], oy = g_oy[g], fy = g_fy[g];
-#pragma unroll
-      for (int m = 0; m < PX; ++m) {
-        const int row = pr0 + m;
-        if (row < lj0 || row > lj1) continue;
-        const float dy = ((float)row - oy) + fy;
-        const float q = (dx2 + dy * dy) * is2;
-        if (q <= nu2) {
-          const float e = __expf(-q);
-          bs[m][0] += g_a0[g] * e;
-          bs[m][1] += g_a1[g] * e;
-          bs[m][2] += g_a2[g] * e;
-        }
+      if (cur >= 0 && cur < NP) {
+        atomicAdd(&acc[cur], (unsigned long long)(long long)rintf(ldexpf(a0, S)));
+        atomicAdd(&acc[NP + cur], (unsigned long long)(long long)rintf(ldexpf(a1, S)));
+        atomicAdd(&acc[2 * NP + cur], (unsigned long long)(long long)rintf(ldexpf(a2, S)));
       }
     }
     __syncthreads();
+    // phase 3: fold the batch sums into the compensated per-pixel sums
 #pragma unroll
     for (int m = 0; m < PX; ++m) {
-      const int pix = (pr0 + m) * T + pc;
+      const int pix = tid + m * kBlock;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float v = acc[c * NP + pix] + bs[m][c];
-        acc[c * NP + pix] = 0.f;
-        bs[m][c] = 0.f;
-        neumaier(sum[m][c], comp[m][c], v);
+        const long long v = (long long)acc[c * NP + pix];
+        acc[c * NP + pix] = 0ull;
+        neumaier(sum[m][c], comp[m][c], (float)ldexp((double)v, -S));
       }
     }
   }
 #pragma unroll
   for (int m = 0; m < PX; ++m) {
-    const int gx = x0 + pc, gy = y0 + pr0 + m;
+    const int pix = tid + m * kBlock;
+    const int gx = x0 + pix % T, gy = y0 + pix / T;
     if (gx < tk.W && gy < tk.H) {
       float *o = img + 3 * ((size_t)gy * tk.W + gx);
 #pragma unroll
@@ -446,15 +482,15 @@ __global__ __launch_bounds__(kBlock) void k_composite_merge(const Item *__restri
 
 hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint32_t *pairs,
                             const float *rec, const uint32_t *counts, int chunk,
-                            const TileK &tk, int scat_max, float *img, hipStream_t s) {
+                            const TileK &tk, float *img, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   if (tile == 16)
-    hipLaunchKernelGGL(k_splat_add<16>, dim3(n_items), dim3(kBlock), 0, s, items, pairs, r, counts,
-                       chunk, tk, scat_max, img);
+    hipLaunchKernelGGL((k_splat_add<16, 256>), dim3(n_items), dim3(kBlock), 0, s, items, pairs, r,
+                       counts, chunk, tk, img);
   else if (tile == 32)
-    hipLaunchKernelGGL(k_splat_add<32>, dim3(n_items), dim3(kBlock), 0, s, items, pairs, r, counts,
-                       chunk, tk, scat_max, img);
+    hipLaunchKernelGGL((k_splat_add<32, 128>), dim3(n_items), dim3(kBlock), 0, s, items, pairs, r,
+                       counts, chunk, tk, img);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

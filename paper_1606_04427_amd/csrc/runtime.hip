@@ -32,8 +32,6 @@ constexpr int kLargeTile = 64;     // px, tiles of the large-particle path
 constexpr int kDefaultTile = 16;
 constexpr double kDefaultCut = 32.0;  // px
 constexpr int kFinBlocks = 1024;
-constexpr int kScatMax16 = 24;
-constexpr int kScatMax32 = 48;
 
 struct DevBuf {
   void *p = nullptr;
@@ -390,7 +388,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
                                  kChunkLarge, tk, f.out, s));
     mark(tf, 7, s);
     HIPTRY(c, launch_splat_add(tk.tile, items0, nfi, (const uint32_t *)c->pairs.p, f.rec, counts,
-                               kChunkSplat, tk, tk.tile == 16 ? kScatMax16 : kScatMax32, f.out, s));
+                               kChunkSplat, tk, f.out, s));
     mark(tf, 8, s);
   } else {
     HIPTRY(c, launch_sort_chunks(keysA, (const Item *)c->items[1].p, (int)T.n_items[1], s));

@@ -196,7 +196,7 @@ hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *
 
 hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint32_t *pairs,
                             const float *rec, const uint32_t *counts, int chunk,
-                            const TileK &tk, int scat_max, float *img, hipStream_t s);
+                            const TileK &tk, float *img, hipStream_t s);
 hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pairs,
                               const float *rec, const uint32_t *counts, int cchunk,
                               const TileK &tk, float *img, hipStream_t s);
