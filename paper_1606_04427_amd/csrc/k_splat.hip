@@ -13,7 +13,7 @@
 //                  16-lane groups take the windows round-robin, one pixel per
 //                  lane, keep running sums while a group's consecutive
 //                  windows coincide (dense cluster cores) and add them into a
-//                  64-bit fixed-point LDS accumulator with integer atomics
+//                  32-bit fixed-point LDS accumulator with integer atomics
 //                  (LDS FP32 atomics are ~40x slower on this hardware).  After
 //                  every batch the accumulator is folded into per-pixel
 //                  Neumaier-compensated FP32 sums.
@@ -43,16 +43,18 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 }
 
 // One list entry's box inside a tile is cut into 4 x 4 windows.  A window
-// work item is a 16-bit word: entry slot in the batch (8 bits), window row and
-// column inside the entry's box (4 bits each).
+// work item is a 32-bit word: entry slot in the batch (8 bits), window origin
+// in the tile (x, y: 6 bits each), valid width and height minus one (2 bits
+// each).
 //
-// Accumulation is in 64-bit fixed point: per batch, the scale 2^S is chosen so
-// that the batch's summed amplitude stays below 2^61, so no pixel sum can
-// overflow; LDS 64-bit integer atomics are cheap on this hardware, LDS FP32
-// atomics are not.  Integer sums are also independent of the order in which
-// the groups add.
+// Accumulation is in 32-bit fixed point: per batch, the scale 2^S is chosen so
+// that the batch's summed amplitude (sum over entries of the largest colour
+// channel) stays below 2^30, so no pixel sum can overflow; one quantum is at
+// most 2^-31 of that sum.  LDS integer atomics are cheap on this hardware,
+// LDS FP32 atomics are not.  Integer sums are also independent of the order in
+// which the groups add.
 template <int T, int BATCH>
-__global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ items,
+__global__ __launch_bounds__(kBlock, 6) void k_splat_add(const Item *__restrict__ items,
                                                       const uint32_t *__restrict__ pairs,
                                                       const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ counts,
@@ -63,10 +65,10 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
   constexpr int MAXWIN = (T / 4) * (T / 4);  // windows of a box that fills the tile
   constexpr int NLW = BATCH / 64;            // waves that load entries
   constexpr float kLog2e = 1.4426950408889634f;
-  __shared__ unsigned long long acc[3 * NP];
-  __shared__ float4 s_geo[BATCH];  // x offset, y offset, log2(e)/sigma^2, -
-  __shared__ float4 s_col[BATCH];  // premultiplied colour, packed box in .w
-  __shared__ uint16_t s_win[BATCH * MAXWIN];
+  __shared__ int acc[3 * NP];
+  __shared__ float4 s_geo[BATCH];  // x offset, y offset, log2(e)/sigma^2, box origin
+  __shared__ float4 s_col[BATCH];  // premultiplied colour
+  __shared__ uint32_t s_win[BATCH * MAXWIN];
   __shared__ int s_wsum[4];
   __shared__ float s_asum[4];
 
@@ -86,12 +88,12 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
       sum[m][c] = 0.f;
       comp[m][c] = 0.f;
     }
-  for (int i = tid; i < 3 * NP; i += kBlock) acc[i] = 0ull;
+  for (int i = tid; i < 3 * NP; i += kBlock) acc[i] = 0;
 
   for (uint32_t base = it.y; base < it.z; base += BATCH) {
     // phase 1: one list entry per loading lane -> box in the tile, constants
     const uint32_t k = base + tid;
-    int nwin = 0, nwx = 1;
+    int nwin = 0, nwx = 1, ex_li0 = 0, ex_li1 = 0, ex_lj0 = 0, ex_lj1 = 0;
     float amax = 0.f;
     if (tid < BATCH && k < it.z) {
       const uint32_t pid = pairs[k];
@@ -106,10 +108,15 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
           // (cx + u, cy + v); the integer parts subtract exactly
           const float cx = ((float)(li0 + x0) - r0.x) + (0.5f - r0.y);
           const float cy = ((float)(lj0 + y0) - r0.z) + (0.5f - r0.w);
-          s_geo[tid] = make_float4(cx, cy, kLog2e / (r1.x * r1.x), 0.f);
-          s_col[tid] = make_float4(r1.y, r1.z, r1.w, __uint_as_float(pack_box(li0, li1, lj0, lj1)));
+          s_geo[tid] = make_float4(cx, cy, kLog2e / (r1.x * r1.x),
+                                   __uint_as_float((uint32_t)li0 | ((uint32_t)lj0 << 16)));
+          s_col[tid] = make_float4(r1.y, r1.z, r1.w, 0.f);
           nwx = (li1 - li0) / 4 + 1;
           nwin = nwx * ((lj1 - lj0) / 4 + 1);
+          ex_li1 = li1;
+          ex_lj1 = lj1;
+          ex_li0 = li0;
+          ex_lj0 = lj0;
           amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
         }
       }
@@ -137,9 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
     }
     int ex = 0;
     (void)frexpf(amp_sum, &ex);  // amp_sum <= 2^ex
-    const int S = 61 - ex;       // batch sums stay below 2^61
-    for (int w = 0, o = woff + incl - nwin; w < nwin; ++w, ++o)
-      s_win[o] = (uint16_t)((tid << 8) | ((w / nwx) << 4) | (w % nwx));
+    const int S = 30 - ex;       // batch sums stay below 2^30
+    for (int w = 0, o = woff + incl - nwin; w < nwin; ++w, ++o) {
+      const int wx0 = ex_li0 + 4 * (w % nwx), wy0 = ex_lj0 + 4 * (w / nwx);
+      const int ww = min(3, ex_li1 - wx0), wh = min(3, ex_lj1 - wy0);
+      s_win[o] = (uint32_t)tid | ((uint32_t)wx0 << 8) | ((uint32_t)wy0 << 14) |
+                 ((uint32_t)ww << 20) | ((uint32_t)wh << 22);
+    }
     __syncthreads();
 
     // phase 2: 16-lane groups take windows round-robin, one pixel per lane,
@@ -149,26 +160,24 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
       int cur = -1;  // the lane's pixel in the current window; NP = outside
       for (int e = grp; e < total; e += 16) {
         const uint32_t w = s_win[e];
-        const int slot = (int)(w >> 8);
+        const int slot = (int)(w & 0xffu);
         const float4 g = s_geo[slot];
         const float4 col = s_col[slot];
-        const uint32_t bx = __float_as_uint(col.w);
-        const int li0 = bx & 0xff, li1 = (bx >> 8) & 0xff, lj0 = (bx >> 16) & 0xff,
-                  lj1 = bx >> 24;
-        const int u = 4 * (int)(w & 15u) + kx, v = 4 * (int)((w >> 4) & 15u) + ky;
-        const int px = li0 + u, py = lj0 + v;
+        const int px = (int)((w >> 8) & 63u) + kx, py = (int)((w >> 14) & 63u) + ky;
         const int pix = (px < T && py < T) ? py * T + px : NP;
         if (pix != cur) {
           if (cur >= 0 && cur < NP) {
-            atomicAdd(&acc[cur], (unsigned long long)(long long)rintf(ldexpf(a0, S)));
-            atomicAdd(&acc[NP + cur], (unsigned long long)(long long)rintf(ldexpf(a1, S)));
-            atomicAdd(&acc[2 * NP + cur], (unsigned long long)(long long)rintf(ldexpf(a2, S)));
+            atomicAdd(&acc[cur], (int)rintf(ldexpf(a0, S)));
+            atomicAdd(&acc[NP + cur], (int)rintf(ldexpf(a1, S)));
+            atomicAdd(&acc[2 * NP + cur], (int)rintf(ldexpf(a2, S)));
           }
           cur = pix;
           a0 = a1 = a2 = 0.f;
         }
-        if (px <= li1 && py <= lj1) {
-          const float dx = g.x + (float)u, dy = g.y + (float)v;
+        if (kx <= (int)((w >> 20) & 3u) && ky <= (int)((w >> 22) & 3u)) {
+          const uint32_t org = __float_as_uint(g.w);
+          const float dx = g.x + (float)(px - (int)(org & 0xffffu));
+          const float dy = g.y + (float)(py - (int)(org >> 16));
           const float q = (dx * dx + dy * dy) * g.z;
           if (q <= qmax) {
             const float e2 = exp2f(-q);
@@ -179,9 +188,9 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
         }
       }
       if (cur >= 0 && cur < NP) {
-        atomicAdd(&acc[cur], (unsigned long long)(long long)rintf(ldexpf(a0, S)));
-        atomicAdd(&acc[NP + cur], (unsigned long long)(long long)rintf(ldexpf(a1, S)));
-        atomicAdd(&acc[2 * NP + cur], (unsigned long long)(long long)rintf(ldexpf(a2, S)));
+        atomicAdd(&acc[cur], (int)rintf(ldexpf(a0, S)));
+        atomicAdd(&acc[NP + cur], (int)rintf(ldexpf(a1, S)));
+        atomicAdd(&acc[2 * NP + cur], (int)rintf(ldexpf(a2, S)));
       }
     }
     __syncthreads();
@@ -191,9 +200,9 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
       const int pix = tid + m * kBlock;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const long long v = (long long)acc[c * NP + pix];
-        acc[c * NP + pix] = 0ull;
-        neumaier(sum[m][c], comp[m][c], (float)ldexp((double)v, -S));
+        const int v = acc[c * NP + pix];
+        acc[c * NP + pix] = 0;
+        neumaier(sum[m][c], comp[m][c], ldexpf((float)v, -S));
       }
     }
   }

@@ -256,15 +256,16 @@ def test_records_match_oracle_projection(env):
         amp = 1.0 / (math.pi * sg ** 2)
         E = np.array([pr[k].E[:] for k in both])
         # single-precision colour lookup: the normalised scalar t carries an
-        # absolute error of a few 1e-8 (log10f, one multiply), which moves the
+        # absolute error of ~1e-7 (log10f, one multiply), which moves the
         # colour by up to that times the palette's steepest slope; on top of
-        # that, a few ulps of rounding in the interpolation and products
+        # that, about eight single-precision roundings in the interpolation
+        # and the products (brightness x intensity x colour x amplitude)
         want = E * amp[:, None]
         sp = ps.species[both]
         slope = np.array([np.abs(np.diff(p.astype(np.float64), axis=0)).max(0) * (len(p) - 1)
                           for p in pals])[sp]
         bi = np.array([looks[k]["brightness"] for k in range(2)])[sp] * ps.intensity[both]
-        allowed = 4e-7 * np.abs(want) + 1e-7 * (bi * amp)[:, None] * slope
+        allowed = 1e-6 * np.abs(want) + 2e-7 * (bi * amp)[:, None] * slope
         err = np.abs(rec[both, 5:8] - want)
         assert np.all(err <= allowed), f"worst excess {np.max(err / allowed):.2f}x"
         np.testing.assert_allclose(rec2[both, 1], [pr[k].zv for k in both], rtol=1e-7)
@@ -333,7 +334,9 @@ def test_paper_bin_rule_render(env):
     looks, pals = _looks(ps)
     exact = _gpu(env, ps, cam, 0, looks, pals, bin_rule=0)
     paper = _gpu(env, ps, cam, 0, looks, pals, bin_rule=1)
-    assert np.all(paper <= exact * (1 + 1e-5) + 1e-12)
+    # the splat sums in fixed point with a quantum of ~1e-7 of a batch's
+    # amplitude sum, so the comparison allows that much absolute slack
+    assert np.all(paper <= exact * (1 + 1e-5) + 1e-6 * exact.max())
     assert 0 < rel_l2(paper, exact) < 0.05
 
 
