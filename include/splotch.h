@@ -63,7 +63,11 @@ typedef struct {
   const void *intensity;     /* n x attr_dtype */
   const void *scalar;        /* colour scalar, n x attr_dtype */
   int32_t attr_dtype;        /* spl_dtype of h, intensity, scalar */
-  float h_scale;             /* world smoothing length = h_scale * h */
+  float h_scale;             /* smoothing length = h_scale * h (world units) */
+  float i_scale;             /* intensity = i_scale * intensity */
+  float s_scale;             /* colour scalar = s_scale * scalar; the scales let
+                                FP16 storage keep values in range (use 1 for
+                                FP32 and BF16) */
   const uint8_t *species;    /* n bytes, or NULL (all species 0) */
   const float *absorption;   /* n floats, SPL_SORTED only, else ignored */
 } spl_particles;
@@ -203,6 +207,16 @@ spl_status spl_autotune(spl_ctx *ctx, const spl_particles *p, const spl_camera *
  * ms, bytes: host arrays of SPL_N_STAGES doubles.  Synchronises. */
 #define SPL_N_STAGES 9
 spl_status spl_set_timing(spl_ctx *ctx, int32_t enable);
+
+/* Context options.
+ *  SPL_OPT_TIMING       0/1: stage timers (same as spl_set_timing).
+ *  SPL_OPT_GRAPHS       0/1: spl_render_batch records the launches after its
+ *                       list-size synchronisation as a HIP graph and replays it.
+ *  SPL_OPT_BATCH_BYTES  device bytes spl_render_batch may use for per-view
+ *                       workspace; views beyond it go to later launches
+ *                       (default 48 GiB). */
+enum { SPL_OPT_TIMING = 0, SPL_OPT_GRAPHS = 1, SPL_OPT_BATCH_BYTES = 2 };
+spl_status spl_set_option(spl_ctx *ctx, int32_t option, int64_t value);
 spl_status spl_get_timing(spl_ctx *ctx, double *ms, double *bytes, int64_t *frames);
 
 #ifdef __cplusplus

@@ -22,7 +22,9 @@ SPL_MAX_SPECIES = 8
 
 EXPORTS = ["spl_create", "spl_destroy", "spl_last_error", "spl_workspace_bytes",
            "spl_scalar_range", "spl_project", "spl_bin", "spl_render_records", "spl_render",
-           "spl_render_batch", "spl_autotune", "spl_set_timing", "spl_get_timing"]
+           "spl_render_batch", "spl_autotune", "spl_set_timing", "spl_get_timing",
+           "spl_set_option"]
+SPL_OPT_TIMING, SPL_OPT_GRAPHS, SPL_OPT_BATCH_BYTES = 0, 1, 2
 SPL_N_STAGES = 9
 STAGES = ["project", "count", "scan", "host_gap_items", "scatter", "sort", "large_splat",
           "splat", "finalise"]
@@ -31,7 +33,8 @@ STAGES = ["project", "count", "scan", "host_gap_items", "scatter", "sort", "larg
 class spl_particles(C.Structure):
     _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("h", C.c_void_p), ("intensity", C.c_void_p), ("scalar", C.c_void_p),
-                ("attr_dtype", C.c_int32), ("h_scale", C.c_float), ("species", C.c_void_p),
+                ("attr_dtype", C.c_int32), ("h_scale", C.c_float), ("i_scale", C.c_float),
+                ("s_scale", C.c_float), ("species", C.c_void_p),
                 ("absorption", C.c_void_p)]
 
 
@@ -101,6 +104,7 @@ def lib():
                                    C.POINTER(spl_params), C.POINTER(i32), C.POINTER(d), vp]
         L.spl_set_timing.argtypes = [vp, i32]
         L.spl_get_timing.argtypes = [vp, C.POINTER(d), C.POINTER(d), C.POINTER(i64)]
+        L.spl_set_option.argtypes = [vp, i32, i64]
         for name in EXPORTS:
             if name not in ("spl_destroy", "spl_last_error", "spl_workspace_bytes"):
                 getattr(L, name).restype = C.c_int
@@ -145,19 +149,26 @@ class DeviceParticles:
         self.device = device
         f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
         self.x, self.y, self.z = f32(ps.x), f32(ps.y), f32(ps.z)
-        h = np.asarray(ps.h, np.float64)
-        if h_scale is None:
-            h_scale = 1.0
-            if attr_dtype == "f16":
-                m = float(np.nanmax(np.abs(h))) if h.size else 1.0
-                h_scale = 2.0 ** math.floor(math.log2(m / 1024.0)) if m > 0 else 1.0
-        self.h_scale = float(h_scale)
+        def pow2_scale(a):
+            # FP16 storage: a power of two that maps the largest magnitude
+            # near 2^10, well inside the FP16 range
+            if attr_dtype != "f16":
+                return 1.0
+            a = np.asarray(a, np.float64)
+            fin = np.abs(a[np.isfinite(a)])
+            m = float(fin.max()) if fin.size else 0.0
+            return 2.0 ** math.floor(math.log2(m / 1024.0)) if m > 0 else 1.0
+
+        self.h_scale = float(h_scale) if h_scale is not None else pow2_scale(ps.h)
+        self.i_scale = pow2_scale(ps.intensity)
+        self.s_scale = pow2_scale(ps.scalar)
         tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[attr_dtype]
         self.code = {"f32": SPL_F32, "bf16": SPL_BF16, "f16": SPL_F16}[attr_dtype]
-        cast = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device).to(tdt)
-        self.h = cast(h / self.h_scale)
-        self.intensity = cast(ps.intensity)
-        self.scalar = cast(ps.scalar)
+        cast = lambda a, sc: torch.from_numpy(
+            np.ascontiguousarray(np.asarray(a, np.float64) / sc, np.float32)).to(device).to(tdt)
+        self.h = cast(ps.h, self.h_scale)
+        self.intensity = cast(ps.intensity, self.i_scale)
+        self.scalar = cast(ps.scalar, self.s_scale)
         self.species = torch.from_numpy(np.ascontiguousarray(ps.species, np.uint8)).to(device)
         self.absorption = None if ps.absorption is None else f32(ps.absorption)
         self.n = int(ps.x.shape[0])
@@ -167,6 +178,8 @@ class DeviceParticles:
         self.st.h, self.st.intensity, self.st.scalar = _ptr(self.h), _ptr(self.intensity), _ptr(self.scalar)
         self.st.attr_dtype = self.code
         self.st.h_scale = self.h_scale
+        self.st.i_scale = self.i_scale
+        self.st.s_scale = self.s_scale
         self.st.species = _ptr(self.species)
         self.st.absorption = _ptr(self.absorption)
 
@@ -306,6 +319,9 @@ class Context:
         self._check(self.L.spl_render_batch(self.h, C.byref(parts.st), nv, cams, prm_arr, out_arr,
                                             sts if stats else None, _stream()))
         return outs, ([s.as_dict() for s in sts] if stats else None)
+
+    def spl_set_option(self, option: int, value: int):
+        self._check(self.L.spl_set_option(self.h, option, int(value)))
 
     def spl_set_timing(self, enable: bool):
         self._check(self.L.spl_set_timing(self.h, int(enable)))

@@ -300,18 +300,21 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ c
                                                   const uint32_t *__restrict__ offsets, int nb,
                                                   int n_fine, int chunk, int cchunk, int minc,
                                                   const uint32_t *__restrict__ item_off,
-                                                  Item *__restrict__ items) {
+                                                  Item *__restrict__ items,
+                                                  Item *__restrict__ coarse,
+                                                  uint32_t coarse_shift, uint32_t view) {
   const int b = blockIdx.x * kBlock + threadIdx.x;
   if (b >= nb) return;
   const uint32_t c = counts[b];
   const uint32_t k = items_for(c, b, n_fine, chunk, cchunk, minc);
   if (k == 0) return;
   const uint32_t ch = (uint32_t)(b < n_fine ? chunk : cchunk);
-  const uint32_t o = offsets[b], e = o + c, base = item_off[b];
+  const uint32_t o = offsets[b], e = o + c;
+  Item *dst = (b < n_fine) ? items + item_off[b] : coarse + (item_off[b] - coarse_shift);
   for (uint32_t i = 0; i < k; ++i) {
     const uint32_t s0 = o + i * ch;
     const uint32_t s1 = min(s0 + ch, e);
-    items[base + i] = make_uint4((uint32_t)b, s0, s1, i);
+    dst[i] = make_uint4((uint32_t)b | (view << 24), s0, s1, i);
   }
 }
 
@@ -348,10 +351,12 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
 
 hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, int n_bins,
                               int n_fine, int chunk, int cchunk, int min_count,
-                              const uint32_t *item_off, Item *items, hipStream_t s) {
+                              const uint32_t *item_off, Item *items, hipStream_t s, Item *coarse,
+                              uint32_t coarse_shift, uint32_t view) {
   const int g = (n_bins + kBlock - 1) / kBlock;
+  if (!coarse) coarse = items;
   hipLaunchKernelGGL(k_items, dim3(g), dim3(kBlock), 0, s, counts, offsets, n_bins, n_fine, chunk,
-                     cchunk, min_count, item_off, items);
+                     cchunk, min_count, item_off, items, coarse, coarse_shift, view);
   return hipGetLastError();
 }
 

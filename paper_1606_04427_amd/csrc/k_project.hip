@@ -40,8 +40,8 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.n; k += stride) {
     const float x = P.x[k], y = P.y[k], z = P.z[k];
     const float h = load_attr(P.h, P.dtype, k) * P.h_scale;
-    const float I = load_attr(P.inten, P.dtype, k);
-    const float s = load_attr(P.scal, P.dtype, k);
+    const float I = load_attr(P.inten, P.dtype, k) * P.i_scale;
+    const float s = load_attr(P.scal, P.dtype, k) * P.s_scale;
     const int sp = P.species ? (int)P.species[k] : 0;
     const float a = (P.mode == SPL_SORTED) ? P.absorb[k] : 0.0f;
     float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar_range(ProjK P, int n_species,
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.n; k += stride) {
-    const float s = load_attr(P.scal, P.dtype, k);
+    const float s = load_attr(P.scal, P.dtype, k) * P.s_scale;
     const int sp = P.species ? (int)P.species[k] : 0;
     if (sp >= n_species || !finitef(s)) continue;
     double g = (double)s;

@@ -54,12 +54,10 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 // LDS FP32 atomics are not.  Integer sums are also independent of the order in
 // which the groups add.
 template <int T, int BATCH>
-__global__ __launch_bounds__(kBlock, 6) void k_splat_add(const Item *__restrict__ items,
-                                                      const uint32_t *__restrict__ pairs,
-                                                      const float4 *__restrict__ rec,
-                                                      const uint32_t *__restrict__ counts,
-                                                      int chunk, TileK tk,
-                                                      float *__restrict__ img) {
+__device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__restrict__ pairs,
+                                               const float4 *__restrict__ rec,
+                                               const uint32_t *__restrict__ counts, int chunk,
+                                               const TileK &tk, float *__restrict__ img) {
   constexpr int NP = T * T;
   constexpr int PX = NP / kBlock;            // pixels per lane in the fold
   constexpr int MAXWIN = (T / 4) * (T / 4);  // windows of a box that fills the tile
@@ -72,7 +70,6 @@ __global__ __launch_bounds__(kBlock, 6) void k_splat_add(const Item *__restrict_
   __shared__ int s_wsum[4];
   __shared__ float s_asum[4];
 
-  const Item it = items[blockIdx.x];
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
@@ -224,21 +221,54 @@ __global__ __launch_bounds__(kBlock, 6) void k_splat_add(const Item *__restrict_
   }
 }
 
+template <int T, int BATCH>
+__global__ __launch_bounds__(kBlock, 6) void k_splat_add(const Item *__restrict__ items,
+                                                      const uint32_t *__restrict__ pairs,
+                                                      const float4 *__restrict__ rec,
+                                                      const uint32_t *__restrict__ counts,
+                                                      int chunk, TileK tk,
+                                                      float *__restrict__ img) {
+  splat_add_item<T, BATCH>(items[blockIdx.x], pairs, rec, counts, chunk, tk, img);
+}
+
+// Persistent form for many views: workgroups take (view, tile chunk) items
+// from a device counter until the queue is empty; every workgroup exits.
+template <int T, int BATCH>
+__global__ __launch_bounds__(kBlock, 6) void k_splat_add_views(const ViewK *__restrict__ views,
+                                                            const Item *__restrict__ items,
+                                                            const uint32_t *__restrict__ n_items,
+                                                            uint32_t *__restrict__ next,
+                                                            int chunk) {
+  __shared__ uint32_t s_idx;
+  const uint32_t n = *n_items;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(next, 1u);
+    __syncthreads();
+    const uint32_t idx = s_idx;
+    __syncthreads();
+    if (idx >= n) break;
+    Item it = items[idx];
+    const ViewK &v = views[it.x >> 24];
+    it.x &= 0xffffffu;
+    splat_add_item<T, BATCH>(it, v.pairs, v.rec, v.counts, chunk, v.tk, v.img);
+    __syncthreads();
+  }
+}
+
 constexpr int kLargeTile = 64;
 constexpr int kLargeThreads = 512;
 constexpr int kLargePx = kLargeTile * kLargeTile / kLargeThreads;  // 8 rows per lane
 
-__global__ __launch_bounds__(kLargeThreads) void k_splat_large(
-    const Item *__restrict__ items, const uint32_t *__restrict__ pairs,
-    const float4 *__restrict__ rec, const uint32_t *__restrict__ counts, int cchunk, TileK tk,
-    float *__restrict__ img) {
+__device__ __forceinline__ void splat_large_item(const Item it, const uint32_t *__restrict__ pairs,
+                                                 const float4 *__restrict__ rec,
+                                                 const uint32_t *__restrict__ counts, int cchunk,
+                                                 const TileK &tk, float *__restrict__ img) {
   __shared__ float g_ox[kLargeThreads], g_fx[kLargeThreads], g_oy[kLargeThreads],
       g_fy[kLargeThreads], g_is2[kLargeThreads];
   __shared__ float g_a0[kLargeThreads], g_a1[kLargeThreads], g_a2[kLargeThreads];
   __shared__ uint32_t g_box[kLargeThreads];
   __shared__ int g_count;
 
-  const Item it = items[blockIdx.x];
   const int cb = (int)it.x - tk.n_tiles;
   const int x0 = (cb % tk.nctx) * kLargeTile, y0 = (cb / tk.nctx) * kLargeTile;
   const bool multi = counts[it.x] > (uint32_t)cchunk;
@@ -332,6 +362,32 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large(
           o[c] += v;
       }
     }
+  }
+}
+
+__global__ __launch_bounds__(kLargeThreads) void k_splat_large(
+    const Item *__restrict__ items, const uint32_t *__restrict__ pairs,
+    const float4 *__restrict__ rec, const uint32_t *__restrict__ counts, int cchunk, TileK tk,
+    float *__restrict__ img) {
+  splat_large_item(items[blockIdx.x], pairs, rec, counts, cchunk, tk, img);
+}
+
+__global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
+    const ViewK *__restrict__ views, const Item *__restrict__ items,
+    const uint32_t *__restrict__ n_items, uint32_t *__restrict__ next, int cchunk) {
+  __shared__ uint32_t s_idx;
+  const uint32_t n = *n_items;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(next, 1u);
+    __syncthreads();
+    const uint32_t idx = s_idx;
+    __syncthreads();
+    if (idx >= n) break;
+    Item it = items[idx];
+    const ViewK &v = views[it.x >> 24];
+    it.x &= 0xffffffu;
+    splat_large_item(it, v.pairs, v.rec, v.counts, cchunk, v.tk, v.img);
+    __syncthreads();
   }
 }
 
@@ -512,6 +568,22 @@ hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pa
   if (tk.ctile != kLargeTile) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_splat_large, dim3(n_items), dim3(kLargeThreads), 0, s, items, pairs,
                      reinterpret_cast<const float4 *>(rec), counts, cchunk, tk, img);
+  return hipGetLastError();
+}
+
+hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
+                              uint32_t *next_fine, const Item *large, const uint32_t *n_large,
+                              uint32_t *next_large, int chunk, int cchunk, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_splat_large_views, dim3(grid), dim3(kLargeThreads), 0, s, views, large,
+                     n_large, next_large, cchunk);
+  if (tile == 16)
+    hipLaunchKernelGGL((k_splat_add_views<16, 256>), dim3(grid), dim3(kBlock), 0, s, views, fine,
+                       n_fine, next_fine, chunk);
+  else if (tile == 32)
+    hipLaunchKernelGGL((k_splat_add_views<32, 128>), dim3(grid), dim3(kBlock), 0, s, views, fine,
+                       n_fine, next_fine, chunk);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -62,6 +62,19 @@ struct spl_ctx {
   double acc_ms[SPL_N_STAGES] = {0};
   double acc_bytes[SPL_N_STAGES] = {0};
   int64_t acc_frames = 0;
+  // many-view batches
+  DevBuf b_rec, b_span, b_counts, b_offsets, b_cursor, b_itemoff, b_totals, b_pairs, b_itf,
+      b_itc, b_views, b_ctr, b_fin, b_stats;
+  Totals *h_btot = nullptr;
+  ViewK *h_views = nullptr;
+  uint32_t *h_ctr = nullptr;
+  double *h_bstats = nullptr;
+  int h_cap = 0;  // views the pinned host arrays hold
+  bool graphs = false;
+  hipStream_t cap_stream = nullptr;   // capture stream for batch graphs
+  hipGraphExec_t gexec = nullptr;     // last instantiated batch graph
+  int64_t budget = (int64_t)48 << 30;
+  int n_cu = 256;
 };
 
 namespace {
@@ -198,8 +211,9 @@ spl_status check_particles(spl_ctx *c, const spl_particles *p, int mode) {
     return fail(c, SPL_EINVAL, "a required particle array is NULL");
   if (p->attr_dtype < SPL_F32 || p->attr_dtype > SPL_F16)
     return fail(c, SPL_EINVAL, "unknown attr_dtype %d", p->attr_dtype);
-  if (!(p->h_scale > 0.0f) || !std::isfinite(p->h_scale))
-    return fail(c, SPL_EINVAL, "h_scale must be finite and > 0");
+  if (!(p->h_scale > 0.0f) || !std::isfinite(p->h_scale) || !(p->i_scale > 0.0f) ||
+      !std::isfinite(p->i_scale) || !(p->s_scale > 0.0f) || !std::isfinite(p->s_scale))
+    return fail(c, SPL_EINVAL, "h_scale, i_scale and s_scale must be finite and > 0");
   if (mode == SPL_SORTED && !p->absorption)
     return fail(c, SPL_EINVAL, "sorted mode needs absorption");
   return SPL_OK;
@@ -233,6 +247,8 @@ void fill_proj(ProjK &pk, const spl_particles *p, const spl_params *prm) {
   pk.scal = p->scalar;
   pk.dtype = p->attr_dtype;
   pk.h_scale = p->h_scale;
+  pk.i_scale = p->i_scale;
+  pk.s_scale = p->s_scale;
   pk.species = p->species;
   pk.absorb = p->absorption;
   pk.n = p->n;
@@ -513,6 +529,244 @@ spl_status render_one(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
   return render_timed(c, f, tf, st, s);
 }
 
+
+constexpr int kMaxBatchViews = 255;
+
+spl_status ensure_host(spl_ctx *c, int views) {
+  if (c->h_cap >= views) return SPL_OK;
+  if (c->h_btot) hipHostFree(c->h_btot);
+  if (c->h_views) hipHostFree(c->h_views);
+  if (c->h_ctr) hipHostFree(c->h_ctr);
+  if (c->h_bstats) hipHostFree(c->h_bstats);
+  c->h_btot = nullptr;
+  c->h_views = nullptr;
+  c->h_ctr = nullptr;
+  c->h_bstats = nullptr;
+  c->h_cap = 0;
+  if (hipHostMalloc((void **)&c->h_btot, sizeof(Totals) * views, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_views, sizeof(ViewK) * views, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_ctr, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_bstats, 8 * sizeof(double) * views, hipHostMallocDefault) != hipSuccess)
+    return fail(c, SPL_ENOMEM, "pinned host allocation failed");
+  c->h_cap = views;
+  return SPL_OK;
+}
+
+// One sub-batch of additive views [0, nv): every view's projection, counts
+// and scan are launched back to back, one host synchronisation reads all list
+// sizes, then the lists of all views are built and splatted by one persistent
+// launch (plus one for large particles) and every image is finalised.
+spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK *pk,
+                        const TileK *tk, const spl_params *const *prm, float *const *outs,
+                        spl_stats *const *st, hipStream_t s) {
+  const int64_t n = p->n;
+  int bins = 0;
+  for (int v = 0; v < nv; ++v) bins = std::max(bins, tk[v].n_tiles + tk[v].n_ctiles);
+  const size_t bstride = (size_t)bins + 1;
+  TRY(ensure_host(c, nv));
+  TRY(ensure(c, c->b_rec, (size_t)nv * n * 32));
+  TRY(ensure(c, c->b_span, (size_t)nv * n * 8));
+  TRY(ensure(c, c->b_counts, nv * bstride * 4));
+  TRY(ensure(c, c->b_offsets, nv * bstride * 4));
+  TRY(ensure(c, c->b_cursor, nv * bstride * 4));
+  TRY(ensure(c, c->b_itemoff, (size_t)nv * 3 * bstride * 4));
+  TRY(ensure(c, c->b_totals, (size_t)nv * sizeof(Totals)));
+  TRY(ensure(c, c->b_views, (size_t)nv * sizeof(ViewK)));
+  TRY(ensure(c, c->b_ctr, 4 * sizeof(uint32_t)));
+  TRY(ensure(c, c->b_fin, (size_t)nv * kFinBlocks * 6 * 8));
+  TRY(ensure(c, c->b_stats, (size_t)nv * 8 * 8));
+  float *rec = (float *)c->b_rec.p;
+  uint2 *span = (uint2 *)c->b_span.p;
+  uint32_t *counts = (uint32_t *)c->b_counts.p, *offsets = (uint32_t *)c->b_offsets.p;
+  uint32_t *cursor = (uint32_t *)c->b_cursor.p, *itemoff = (uint32_t *)c->b_itemoff.p;
+  Totals *tot = (Totals *)c->b_totals.p;
+  const int chunk[3] = {kChunkSplat, 0, 0}, cchunk[3] = {kChunkLarge, 0, 0}, minc[3] = {1, 1, 1};
+  HIPTRY(c, launch_fill_u32((uint32_t *)tot, 0u, (int64_t)nv * sizeof(Totals) / 4, s));
+  for (int v = 0; v < nv; ++v) {
+    const int nb = tk[v].n_tiles + tk[v].n_ctiles;
+    float *rv = rec + (size_t)v * n * 8;
+    uint2 *sv = span + (size_t)v * n;
+    HIPTRY(c, launch_fill_u32(counts + v * bstride, 0u, nb, s));
+    HIPTRY(c, launch_project(pk[v], tk[v], rv, nullptr, sv, 0, tot + v, s));
+    HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, s));
+    HIPTRY(c, launch_scan(counts + v * bstride, nb, tk[v].n_tiles, offsets + v * bstride,
+                          cursor + v * bstride, chunk, cchunk, minc, itemoff + v * 3 * bstride,
+                          tot + v, s));
+  }
+  HIPTRY(c, hipMemcpyAsync(c->h_btot, tot, sizeof(Totals) * nv, hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  std::vector<uint64_t> pb(nv), fb(nv), cb(nv);
+  uint64_t pairs_total = 0, fine_total = 0, coarse_total = 0;
+  for (int v = 0; v < nv; ++v) {
+    const Totals &T = c->h_btot[v];
+    pb[v] = pairs_total;
+    fb[v] = fine_total;
+    cb[v] = coarse_total;
+    pairs_total += T.n_pairs;
+    fine_total += T.n_fine_items[0];
+    coarse_total += T.n_items[0] - T.n_fine_items[0];
+  }
+  if (pairs_total >= 0xffffffffull || fine_total > 0x7fffffffull || coarse_total > 0x7fffffffull)
+    return fail(c, SPL_EUNSUPPORTED, "batch lists too long (%llu entries)",
+                (unsigned long long)pairs_total);
+  TRY(ensure(c, c->b_pairs, pairs_total * 4));
+  TRY(ensure(c, c->b_itf, fine_total * sizeof(Item)));
+  TRY(ensure(c, c->b_itc, coarse_total * sizeof(Item)));
+  uint32_t *pairs = (uint32_t *)c->b_pairs.p;
+  Item *itf = (Item *)c->b_itf.p, *itc = (Item *)c->b_itc.p;
+  for (int v = 0; v < nv; ++v) {
+    ViewK &vk = c->h_views[v];
+    vk.tk = tk[v];
+    vk.counts = counts + v * bstride;
+    vk.pairs = pairs + pb[v];
+    vk.rec = reinterpret_cast<const float4 *>(rec + (size_t)v * n * 8);
+    vk.img = outs[v];
+  }
+  c->h_ctr[0] = (uint32_t)fine_total;
+  c->h_ctr[1] = (uint32_t)coarse_total;
+  // everything after the synchronisation depends only on the list sizes just
+  // read; it is enqueued as one unit, directly or as a captured graph
+  auto post = [&](hipStream_t q) -> spl_status {
+    for (int v = 0; v < nv; ++v) {
+      const Totals &T = c->h_btot[v];
+      const int nb = tk[v].n_tiles + tk[v].n_ctiles;
+      if (T.n_items[0])
+        HIPTRY(c, launch_build_items(counts + v * bstride, offsets + v * bstride, nb,
+                                     tk[v].n_tiles, kChunkSplat, kChunkLarge, 1,
+                                     itemoff + v * 3 * bstride, itf + fb[v], q, itc + cb[v],
+                                     (uint32_t)T.n_fine_items[0], (uint32_t)v));
+      HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n, tk[v],
+                               cursor + v * bstride, pairs + pb[v], nullptr, q));
+      HIPTRY(c, launch_fill_f32(outs[v], 0.0f, 3 * (int64_t)tk[v].W * tk[v].H, q));
+    }
+    HIPTRY(c, hipMemcpyAsync(c->b_views.p, c->h_views, sizeof(ViewK) * nv, hipMemcpyHostToDevice,
+                             q));
+    HIPTRY(c, hipMemcpyAsync(c->b_ctr.p, c->h_ctr, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, q));
+    uint32_t *ctr = (uint32_t *)c->b_ctr.p;
+    HIPTRY(c, launch_fill_u32(ctr + 2, 0u, 2, q));
+    HIPTRY(c, launch_splat_views(tk[0].tile, (const ViewK *)c->b_views.p, itf, ctr, ctr + 2, itc,
+                                 ctr + 1, ctr + 3, kChunkSplat, kChunkLarge, 4 * c->n_cu, q));
+    double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
+    for (int v = 0; v < nv; ++v) {
+      const int64_t npx = (int64_t)tk[v].W * tk[v].H;
+      const int fbk = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
+      HIPTRY(c, launch_finalise(outs[v], npx, prm[v]->mode == SPL_ADD_AEQE,
+                                fin + (size_t)v * kFinBlocks * 6, fbk, q));
+      HIPTRY(c, launch_reduce_stats(fin + (size_t)v * kFinBlocks * 6, fbk, stats + 8 * v, q));
+      if (prm[v]->normalise) HIPTRY(c, launch_normalise(outs[v], npx, stats + 8 * v, q));
+    }
+    return SPL_OK;
+  };
+  if (!c->graphs) {
+    TRY(post(s));
+  } else {
+    // capture on the context's own stream (the null stream cannot be
+    // captured), then replay on the caller's stream; the executable graph is
+    // kept and updated in place while the launch topology stays the same
+    if (!c->cap_stream) HIPTRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPTRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const spl_status cs = post(c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
+    if (cs != SPL_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return cs;
+    }
+    if (ce != hipSuccess) return fail(c, SPL_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+    hipError_t e = hipSuccess;
+    if (c->gexec) {
+      hipGraphNode_t bad = nullptr;
+      hipGraphExecUpdateResult res;
+      if (hipGraphExecUpdate(c->gexec, graph, &bad, &res) != hipSuccess) {
+        (void)hipGetLastError();
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+      }
+    }
+    if (!c->gexec) e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipGraphLaunch(c->gexec, s);
+    if (e != hipSuccess) return fail(c, SPL_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
+  }
+  double *stats = (double *)c->b_stats.p;
+  bool any_stats = false;
+  for (int v = 0; v < nv; ++v) any_stats = any_stats || st[v];
+  if (any_stats) {
+    HIPTRY(c, hipMemcpyAsync(c->h_bstats, stats, 8 * sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    for (int v = 0; v < nv; ++v) {
+      if (!st[v]) continue;
+      const Totals &T = c->h_btot[v];
+      st[v]->n_active = (int64_t)T.n_active;
+      st[v]->n_large = (int64_t)T.n_large;
+      st[v]->n_pairs = (int64_t)T.n_fine_pairs;
+      st[v]->n_large_pairs = (int64_t)(T.n_pairs - T.n_fine_pairs);
+      st[v]->n_items = (int64_t)T.n_items[0];
+      for (int q = 0; q < 3; ++q) {
+        st[v]->flux[q] = c->h_bstats[8 * v + q];
+        st[v]->max[q] = c->h_bstats[8 * v + 3 + q];
+      }
+      st[v]->tile = tk[v].tile;
+      st[v]->large_cut = std::isfinite(tk[v].large_cut) ? (double)tk[v].large_cut : -1.0;
+    }
+  }
+  return SPL_OK;
+}
+
+spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_camera *cams,
+                        const spl_params *prms, float *const *outs, spl_stats *st,
+                        hipStream_t s) {
+  TRY(check_particles(c, p, SPL_ADD_RAW));
+  std::vector<ProjK> pk;
+  std::vector<TileK> tk;
+  std::vector<const spl_params *> pv;
+  std::vector<float *> ov;
+  std::vector<spl_stats *> sv;
+  int tile0 = 0;
+  // every view is validated before any work is enqueued
+  bool any_sorted = false;
+  for (int v = 0; v < nv; ++v) {
+    ProjK k;
+    TRY(check_params(c, &prms[v], true));
+    TRY(camera_frame(c, &cams[v], k));
+    if (!outs[v]) return fail(c, SPL_EINVAL, "output image %d is NULL", v);
+    any_sorted = any_sorted || prms[v].mode == SPL_SORTED;
+  }
+  if (any_sorted) TRY(check_particles(c, p, SPL_SORTED));
+  for (int v = 0; v < nv; ++v) {
+    // views that need a depth-sorted composite take the single-view path
+    if (prms[v].mode == SPL_SORTED) {
+      TRY(render_one(c, p, &cams[v], &prms[v], outs[v], st ? &st[v] : nullptr, s));
+      continue;
+    }
+    ProjK k;
+    camera_frame(c, &cams[v], k);
+    fill_proj(k, p, &prms[v]);
+    int tile;
+    double cut;
+    choose(c, p->n, cams[v].width, cams[v].height, &prms[v], tile, cut);
+    if (!tile0) tile0 = tile;  // one tile size per persistent launch
+    TileK t;
+    fill_tiles(t, cams[v].width, cams[v].height, tile0, prms[v].nu, cut, prms[v].bin_rule);
+    pk.push_back(k);
+    tk.push_back(t);
+    pv.push_back(&prms[v]);
+    ov.push_back(outs[v]);
+    sv.push_back(st ? &st[v] : nullptr);
+  }
+  const int na = (int)pk.size();
+  if (na == 0) return SPL_OK;
+  // views per launch: what the memory budget allows (records, spans and about
+  // two list entries per particle, per view)
+  const int64_t per_view = p->n * (32 + 8 + 8) + ((int64_t)4 << 20);
+  int per = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBatchViews, c->budget / std::max<int64_t>(per_view, 1)));
+  for (int v0 = 0; v0 < na; v0 += per) {
+    const int m = std::min(per, na - v0);
+    TRY(render_views(c, p, m, &pk[v0], &tk[v0], &pv[v0], &ov[v0], &sv[v0], s));
+  }
+  return SPL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -530,6 +784,9 @@ spl_status spl_create(int device, spl_ctx **out) {
   spl_ctx *c = new (std::nothrow) spl_ctx();
   if (!c) return SPL_ENOMEM;
   c->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    c->n_cu = ncu;
   if (hipHostMalloc((void **)&c->h_tot, sizeof(Totals), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     if (c->h_tot) hipHostFree(c->h_tot);
@@ -547,7 +804,9 @@ void spl_destroy(spl_ctx *c) {
   DevBuf *bufs[] = {&c->rec, &c->rec2, &c->span, &c->counts, &c->offsets, &c->cursor,
                     &c->item_off, &c->items[0], &c->items[1], &c->items[2], &c->pairs,
                     &c->keysA, &c->keysB, &c->partial, &c->fin, &c->stats, &c->totals,
-                    &c->minmax};
+                    &c->minmax, &c->b_rec, &c->b_span, &c->b_counts, &c->b_offsets,
+                    &c->b_cursor, &c->b_itemoff, &c->b_totals, &c->b_pairs, &c->b_itf,
+                    &c->b_itc, &c->b_views, &c->b_ctr, &c->b_fin, &c->b_stats};
   for (DevBuf *b : bufs)
     if (b->p) hipFree(b->p);
   for (TimedFrame &tf : c->pending)
@@ -555,6 +814,12 @@ void spl_destroy(spl_ctx *c) {
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   if (c->h_tot) hipHostFree(c->h_tot);
   if (c->h_stats) hipHostFree(c->h_stats);
+  if (c->h_btot) hipHostFree(c->h_btot);
+  if (c->h_views) hipHostFree(c->h_views);
+  if (c->h_ctr) hipHostFree(c->h_ctr);
+  if (c->h_bstats) hipHostFree(c->h_bstats);
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -583,6 +848,7 @@ spl_status spl_scalar_range(spl_ctx *c, const spl_particles *p, int32_t n_specie
   pk.scal = p->scalar;
   pk.species = p->species;
   pk.dtype = p->attr_dtype;
+  pk.s_scale = (p->s_scale > 0.0f && std::isfinite(p->s_scale)) ? p->s_scale : 1.0f;
   pk.n = p->n;
   HIPTRY(c, launch_scalar_range(pk, n_species, log10_scalar ? 1 : 0, (double *)c->minmax.p, s));
   double h[2 * SPL_MAX_SPECIES];
@@ -758,9 +1024,26 @@ spl_status spl_render_batch(spl_ctx *c, const spl_particles *p, int32_t n_views,
   if (n_views < 0 || (n_views > 0 && (!cams || !prms || !outs)))
     return fail(c, SPL_EINVAL, "bad view arrays");
   HIPTRY(c, hipSetDevice(c->device));
-  for (int v = 0; v < n_views; ++v)
-    TRY(render_one(c, p, &cams[v], &prms[v], outs[v], st ? &st[v] : nullptr, (hipStream_t)stream));
-  return SPL_OK;
+  if (n_views == 0) return SPL_OK;
+  return render_batch(c, p, n_views, cams, prms, outs, st, (hipStream_t)stream);
+}
+
+spl_status spl_set_option(spl_ctx *c, int32_t option, int64_t value) {
+  if (!c) return SPL_EINVAL;
+  switch (option) {
+    case SPL_OPT_TIMING:
+      c->timing = value != 0;
+      return SPL_OK;
+    case SPL_OPT_GRAPHS:
+      c->graphs = value != 0;
+      return SPL_OK;
+    case SPL_OPT_BATCH_BYTES:
+      if (value <= 0) return fail(c, SPL_EINVAL, "batch budget must be > 0");
+      c->budget = value;
+      return SPL_OK;
+    default:
+      return fail(c, SPL_EINVAL, "unknown option %d", option);
+  }
 }
 
 spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *cam,

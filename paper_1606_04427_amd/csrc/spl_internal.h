@@ -50,10 +50,19 @@ struct ProjK {
   const float *x, *y, *z;
   const void *h, *inten, *scal;
   int dtype;
-  float h_scale;
+  float h_scale, i_scale, s_scale;
   const uint8_t *species;
   const float *absorb;
   int64_t n;
+};
+
+// One view of a batch, as the persistent splat kernels read it.
+struct ViewK {
+  TileK tk;
+  const uint32_t *counts;
+  const uint32_t *pairs;
+  const float4 *rec;
+  float *img;
 };
 
 // Device totals written by the binning stage and read back by the host.
@@ -177,9 +186,14 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
                        uint32_t *cursor, const int chunk[3], const int cchunk[3],
                        const int min_count[3], uint32_t *item_off /* 3 x (n_bins+1) */,
                        Totals *tot, hipStream_t s);
+// Items of fine bins go to items[item_off[b]], items of large bins to
+// coarse[item_off[b] - coarse_shift]; the view index is stored in the top 8
+// bits of the bin field.
 hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, int n_bins,
                               int n_fine, int chunk, int cchunk, int min_count,
-                              const uint32_t *item_off, Item *items, hipStream_t s);
+                              const uint32_t *item_off, Item *items, hipStream_t s,
+                              Item *coarse = nullptr, uint32_t coarse_shift = 0,
+                              uint32_t view = 0);
 hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,
                           const TileK &tk, uint32_t *cursor, uint32_t *pairs,
                           unsigned long long *keys, hipStream_t s);
@@ -200,6 +214,11 @@ hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint
 hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pairs,
                               const float *rec, const uint32_t *counts, int cchunk,
                               const TileK &tk, float *img, hipStream_t s);
+// Persistent splat over the (view, tile chunk) items of many views: large
+// items first, then fine items; n_* and next_* are device counters.
+hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
+                              uint32_t *next_fine, const Item *large, const uint32_t *n_large,
+                              uint32_t *next_large, int chunk, int cchunk, int grid, hipStream_t s);
 hipError_t launch_composite(int tile, const Item *items, int n_items,
                             const unsigned long long *keys, const float *rec,
                             const float *rec2, const uint32_t *counts, int chunk,

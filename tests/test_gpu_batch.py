@@ -1,0 +1,105 @@
+"""Many views in one call (spl_render_batch): one list-size synchronisation for
+the whole batch and one persistent splat launch over every view's work items.
+Each image must equal the single-view render of the same view (both are
+sums of the same FP32 contributions; the fixed-point batch sums are exact, so
+only the order of the compensated folds can differ) and the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_1606_04427_amd import synth
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(oracle):
+    import torch
+
+    from paper_1606_04427_amd import binding as B
+
+    assert torch.cuda.is_available()
+    ctx = B.Context(0)
+    yield B, ctx, oracle
+    ctx.close()
+
+
+def _setup(B, n=120_000, seed=51):
+    ps = synth.soneira_peebles(n, seed=seed, absorption=True)
+    looks, pals = [], []
+    for k in range(2):
+        s = ps.scalar[ps.species == k]
+        looks.append(dict(log10=1, brightness=0.03 * (1 + k), lo=float(np.log10(s.min())),
+                          hi=float(np.log10(s.max()))))
+        pals.append(synth.palette(k))
+    return ps, looks, pals
+
+
+def _poses():
+    sizes = [(256, 256), (512, 384), (200, 130), (384, 512), (256, 256), (96, 160)]
+    out = []
+    for k, (w, h) in enumerate(sizes):
+        out += synth.random_poses(1, seed=300 + k, width=w, height=h)
+    return out
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_batch_equals_single_view_and_oracle(env, graphs):
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals = _setup(B)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    poses = _poses()
+    modes = [1, 0, 1, 2, 1, 0]
+    prms = [B.make_params(m, P, looks, tile=16, large_cut=16.0) for m in modes]
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, graphs)
+    outs, sts = ctx.spl_render_batch(parts, poses, prms)
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+    torch.cuda.synchronize()
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    RP = R.Particles(ps)
+    for pose, prm, m, o, st in zip(poses, prms, modes, outs, sts):
+        single, st1 = ctx.spl_render(parts, pose, prm)
+        torch.cuda.synchronize()
+        got = o.cpu().numpy().astype(np.float64)
+        assert rel_l2(got, single.cpu().numpy()) < 1e-6
+        assert st["n_active"] == st1["n_active"] and st["n_pairs"] == st1["n_pairs"]
+        ref = R.render(RP, pose, R.params(m, L))
+        if np.abs(ref).max() > 0:
+            assert rel_l2(got, ref) < 1e-5
+
+
+def test_batch_budget_splits_launches(env):
+    """A budget that holds one view forces one persistent launch per view; the
+    images must not change."""
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals = _setup(B, n=50_000, seed=52)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    poses = _poses()[:4]
+    prms = [B.make_params(1, P, looks, tile=16) for _ in poses]
+    a, _ = ctx.spl_render_batch(parts, poses, prms, stats=False)
+    torch.cuda.synchronize()
+    a = [x.cpu().numpy() for x in a]
+    ctx.spl_set_option(B.SPL_OPT_BATCH_BYTES, 1)
+    b, _ = ctx.spl_render_batch(parts, poses, prms, stats=False)
+    ctx.spl_set_option(B.SPL_OPT_BATCH_BYTES, 48 << 30)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert rel_l2(y.cpu().numpy(), x) < 1e-6
+
+
+def test_batch_rejects_bad_view(env):
+    B, ctx, _ = env
+    ps, looks, pals = _setup(B, n=1000, seed=53)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    poses = _poses()[:2]
+    poses[1] = synth.Pose((0, 0, 1), (0, 0, 1), (0, 1, 0), 60, 0.0, 8, 8)
+    prms = [B.make_params(1, P, looks) for _ in poses]
+    with pytest.raises(B.SplotchError):
+        ctx.spl_render_batch(parts, poses, prms)

@@ -363,3 +363,26 @@ def test_invalid_arguments_are_rejected(env):
     prm.mode = 2  # sorted without absorption
     with pytest.raises(B.SplotchError):
         ctx.spl_render(parts, cam, prm)
+
+
+# ---------------------------------------------------------------- reduced precision
+
+@pytest.mark.parametrize("dtype,tol", [("bf16", 2e-3), ("f16", 5e-4)])
+def test_reduced_precision_attributes(env, dtype, tol):
+    """Smoothing length, intensity and colour scalar stored in BF16 / FP16
+    (positions stay FP32), accumulation in FP32: image error against the FP64
+    oracle run on the original FP32 attributes.  BF16 keeps 8 mantissa bits
+    (relative rounding 2^-9), FP16 11 bits (2^-12); per particle the error is
+    a few times that, and it averages down over overlapping particles."""
+    ps, poses = _sp_case(200_000, W=384, H=320)
+    looks, pals = _looks(ps, n_species=2, brightness=0.02)
+    errs = []
+    for pose in poses[:3]:
+        got = _gpu(env, ps, pose, 1, looks, pals, attr_dtype=dtype)
+        ref = _ref(env, ps, pose, 1, looks, pals)
+        if np.abs(ref).max() == 0:
+            continue
+        errs.append(rel_l2(got, ref))
+        full = _gpu(env, ps, pose, 1, looks, pals)
+        assert rel_l2(full, ref) <= P2_TOL
+    assert errs and max(errs) <= tol, f"{dtype}: rel-L2 {errs}"
