@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Splotch frame throughput on one MI355X (gfx950).
 
-Workload: 10M particles in a Soneira-Peebles hierarchy (4 levels, 8
-sub-clusters per level), two species with their own palettes, smoothing
-length h = 1.3 n^(-1/3) from the local density (projected kernel radii from
-sub-pixel to ~300 px over the poses), 1024 x 1024 images, 8 random camera
-poses (some inside the cube), additive absorption-equals-emission transfer,
-FP32 attributes.  One step renders all 8 poses; particles/s counts every input
-particle of every pose.  Inputs are resident in device memory before timing.
+Default workload (additive): 10M particles in a Soneira-Peebles hierarchy (4
+levels, 8 sub-clusters per level), two species with their own palettes,
+smoothing length h = 1.3 n^(-1/3) from the local density (projected kernel
+radii from sub-pixel to hundreds of px over the poses), 1024 x 1024 images, 8
+random camera poses (some inside the cube), additive absorption-equals-emission
+transfer, FP32 attributes.  One step renders all 8 poses; particles/s counts
+every input particle of every pose.  Inputs are resident in device memory
+before timing.
+
+Other workloads (--workload): `sorted` (the same 10M set with absorption,
+depth-sorted transfer, one 2048 x 2048 view), `batched` (200M particles with
+BF16 or FP16 attributes, 64 views of 4096^2 and 1024^2 in batched launches),
+`serving` (100M resident particles, a Poisson stream of mixed-size views).
 
 Prints one JSON line.  `roofline` is for the dominant kernel, from HIP events
 recorded inside the library around each stage during the timed steps;
@@ -28,28 +34,43 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# FP32 operations per Gaussian pixel update: two differences, squared
+# distance (mul + fma), scale, exponential, three colour products and three
+# accumulations
+FLOPS_PER_UPDATE = 13.0
 METRIC = "particles/s + HBM GB/s per frame; p50/p99 latency on mixed-view stream"
+KERNEL_OF_STAGE = {"splat": "k_splat_add", "project": "k_project", "large_splat": "k_splat_large",
+                   "scatter": "k_scatter", "count": "k_count", "finalise": "k_finalise",
+                   "sort": "k_sort_chunks/k_merge_pass", "scan": "k_scan"}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def workload(n, seed=1001, pose_seed=2001, width=1024, height=1024, n_poses=8):
+def looks_for(ps, scale=1.0, palette_offset=0):
     from paper_1606_04427_amd import synth
 
-    ps = synth.soneira_peebles(n, seed=seed)
-    poses = synth.random_poses(n_poses, seed=pose_seed, width=width, height=height)
     looks, pals = [], []
     for k in range(2):
         s = ps.scalar[ps.species == k]
-        looks.append(dict(log10=1, brightness=0.02 * (1 + k), lo=float(np.log10(s.min())),
+        looks.append(dict(log10=1, brightness=0.02 * (1 + k) * scale, lo=float(np.log10(s.min())),
                           hi=float(np.log10(s.max()))))
-        pals.append(synth.palette(k))
+        pals.append(synth.palette((k + palette_offset) % 2))
+    return looks, pals
+
+
+def workload(n, seed=1001, pose_seed=2001, width=1024, height=1024, n_poses=8, absorption=False):
+    from paper_1606_04427_amd import synth
+
+    ps = synth.soneira_peebles(n, seed=seed, absorption=absorption)
+    poses = synth.random_poses(n_poses, seed=pose_seed, width=width, height=height)
+    looks, pals = looks_for(ps)
     return ps, poses, looks, pals
 
 
-def cpu_baseline(ps, poses, looks, pals, sample):
+def cpu_baseline(ps, poses, looks, pals, sample, mode):
     from oracle import splref as R
 
     R.build(force=False)
@@ -57,7 +78,7 @@ def cpu_baseline(ps, poses, looks, pals, sample):
     idx = np.sort(rng.choice(ps.n, sample, replace=False))
     sub = ps.subset(idx)
     L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
-    prm = R.params(R.ADD_AEQE, L)
+    prm = R.params(mode, L)
     P = R.Particles(sub)
     t0 = time.perf_counter()
     for pose in poses:
@@ -65,30 +86,89 @@ def cpu_baseline(ps, poses, looks, pals, sample):
     dt = time.perf_counter() - t0
     return {"value": sample * len(poses) / dt, "unit": "particles/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"random {sample}-particle subsample of the same set, all {len(poses)} poses, "
+            "sample": f"random {sample}-particle subsample of the same set, {len(poses)} pose(s), "
                       f"FP64 single-threaded C oracle, {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build renders on exactly one GPU; --gpus must be 1", file=sys.stderr)
-        sys.exit(2)
+def box_pixels(rec, width, height, cut):
+    """Pixels inside the clipped integer box of every small particle (R <= cut
+    or no cut): the Gaussian updates an exact splat must evaluate."""
+    r = rec.reshape(-1, 8).astype(np.float64)
+    sig = r[:, 4]
+    R = 3.0 * sig
+    X = r[:, 0] + r[:, 1]
+    Y = r[:, 2] + r[:, 3]
+    small = sig > 0
+    if cut > 0:
+        small &= R <= cut
+    i0 = np.clip(np.ceil(X - R - 0.5), 0, width - 1)
+    i1 = np.clip(np.floor(X + R - 0.5), 0, width - 1)
+    j0 = np.clip(np.ceil(Y - R - 0.5), 0, height - 1)
+    j1 = np.clip(np.floor(Y + R - 0.5), 0, height - 1)
+    area = np.maximum(i1 - i0 + 1, 0) * np.maximum(j1 - j0 + 1, 0)
+    return float(area[small].sum()), int(small.sum())
 
-    import torch
 
-    from paper_1606_04427_amd import binding as B
+def timed_steps(ctx, step, steps, warmup, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.spl_set_timing(True)
+    ctx.spl_get_timing()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, by, frames = ctx.spl_get_timing()
+    ctx.spl_set_timing(False)
+    return elapsed, ms, by, frames
 
+
+def stage_table(B, ms, by, frames):
+    out = {}
+    for k, name in enumerate(B.STAGES):
+        if frames:
+            out[name] = {"ms_per_frame": ms[k] / frames,
+                         "GBps": (by[k] / (ms[k] * 1e-3) / 1e9) if ms[k] > 0 else None}
+    return out
+
+
+def roofline_for(B, ms, by, frames, updates_per_frame=None):
+    kern = [k for k in range(len(B.STAGES)) if B.STAGES[k] not in ("host_gap_items",)]
+    dom = max(kern, key=lambda k: ms[k])
+    name = B.STAGES[dom]
+    per_launch = ms[dom] / max(frames, 1)
+    if name == "splat" and updates_per_frame:
+        # the splat evaluates a Gaussian per pixel of each particle's box: its
+        # bound is the vector ALU, not HBM
+        achieved = FLOPS_PER_UPDATE * updates_per_frame / (per_launch * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "kernel": KERNEL_OF_STAGE[name], "ms_per_launch": per_launch,
+                "updates_per_launch": updates_per_frame,
+                "flops_per_update": FLOPS_PER_UPDATE,
+                "hbm_GBps": by[dom] / (ms[dom] * 1e-3) / 1e9,
+                "hbm_frac": by[dom] / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "bytes_per_launch": by[dom] / max(frames, 1)}
+    achieved = by[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": KERNEL_OF_STAGE[name],
+            "ms_per_launch": per_launch, "bytes_per_launch": by[dom] / max(frames, 1)}
+
+
+def base_record(args, value, ms_per_step, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+# ----------------------------------------------------------------------------
+def run_additive(args, torch, B):
     t = time.time()
-    ps, poses, looks, pals = workload(args.n)
+    ps, poses, looks, pals = workload(args.n or 10_000_000)
     log(f"generated {ps.n} particles in {time.time() - t:.1f} s")
     dev = "cuda:0"
     ctx = B.Context(0)
@@ -106,62 +186,300 @@ def main():
         for k, pose in enumerate(poses):
             ctx.spl_render(parts, pose, prm, out=imgs[k], stats=False)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    stats = [ctx.spl_render(parts, p, prm, out=imgs[k])[1] for k, p in enumerate(poses)]
-    ctx.spl_set_timing(True)
-    ctx.spl_get_timing()  # reset
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms, by, frames = ctx.spl_get_timing()
-    ctx.spl_set_timing(False)
-    elapsed = t1 - t0
+    elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps * len(poses) * ps.n / elapsed
     log(f"{args.steps} steps in {elapsed:.3f} s, {ms_per_step:.2f} ms/step, {value:.3e} particles/s")
 
-    stages = {}
-    for k, name in enumerate(B.STAGES):
-        if frames:
-            stages[name] = {"ms_per_frame": ms[k] / frames,
-                            "GBps": (by[k] / (ms[k] * 1e-3) / 1e9) if ms[k] > 0 else None}
-    kern = [k for k in range(len(B.STAGES)) if B.STAGES[k] not in ("host_gap_items",)]
-    dom = max(kern, key=lambda k: ms[k])
-    achieved = by[dom] / (ms[dom] * 1e-3) / 1e9 if ms[dom] > 0 else 0.0
-    frame_bytes = sum(by[k] for k in kern) / max(frames, 1)
-    dom_kernel = {"splat": "k_splat_add", "project": "k_project", "large_splat": "k_splat_large",
-                  "scatter": "k_scatter", "count": "k_count", "finalise": "k_finalise",
-                  "sort": "k_sort_chunks/k_merge_pass", "scan": "k_scan"}[B.STAGES[dom]]
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom_kernel,
-                "ms_per_launch": ms[dom] / max(frames, 1),
-                "bytes_per_launch": by[dom] / max(frames, 1)}
-    out = {
-        "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "Soneira-Peebles clustered set (4 levels x 8), 2 species, "
-                               "1024x1024, 8 random poses, additive absorption=emission, FP32",
-                   "n_particles": ps.n, "image": [1024, 1024], "poses": len(poses),
-                   "tile": tile, "large_cut_px": cut},
+    # outside the timed region: per-pose statistics and the Gaussian updates
+    # the splat had to evaluate (from the device's own records)
+    stats = [ctx.spl_render(parts, p, prm, out=imgs[k])[1] for k, p in enumerate(poses)]
+    updates, small = 0.0, 0
+    for k, p in enumerate(poses):
+        rec, _ = ctx.spl_project(parts, p, prm)
+        u, s = box_pixels(rec.cpu().numpy(), p.width, p.height, stats[k]["large_cut"])
+        updates += u
+        small += s
+        del rec
+    updates /= len(poses)
+    roofline = roofline_for(B, ms, by, frames, updates)
+
+    # the same step through the batched entry point (one call for all poses)
+    batched = {}
+    for graphs in (0, 1):
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, graphs)
+        prms = [prm] * len(poses)
+
+        def bstep():
+            ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
+
+        for _ in range(args.warmup):
+            bstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            bstep()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        batched["graphs" if graphs else "direct"] = {
+            "ms_per_step": 1e3 * dt / args.steps,
+            "particles_per_s": args.steps * len(poses) * ps.n / dt}
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+    log("batched: " + json.dumps(batched))
+
+    frame_bytes = sum(by[k] for k in range(len(B.STAGES)) if B.STAGES[k] != "host_gap_items")
+    frame_bytes /= max(frames, 1)
+    out = base_record(args, value, ms_per_step, "f32", {
+        "workload": "Soneira-Peebles clustered set (4 levels x 8), 10M particles, 2 species, "
+                    "1024x1024, 8 random poses, additive absorption=emission, FP32",
+        "n_particles": ps.n, "image": [1024, 1024], "poses": len(poses), "tile": tile,
+        "large_cut_px": cut})
+    out.update({
         "hbm_GBps_per_frame": frame_bytes / (ms_per_step * 1e-3 / len(poses)) / 1e9,
         "ms_per_frame": ms_per_step / len(poses),
         "roofline": roofline,
-        "stages": stages,
+        "stages": stage_table(B, ms, by, frames),
+        "batched_entry_point": batched,
+        "mean_box_px_per_small_particle": updates * len(poses) / max(small, 1),
         "frames": [{"n_active": s["n_active"], "n_pairs": s["n_pairs"], "n_large": s["n_large"],
                     "n_large_pairs": s["n_large_pairs"]} for s in stats],
-    }
+    })
     ctx.close()
     if not args.no_cpu_baseline:
         t = time.time()
-        out["cpu_baseline"] = cpu_baseline(ps, poses, looks, pals, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(ps, poses, looks, pals, args.cpu_sample or 5_000_000,
+                                           B.SPL_ADD_AEQE)
         log(f"cpu baseline in {time.time() - t:.1f} s")
+    return out
+
+
+# ----------------------------------------------------------------------------
+def run_sorted(args, torch, B):
+    t = time.time()
+    ps, poses, looks, pals = workload(args.n or 10_000_000, width=2048, height=2048,
+                                      absorption=True)
+    log(f"generated {ps.n} particles in {time.time() - t:.1f} s")
+    dev = "cuda:0"
+    ctx = B.Context(0)
+    parts = B.DeviceParticles(ps, dev, "f32")
+    prm = B.make_params(B.SPL_SORTED, B.Palettes(pals, dev), looks)
+    pose = poses[0]
+    img = torch.empty((pose.height, pose.width, 3), dtype=torch.float32, device=dev)
+    tile = None
+    if not args.no_autotune:
+        tile, _ = ctx.spl_autotune(parts, pose, prm)
+        log(f"autotune: tile {tile}")
+
+    def step():
+        ctx.spl_render(parts, pose, prm, out=img, stats=False)
+
+    elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps * ps.n / elapsed
+    st = ctx.spl_render(parts, pose, prm, out=img)[1]
+    log(f"{args.steps} steps in {elapsed:.3f} s, {ms_per_step:.2f} ms/step, {value:.3e} particles/s")
+    out = base_record(args, value, ms_per_step, "f32", {
+        "workload": "Soneira-Peebles clustered set, 10M particles with absorption U[0.01,0.5], "
+                    "2048x2048, depth-sorted transfer, FP32", "n_particles": ps.n,
+        "image": [2048, 2048], "poses": 1, "tile": st["tile"]})
+    out.update({"roofline": roofline_for(B, ms, by, frames), "stages": stage_table(B, ms, by, frames),
+                "frame": {"n_active": st["n_active"], "n_pairs": st["n_pairs"]}})
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ps, [pose], looks, pals, args.cpu_sample or 2_000_000,
+                                           B.SPL_SORTED)
+    return out
+
+
+# ----------------------------------------------------------------------------
+def run_batched(args, torch, B):
+    from oracle import splref as R
+    from paper_1606_04427_amd import synth
+
+    n = args.n or 200_000_000
+    t = time.time()
+    ps = synth.soneira_peebles(n, seed=1003)
+    log(f"generated {ps.n} particles in {time.time() - t:.1f} s")
+    big = synth.random_poses(32, seed=2003, width=4096, height=4096)
+    small = synth.random_poses(32, seed=2004, width=1024, height=1024)
+    poses = [p for pair in zip(big, small) for p in pair][: args.views]
+    looks, pals = looks_for(ps)
+    dev = "cuda:0"
+    pal_d = B.Palettes(pals, dev)
+    prm = B.make_params(B.SPL_ADD_AEQE, pal_d, looks)
+    imgs = [torch.empty((p.height, p.width, 3), dtype=torch.float32, device=dev) for p in poses]
+    rng = np.random.Generator(np.random.PCG64(11))
+    sub_idx = np.sort(rng.choice(ps.n, min(ps.n, 1_000_000), replace=False))
+    sub = ps.subset(sub_idx)
+    results = {}
+    for dt_name in args.dtypes.split(","):
+        ctx = B.Context(0)
+        parts = B.DeviceParticles(ps, dev, dt_name)
+        torch.cuda.synchronize()
+        prms = [prm] * len(poses)
+
+        def bstep():
+            ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
+
+        def pstep():
+            for k, p in enumerate(poses):
+                ctx.spl_render(parts, p, prm, out=imgs[k], stats=False)
+
+        res = {}
+        for name, fn in (("batched", bstep), ("per_view", pstep)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res[name] = {"ms_per_step": 1e3 * dt / args.steps,
+                         "particles_per_s": args.steps * len(poses) * ps.n / dt}
+            log(f"{dt_name} {name}: {res[name]}")
+        del parts
+        # error against the FP64 oracle on a fixed 1M subsample, views
+        # alternating 4096^2 and 1024^2
+        sparts = B.DeviceParticles(sub, dev, dt_name)
+        L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+        RP = R.Particles(sub)
+        errs = []
+        for p in poses[: args.error_views]:
+            g, _ = ctx.spl_render(sparts, p, prm)
+            want = R.render(RP, p, R.params(R.ADD_AEQE, L))
+            got = g.cpu().numpy().astype(np.float64)
+            den = np.linalg.norm(want)
+            errs.append({"image": [p.width, p.height],
+                         "rel_l2": float(np.linalg.norm(got - want) / den) if den else 0.0,
+                         "max_abs": float(np.abs(got - want).max()),
+                         "max_ref": float(np.abs(want).max())})
+        res["error_vs_fp64_oracle_1M_subsample"] = errs
+        results[dt_name] = res
+        ctx.close()
+        del sparts
+        torch.cuda.empty_cache()
+    first = results[args.dtypes.split(",")[0]]
+    value = first["batched"]["particles_per_s"]
+    out = base_record(args, value, first["batched"]["ms_per_step"], args.dtypes.split(",")[0], {
+        "workload": f"Soneira-Peebles clustered set, {ps.n} particles, {len(poses)} views "
+                    "alternating 4096^2 and 1024^2, additive absorption=emission, reduced-"
+                    "precision attributes, batched launches", "n_particles": ps.n,
+        "views": len(poses)})
+    out["variants"] = results
+    return out
+
+
+# ----------------------------------------------------------------------------
+def run_serving(args, torch, B):
+    from paper_1606_04427_amd import serve, synth
+
+    n = args.n or 100_000_000
+    t = time.time()
+    ps = synth.soneira_peebles(n, seed=1004, absorption=True)
+    log(f"generated {ps.n} particles in {time.time() - t:.1f} s")
+    dev = "cuda:0"
+    parts = B.DeviceParticles(ps, dev, "f32")
+    bank = []
+    for k in range(8):
+        looks, pals = looks_for(ps, scale=1.0 + 0.25 * k, palette_offset=k)
+        bank.append((B.Palettes(pals, dev), looks))
+    sizes = [256, 512, 1024, 2048, 4096]
+    rng = np.random.Generator(np.random.PCG64(41))
+
+    def make(count, base):
+        out = []
+        for k in range(count):
+            s = sizes[rng.integers(len(sizes))]
+            pose = synth.random_poses(1, seed=base + k, width=s, height=s)[0]
+            mode = B.SPL_SORTED if rng.uniform() < 0.2 else B.SPL_ADD_AEQE
+            out.append(serve.Request(base + k, pose, mode, look=int(rng.integers(8))))
+        return out
+
+    cost = lambda r: serve.request_bytes(parts.n, r.pose.width, r.pose.height,
+                                         r.mode == B.SPL_SORTED)
+    keep = lambda r: False
+    result = {}
+    # plain path: one request per call on one stream, closed loop (capacity)
+    ex = serve.GpuExecutor(parts, bank)
+    serve.one_per_call(ex, make(args.warm_requests, 10_000), keep=keep)
+    base = serve.one_per_call(ex, make(args.requests, 20_000), keep=keep)
+    cap = serve.summary(base)
+    result["one_per_call_closed_loop"] = cap
+    log(f"one per call, closed loop: {cap}")
+    capacity = cap["frames_per_s"]
+
+    def server():
+        return serve.Server(lambda w: serve.GpuExecutor(parts, bank, batch_bytes=args.budget),
+                            n_workers=args.workers, budget_bytes=args.budget,
+                            max_views=args.max_views, cost=cost, keep=keep).start()
+
+    srv = server()
+    serve.drive(srv, make(args.warm_requests, 30_000), np.zeros(args.warm_requests))
+    reqs = make(args.requests, 40_000)
+    serve.drive(srv, reqs, np.zeros(len(reqs)))
+    closed = serve.summary(reqs)
+    closed["batches"] = srv.n_batches
+    result["server_closed_loop"] = closed
+    log(f"server, closed loop: {closed}")
+    for frac in args.rates:
+        rate = frac * capacity
+        arr = synth.poisson_arrivals(args.requests, rate, seed=int(1000 * frac))
+        reqs = make(args.requests, int(50_000 + 10_000 * frac))
+        serve.drive(srv, reqs, arr)
+        s = serve.summary(reqs)
+        s["offered_rate"] = rate
+        result[f"server_poisson_{frac:g}x"] = s
+        log(f"server at {frac:g} x capacity: {s}")
+        reqs = make(args.requests, int(60_000 + 10_000 * frac))
+        b = serve.summary(serve.one_per_call(ex, reqs, arr, keep=keep))
+        b["offered_rate"] = rate
+        result[f"one_per_call_poisson_{frac:g}x"] = b
+        log(f"one per call at {frac:g} x capacity: {b}")
+    srv.stop()
+    ex.close()
+    value = closed["frames_per_s"]
+    out = base_record(args, value, 1e3 / value, "f32", {
+        "workload": f"serving: {ps.n} resident clustered particles, views 256^2..4096^2, "
+                    "80% additive / 20% depth-sorted, 8 looks", "n_particles": ps.n,
+        "workers": args.workers, "budget_bytes": args.budget, "max_views": args.max_views})
+    out["unit"] = "frames/s"
+    out["speedup_vs_one_per_call"] = value / capacity
+    out["serving"] = result
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="additive",
+                    choices=["additive", "sorted", "batched", "serving"])
+    ap.add_argument("--n", type=int, default=0, help="particles (0: the workload's size)")
+    ap.add_argument("--cpu-sample", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--dtypes", default="bf16,f16", help="batched: attribute dtypes")
+    ap.add_argument("--views", type=int, default=64, help="batched: views per step")
+    ap.add_argument("--error-views", type=int, default=4, help="batched: views checked")
+    ap.add_argument("--requests", type=int, default=150, help="serving: requests per run")
+    ap.add_argument("--warm-requests", type=int, default=20)
+    ap.add_argument("--workers", type=int, default=2)
+    ap.add_argument("--max-views", type=int, default=16)
+    ap.add_argument("--budget", type=int, default=48 << 30)
+    ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 1.0, 1.2])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build renders on exactly one GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1606_04427_amd import binding as B
+
+    run = {"additive": run_additive, "sorted": run_sorted, "batched": run_batched,
+           "serving": run_serving}[args.workload]
+    out = run(args, torch, B)
     print(json.dumps(out), flush=True)
 
 

@@ -6,17 +6,14 @@
 // atomics (additive) or by an ordered merge of partial (colour,
 // transmittance) tiles (sorted).
 //
-// k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of list
-//                  entries is loaded once, one entry per lane, and each
-//                  entry's box inside the tile is cut into 4 x 4 windows
-//                  listed in LDS (offsets from a prefix sum, no atomics).
-//                  16-lane groups take the windows round-robin, one pixel per
-//                  lane, keep running sums while a group's consecutive
-//                  windows coincide (dense cluster cores) and add them into a
-//                  32-bit fixed-point LDS accumulator with integer atomics
-//                  (LDS FP32 atomics are ~40x slower on this hardware).  After
-//                  every batch the accumulator is folded into per-pixel
-//                  Neumaier-compensated FP32 sums.
+// k_splat_add<T>   additive modes, T x T tile, 256 lanes, one pixel (T = 16)
+//                  or four (T = 32) per lane.  Each batch of list entries is
+//                  staged in LDS; 16-lane groups own 4 x 4 micro-tiles, list
+//                  the staged entries that meet their micro-tile and gather
+//                  them in registers: no atomics inside the tile, and a lane
+//                  only evaluates entries whose box meets its micro-tile.
+//                  Batch sums fold into per-pixel Neumaier-compensated FP32
+//                  sums.
 // k_splat_large    the large-particle path: 64 x 64 px tiles, 512 lanes, 8
 //                  pixels per lane, gather only (a large particle covers most
 //                  of the pixels it is tested against).
@@ -42,57 +39,50 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
   return (uint32_t)a0 | ((uint32_t)a1 << 8) | ((uint32_t)b0 << 16) | ((uint32_t)b1 << 24);
 }
 
-// One list entry's box inside a tile is cut into 4 x 4 windows.  A window
-// work item is a 32-bit word: entry slot in the batch (8 bits), window origin
-// in the tile (x, y: 6 bits each), valid width and height minus one (2 bits
-// each).
-//
-// Accumulation is in 32-bit fixed point: per batch, the scale 2^S is chosen so
-// that the batch's summed amplitude (sum over entries of the largest colour
-// channel) stays below 2^30, so no pixel sum can overflow; one quantum is at
-// most 2^-31 of that sum.  LDS integer atomics are cheap on this hardware,
-// LDS FP32 atomics are not.  Integer sums are also independent of the order in
-// which the groups add.
-template <int T, int BATCH>
+// A batch of up to 256 list entries is staged in LDS (offsets, width,
+// premultiplied colour, box inside the tile).  The tile is split into 4 x 4
+// micro-tiles; a 16-lane group owns one micro-tile (T = 16) or four (T = 32),
+// one pixel per lane.  For each of its micro-tiles the group lists, in list
+// order, the staged entries whose box meets the micro-tile (ballot and
+// population count, no atomics), then every lane evaluates its pixel for each
+// listed entry and accumulates in registers.  Batch sums are folded into
+// per-pixel Neumaier-compensated FP32 sums.
+template <int T>
 __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__restrict__ pairs,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ counts, int chunk,
                                                const TileK &tk, float *__restrict__ img) {
-  constexpr int NP = T * T;
-  constexpr int PX = NP / kBlock;            // pixels per lane in the fold
-  constexpr int MAXWIN = (T / 4) * (T / 4);  // windows of a box that fills the tile
-  constexpr int NLW = BATCH / 64;            // waves that load entries
+  constexpr int MX = T / 4;            // micro-tiles per tile row
+  constexpr int MT = MX * MX / 16;     // micro-tiles per group
   constexpr float kLog2e = 1.4426950408889634f;
-  __shared__ int acc[3 * NP];
-  __shared__ float4 s_geo[BATCH];  // x offset, y offset, log2(e)/sigma^2, box origin
-  __shared__ float4 s_col[BATCH];  // premultiplied colour
-  __shared__ uint32_t s_win[BATCH * MAXWIN];
-  __shared__ int s_wsum[4];
-  __shared__ float s_asum[4];
+  constexpr uint32_t kEmpty = 0x000000ffu | 0x00ff0000u;  // li0 = lj0 = 255 > li1 = lj1 = 0
+  __shared__ float4 s_pos[kBlock];     // Xi - x0, 0.5 - Xf, Yi - y0, 0.5 - Yf
+  __shared__ float4 s_col[kBlock];     // log2(e)/sigma^2, premultiplied colour
+  __shared__ uint32_t s_box[kBlock];   // li0 | li1 << 8 | lj0 << 16 | lj1 << 24
+  __shared__ __align__(4) uint8_t s_list[16][kBlock];
 
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int grp = tid >> 4, kx = tid & 3, ky = (tid >> 2) & 3;
+  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
+  const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
+  uint8_t *const my_list = s_list[grp];
 
-  float sum[PX][3], comp[PX][3];
+  float sum[MT][3], comp[MT][3];
 #pragma unroll
-  for (int m = 0; m < PX; ++m)
+  for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       sum[m][c] = 0.f;
       comp[m][c] = 0.f;
     }
-  for (int i = tid; i < 3 * NP; i += kBlock) acc[i] = 0;
 
-  for (uint32_t base = it.y; base < it.z; base += BATCH) {
-    // phase 1: one list entry per loading lane -> box in the tile, constants
+  for (uint32_t base = it.y; base < it.z; base += kBlock) {
+    // stage one list entry per lane
     const uint32_t k = base + tid;
-    int nwin = 0, nwx = 1, ex_li0 = 0, ex_li1 = 0, ex_lj0 = 0, ex_lj1 = 0;
-    float amax = 0.f;
-    if (tid < BATCH && k < it.z) {
+    uint32_t box = kEmpty;
+    if (k < it.z) {
       const uint32_t pid = pairs[k];
       const float4 r0 = rec[2 * (size_t)pid];
       const float4 r1 = rec[2 * (size_t)pid + 1];
@@ -101,112 +91,72 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
         const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
         if (li0 <= li1 && lj0 <= lj1) {
-          // offset of pixel centre (li0 + u, lj0 + v) from the particle is
-          // (cx + u, cy + v); the integer parts subtract exactly
-          const float cx = ((float)(li0 + x0) - r0.x) + (0.5f - r0.y);
-          const float cy = ((float)(lj0 + y0) - r0.z) + (0.5f - r0.w);
-          s_geo[tid] = make_float4(cx, cy, kLog2e / (r1.x * r1.x),
-                                   __uint_as_float((uint32_t)li0 | ((uint32_t)lj0 << 16)));
-          s_col[tid] = make_float4(r1.y, r1.z, r1.w, 0.f);
-          nwx = (li1 - li0) / 4 + 1;
-          nwin = nwx * ((lj1 - lj0) / 4 + 1);
-          ex_li1 = li1;
-          ex_lj1 = lj1;
-          ex_li0 = li0;
-          ex_lj0 = lj0;
-          amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
+          box = pack_box(li0, li1, lj0, lj1);
+          s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
+          s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
         }
       }
     }
-    // window offsets: inclusive scan inside each wave, wave totals in LDS;
-    // batch amplitude bound: sum of each entry's largest channel
-    int incl = nwin;
-    float asum = amax;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-      asum += __shfl_xor(asum, d);
-    }
-    if (wave < NLW && lane == 63) s_wsum[wave] = incl;
-    if (wave < NLW && lane == 0) s_asum[wave] = asum;
+    s_box[tid] = box;
     __syncthreads();
-    int woff = 0, total = 0;
-    float amp_sum = 0.f;
+    const int nb = (int)min((uint32_t)kBlock, it.z - base);
 #pragma unroll
-    for (int w = 0; w < NLW; ++w) {
-      if (w < wave) woff += s_wsum[w];
-      total += s_wsum[w];
-      amp_sum += s_asum[w];
-    }
-    int ex = 0;
-    (void)frexpf(amp_sum, &ex);  // amp_sum <= 2^ex
-    const int S = 30 - ex;       // batch sums stay below 2^30
-    for (int w = 0, o = woff + incl - nwin; w < nwin; ++w, ++o) {
-      const int wx0 = ex_li0 + 4 * (w % nwx), wy0 = ex_lj0 + 4 * (w / nwx);
-      const int ww = min(3, ex_li1 - wx0), wh = min(3, ex_lj1 - wy0);
-      s_win[o] = (uint32_t)tid | ((uint32_t)wx0 << 8) | ((uint32_t)wy0 << 14) |
-                 ((uint32_t)ww << 20) | ((uint32_t)wh << 22);
-    }
-    __syncthreads();
-
-    // phase 2: 16-lane groups take windows round-robin, one pixel per lane,
-    // and keep running sums while a group's consecutive windows coincide
-    {
+    for (int m = 0; m < MT; ++m) {
+      const int q = grp + 16 * m;
+      const int mx0 = (q % MX) * 4, my0 = (q / MX) * 4;
+      // the group's list: staged entries whose box meets its micro-tile
+      int cnt = 0;
+      for (int s0 = 0; s0 < nb; s0 += 16) {
+        // every slot holds a box (empty past the end of the list)
+        const int j = s0 + l;
+        const uint32_t b = s_box[j];
+        const int bi0 = (int)(b & 0xffu), bi1 = (int)((b >> 8) & 0xffu);
+        const int bj0 = (int)((b >> 16) & 0xffu), bj1 = (int)(b >> 24);
+        const bool hit = (bi0 <= mx0 + 3) & (bi1 >= mx0) & (bj0 <= my0 + 3) & (bj1 >= my0);
+        const uint32_t bits = (uint32_t)(__ballot(hit) >> (16 * gw)) & 0xffffu;
+        if (hit) my_list[cnt + __popc(bits & ((1u << l) - 1u))] = (uint8_t)j;
+        cnt += __popc(bits);
+      }
+      // the list is written and read by the same wave
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const float px = (float)(mx0 + lx), py = (float)(my0 + ly);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-      int cur = -1;  // the lane's pixel in the current window; NP = outside
-      for (int e = grp; e < total; e += 16) {
-        const uint32_t w = s_win[e];
-        const int slot = (int)(w & 0xffu);
-        const float4 g = s_geo[slot];
-        const float4 col = s_col[slot];
-        const int px = (int)((w >> 8) & 63u) + kx, py = (int)((w >> 14) & 63u) + ky;
-        const int pix = (px < T && py < T) ? py * T + px : NP;
-        if (pix != cur) {
-          if (cur >= 0 && cur < NP) {
-            atomicAdd(&acc[cur], (int)rintf(ldexpf(a0, S)));
-            atomicAdd(&acc[NP + cur], (int)rintf(ldexpf(a1, S)));
-            atomicAdd(&acc[2 * NP + cur], (int)rintf(ldexpf(a2, S)));
-          }
-          cur = pix;
-          a0 = a1 = a2 = 0.f;
-        }
-        if (kx <= (int)((w >> 20) & 3u) && ky <= (int)((w >> 22) & 3u)) {
-          const uint32_t org = __float_as_uint(g.w);
-          const float dx = g.x + (float)(px - (int)(org & 0xffffu));
-          const float dy = g.y + (float)(py - (int)(org >> 16));
-          const float q = (dx * dx + dy * dy) * g.z;
-          if (q <= qmax) {
-            const float e2 = exp2f(-q);
-            a0 += col.x * e2;
-            a1 += col.y * e2;
-            a2 += col.z * e2;
-          }
-        }
+      auto eval = [&](int j) {
+        const float4 p = s_pos[j];
+        const float4 c = s_col[j];
+        const float dx = (px - p.x) + p.y;
+        const float dy = (py - p.z) + p.w;
+        const float qq = (dx * dx + dy * dy) * c.x;
+        // qq <= qmax keeps the result far above the denormal range, so the
+        // hardware exponential needs no range fix-up
+        const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
+        a0 += c.y * e;
+        a1 += c.z * e;
+        a2 += c.w * e;
+      };
+      int i = 0;
+      for (; i + 4 <= cnt; i += 4) {
+        const uint32_t w4 = *reinterpret_cast<const uint32_t *>(my_list + i);
+        eval((int)(w4 & 0xffu));
+        eval((int)((w4 >> 8) & 0xffu));
+        eval((int)((w4 >> 16) & 0xffu));
+        eval((int)(w4 >> 24));
       }
-      if (cur >= 0 && cur < NP) {
-        atomicAdd(&acc[cur], (int)rintf(ldexpf(a0, S)));
-        atomicAdd(&acc[NP + cur], (int)rintf(ldexpf(a1, S)));
-        atomicAdd(&acc[2 * NP + cur], (int)rintf(ldexpf(a2, S)));
-      }
+      for (; i < cnt; ++i) eval((int)my_list[i]);
+      neumaier(sum[m][0], comp[m][0], a0);
+      neumaier(sum[m][1], comp[m][1], a1);
+      neumaier(sum[m][2], comp[m][2], a2);
+      // the next micro-tile's list overwrites this one
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // phase 3: fold the batch sums into the compensated per-pixel sums
-#pragma unroll
-    for (int m = 0; m < PX; ++m) {
-      const int pix = tid + m * kBlock;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int v = acc[c * NP + pix];
-        acc[c * NP + pix] = 0;
-        neumaier(sum[m][c], comp[m][c], ldexpf((float)v, -S));
-      }
-    }
   }
 #pragma unroll
-  for (int m = 0; m < PX; ++m) {
-    const int pix = tid + m * kBlock;
-    const int gx = x0 + pix % T, gy = y0 + pix / T;
+  for (int m = 0; m < MT; ++m) {
+    const int q = grp + 16 * m;
+    const int gx = x0 + (q % MX) * 4 + lx, gy = y0 + (q / MX) * 4 + ly;
     if (gx < tk.W && gy < tk.H) {
       float *o = img + 3 * ((size_t)gy * tk.W + gx);
 #pragma unroll
@@ -221,20 +171,20 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   }
 }
 
-template <int T, int BATCH>
-__global__ __launch_bounds__(kBlock, 6) void k_splat_add(const Item *__restrict__ items,
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ items,
                                                       const uint32_t *__restrict__ pairs,
                                                       const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ counts,
                                                       int chunk, TileK tk,
                                                       float *__restrict__ img) {
-  splat_add_item<T, BATCH>(items[blockIdx.x], pairs, rec, counts, chunk, tk, img);
+  splat_add_item<T>(items[blockIdx.x], pairs, rec, counts, chunk, tk, img);
 }
 
 // Persistent form for many views: workgroups take (view, tile chunk) items
 // from a device counter until the queue is empty; every workgroup exits.
-template <int T, int BATCH>
-__global__ __launch_bounds__(kBlock, 6) void k_splat_add_views(const ViewK *__restrict__ views,
+template <int T>
+__global__ __launch_bounds__(kBlock) void k_splat_add_views(const ViewK *__restrict__ views,
                                                             const Item *__restrict__ items,
                                                             const uint32_t *__restrict__ n_items,
                                                             uint32_t *__restrict__ next,
@@ -250,7 +200,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_splat_add_views(const ViewK *__re
     Item it = items[idx];
     const ViewK &v = views[it.x >> 24];
     it.x &= 0xffffffu;
-    splat_add_item<T, BATCH>(it, v.pairs, v.rec, v.counts, chunk, v.tk, v.img);
+    splat_add_item<T>(it, v.pairs, v.rec, v.counts, chunk, v.tk, v.img);
     __syncthreads();
   }
 }
@@ -551,10 +501,10 @@ hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint
   if (n_items == 0) return hipSuccess;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   if (tile == 16)
-    hipLaunchKernelGGL((k_splat_add<16, 256>), dim3(n_items), dim3(kBlock), 0, s, items, pairs, r,
+    hipLaunchKernelGGL((k_splat_add<16>), dim3(n_items), dim3(kBlock), 0, s, items, pairs, r,
                        counts, chunk, tk, img);
   else if (tile == 32)
-    hipLaunchKernelGGL((k_splat_add<32, 128>), dim3(n_items), dim3(kBlock), 0, s, items, pairs, r,
+    hipLaunchKernelGGL((k_splat_add<32>), dim3(n_items), dim3(kBlock), 0, s, items, pairs, r,
                        counts, chunk, tk, img);
   else
     return hipErrorInvalidValue;
@@ -577,10 +527,10 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
   hipLaunchKernelGGL(k_splat_large_views, dim3(grid), dim3(kLargeThreads), 0, s, views, large,
                      n_large, next_large, cchunk);
   if (tile == 16)
-    hipLaunchKernelGGL((k_splat_add_views<16, 256>), dim3(grid), dim3(kBlock), 0, s, views, fine,
+    hipLaunchKernelGGL((k_splat_add_views<16>), dim3(grid), dim3(kBlock), 0, s, views, fine,
                        n_fine, next_fine, chunk);
   else if (tile == 32)
-    hipLaunchKernelGGL((k_splat_add_views<32, 128>), dim3(grid), dim3(kBlock), 0, s, views, fine,
+    hipLaunchKernelGGL((k_splat_add_views<32>), dim3(grid), dim3(kBlock), 0, s, views, fine,
                        n_fine, next_fine, chunk);
   else
     return hipErrorInvalidValue;
