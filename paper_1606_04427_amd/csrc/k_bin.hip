@@ -20,6 +20,7 @@ namespace {
 
 constexpr int kLdsBins = 16384;  // 64 KB of u32 bins
 constexpr int kChunk = 4096;     // particles per workgroup pass
+constexpr int kSerialSpan = 16;  // spans of up to this many tiles stay on their lane
 
 struct SpanDec {
   int tx0, tx1, ty0, ty1;
@@ -53,6 +54,83 @@ __device__ __forceinline__ int wave_runs(bool single, int key, int &head_of) {
   return after ? (__builtin_ctzll(after) + 1) : (64 - lane);
 }
 
+// The (particle, tile) pairs of the wave's multi-tile particles.  A lane
+// walks a short span itself; the pairs of long spans are handed out 64 at a
+// time to all lanes: the pairs are numbered by a wave prefix sum and
+// each lane finds its pair's particle (the owner lane) by a binary search
+// over the lanes, so a particle that spans many tiles does not serialise its
+// own lane.  For every pair the binning rule keeps, fn(bin, owner_index,
+// owner_payload) runs on the lane that took the pair.  Every shuffle runs with
+// the whole wave active.
+template <class F>
+__device__ __forceinline__ void multi_tile_pairs(bool multi, const SpanDec &d, bool filt, int off,
+                                                 int ntx, const float4 *__restrict__ rec,
+                                                 int64_t k, uint32_t payload, const TileK &tk,
+                                                 F &&fn) {
+  const int lane = __lane_id();
+  const int w = multi ? d.tx1 - d.tx0 + 1 : 1;
+  const uint32_t span_tiles = multi ? (uint32_t)(w * (d.ty1 - d.ty0 + 1)) : 0u;
+  // the paper rule needs the owner's record; each lane loads its own
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float sg = 0.f;
+  if (filt && multi) {
+    r0 = rec[2 * k];
+    sg = rec[2 * k + 1].x;
+  }
+  // short spans: the lane walks its own tiles
+  if (span_tiles > 0 && span_tiles <= (uint32_t)kSerialSpan) {
+    for (int ty = d.ty0; ty <= d.ty1; ++ty)
+      for (int tx = d.tx0; tx <= d.tx1; ++tx)
+        if (!filt || paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
+          fn((uint32_t)(off + ty * ntx + tx), (uint32_t)k, payload);
+  }
+  // long spans: shared by the wave
+  const uint32_t cnt = span_tiles > (uint32_t)kSerialSpan ? span_tiles : 0u;
+  if (__ballot(cnt != 0u) == 0ull) return;  // uniform
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t v = (uint32_t)__shfl_up((int)incl, o);
+    if (lane >= o) incl += v;
+  }
+  const uint32_t total = (uint32_t)__shfl((int)incl, 63);
+  const uint32_t excl = incl - cnt;
+  const float inv_w = 1.0f / (float)w;
+  const bool any_filt = __ballot(filt) != 0ull;
+  for (uint32_t r = 0; r < total; r += 64) {  // uniform trip count
+    const uint32_t t = r + (uint32_t)lane;
+    // owner: the last lane whose first pair number is <= t (lanes without
+    // pairs share the first number of the next lane that has some)
+    int L = 0;
+#pragma unroll
+    for (int st = 32; st >= 1; st >>= 1) {
+      const uint32_t e = (uint32_t)__shfl((int)excl, L + st);
+      if (e <= t) L += st;
+    }
+    const uint32_t local = t - (uint32_t)__shfl((int)excl, L);
+    const uint32_t ow = (uint32_t)__shfl(w, L);
+    const float oinv = __shfl(inv_w, L);
+    const int otx0 = __shfl(d.tx0, L), oty0 = __shfl(d.ty0, L);
+    const int boff = __shfl(off, L), bntx = __shfl(ntx, L);
+    const uint32_t ok = (uint32_t)__shfl((int)(uint32_t)k, L);
+    const uint32_t opay = (uint32_t)__shfl((int)payload, L);
+    uint32_t q = (uint32_t)((float)local * oinv);
+    if (q * ow > local)
+      --q;
+    else if ((q + 1) * ow <= local)
+      ++q;
+    const int tx = otx0 + (int)(local - q * ow), ty = oty0 + (int)q;
+    bool keep = t < total;
+    if (any_filt) {
+      const bool of = __shfl((int)filt, L) != 0;
+      const float x0 = __shfl(r0.x, L), x1 = __shfl(r0.y, L), y0 = __shfl(r0.z, L),
+                  y1 = __shfl(r0.w, L), sgo = __shfl(sg, L);
+      if (keep && of) keep = paper_rule_keeps(x0, x1, y0, y1, sgo, tk.nu, tk.tile, tx, ty);
+    }
+    if (keep) fn((uint32_t)(boff + ty * bntx + tx), ok, opay);
+  }
+}
+
 template <bool kLds>
 __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
                                                   const float4 *__restrict__ rec, int64_t n,
@@ -81,20 +159,8 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
       int head_of;
       const int len = wave_runs(single, key, head_of);
       if (len) atomicAdd(&bins[key], (uint32_t)len);
-      if (act && !single) {
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float sg = 0.f;
-        if (filt) {
-          r0 = rec[2 * k];
-          sg = rec[2 * k + 1].x;
-        }
-        for (int ty = d.ty0; ty <= d.ty1; ++ty)
-          for (int tx = d.tx0; tx <= d.tx1; ++tx) {
-            if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
-              continue;
-            atomicAdd(&bins[off + ty * ntx + tx], 1u);
-          }
-      }
+      multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, 0u, tk,
+                       [&](uint32_t bin, uint32_t, uint32_t) { atomicAdd(&bins[bin], 1u); });
     }
     if (kLds) {
       __syncthreads();
@@ -138,20 +204,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
         int head_of;
         const int len = wave_runs(single, key, head_of);
         if (len) atomicAdd(&hist[key], (uint32_t)len);
-        if (act && !single) {
-          float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-          float sg = 0.f;
-          if (filt) {
-            r0 = rec[2 * k];
-            sg = rec[2 * k + 1].x;
-          }
-          for (int ty = d.ty0; ty <= d.ty1; ++ty)
-            for (int tx = d.tx0; tx <= d.tx1; ++tx) {
-              if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
-                continue;
-              atomicAdd(&hist[off + ty * ntx + tx], 1u);
-            }
-        }
+        multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, 0u, tk,
+                         [&](uint32_t bin, uint32_t, uint32_t) { atomicAdd(&hist[bin], 1u); });
       }
       __syncthreads();
       for (int i = threadIdx.x; i < nb; i += kBlock) {
@@ -184,24 +238,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
           keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
         else
           pairs[slot] = (uint32_t)k;
-      } else if (act) {
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        float sg = 0.f;
-        if (filt) {
-          r0 = rec[2 * k];
-          sg = rec[2 * k + 1].x;
-        }
-        for (int ty = d.ty0; ty <= d.ty1; ++ty)
-          for (int tx = d.tx0; tx <= d.tx1; ++tx) {
-            if (filt && !paper_rule_keeps(r0.x, r0.y, r0.z, r0.w, sg, tk.nu, tk.tile, tx, ty))
-              continue;
-            const uint32_t slot = atomicAdd(&bins[off + ty * ntx + tx], 1u);
-            if (kKeys)
-              keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
-            else
-              pairs[slot] = (uint32_t)k;
-          }
       }
+      multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, (uint32_t)(key_hi >> 32), tk,
+                       [&](uint32_t bin, uint32_t pk, uint32_t zbits) {
+                         const uint32_t slot = atomicAdd(&bins[bin], 1u);
+                         if (kKeys)
+                           keys[slot] = ((unsigned long long)zbits << 32) | (unsigned long long)pk;
+                         else
+                           pairs[slot] = pk;
+                       });
     }
     if (kLds) __syncthreads();
   }

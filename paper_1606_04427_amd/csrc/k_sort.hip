@@ -28,17 +28,17 @@ __global__ __launch_bounds__(kBlock) void k_sort_chunks(unsigned long long *__re
   while (np < n) np <<= 1;
   for (int i = threadIdx.x; i < np; i += kBlock) s[i] = (i < n) ? keys[it.y + i] : ~0ull;
   __syncthreads();
+  // every lane takes compare-exchange pairs (i, i + j): i is the pair number
+  // with a zero bit inserted at bit log2(j)
   for (int k = 2; k <= np; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < np; i += kBlock) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const unsigned long long a = s[i], b = s[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) {
-            s[i] = b;
-            s[ixj] = a;
-          }
+      for (int p = threadIdx.x; p < (np >> 1); p += kBlock) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+        const unsigned long long a = s[i], b = s[i + j];
+        const bool up = (i & k) == 0;
+        if ((a > b) == up) {
+          s[i] = b;
+          s[i + j] = a;
         }
       }
       __syncthreads();

@@ -17,9 +17,9 @@
 // k_splat_large    the large-particle path: 64 x 64 px tiles, 512 lanes, 8
 //                  pixels per lane, gather only (a large particle covers most
 //                  of the pixels it is tested against).
-// k_composite<T>   sorted mode: front-to-back slab compositing in list order,
-//                  one pixel per lane (T = 16) or 4 (T = 32); transmittance
-//                  per pixel in registers.
+// k_composite<T>   sorted mode: the same staging and micro-tile lists, with
+//                  front-to-back slab compositing per pixel in list order;
+//                  transmittance per pixel in registers.
 #include "spl_internal.h"
 
 namespace spl {
@@ -341,6 +341,11 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
   }
 }
 
+// Sorted mode.  Staging and micro-tile lists as in splat_add_item; the lists
+// keep the depth order of the tile list, so each lane composites its pixel
+// front to back: C += T E tau phi(a tau), T *= exp(-a tau), with
+// phi(x) = (1 - e^-x)/x from its Taylor series below x = 1/2 (no
+// cancellation) and from the exponential above.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ items,
                                                       const unsigned long long *__restrict__ keys,
@@ -351,36 +356,38 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
                                                       float *__restrict__ img,
                                                       float4 *__restrict__ partial) {
   constexpr int NP = T * T;
-  constexpr int PX = NP / kBlock;
-  constexpr int WROWS = (64 / T) * PX;
-  __shared__ float g_ox[kBlock], g_fx[kBlock], g_oy[kBlock], g_fy[kBlock], g_is2[kBlock];
-  __shared__ float g_a0[kBlock], g_a1[kBlock], g_a2[kBlock], g_ap[kBlock];
-  __shared__ uint32_t g_box[kBlock];
+  constexpr int MX = T / 4;
+  constexpr int MT = MX * MX / 16;
+  constexpr float kLog2e = 1.4426950408889634f;
+  constexpr uint32_t kEmpty = 0x000000ffu | 0x00ff0000u;
+  __shared__ float4 s_pos[kBlock];
+  __shared__ float4 s_col[kBlock];
+  __shared__ float s_ap[kBlock];       // a / (pi sigma^2)
+  __shared__ uint32_t s_box[kBlock];
+  __shared__ __align__(4) uint8_t s_list[16][kBlock];
 
   const Item it = items[blockIdx.x];
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
-  const int tid = threadIdx.x;
-  const int pc = tid % T;
-  const int pr0 = (tid / T) * PX;
-  const int wr0 = (tid / 64) * WROWS, wr1 = wr0 + WROWS - 1;
-  const float nu2 = tk.nu * tk.nu;
+  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
+  const int lx = l & 3, ly = l >> 2;
+  const float qmax = tk.nu * tk.nu * kLog2e;
+  uint8_t *const my_list = s_list[grp];
 
-  float C[PX][3], Cc[PX][3], Cb[PX][3], Tr[PX];
+  float C[MT][3], Cc[MT][3], Tr[MT];
 #pragma unroll
-  for (int m = 0; m < PX; ++m) {
+  for (int m = 0; m < MT; ++m) {
     Tr[m] = 1.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       C[m][c] = 0.f;
       Cc[m][c] = 0.f;
-      Cb[m][c] = 0.f;
     }
   }
   for (uint32_t base = it.y; base < it.z; base += kBlock) {
     const uint32_t k = base + tid;
-    uint32_t box = pack_box(1, 0, 1, 0);  // empty unless set below (li0 > li1)
+    uint32_t box = kEmpty;
     if (k < it.z) {
       const uint32_t pid = (uint32_t)(keys[k] & 0xffffffffull);
       const float4 r0 = rec[2 * (size_t)pid];
@@ -391,66 +398,83 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
         const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
         if (li0 <= li1 && lj0 <= lj1) {
           box = pack_box(li0, li1, lj0, lj1);
-          g_ox[tid] = r0.x - (float)x0;
-          g_fx[tid] = 0.5f - r0.y;
-          g_oy[tid] = r0.z - (float)y0;
-          g_fy[tid] = 0.5f - r0.w;
-          g_is2[tid] = 1.0f / (r1.x * r1.x);
-          g_a0[tid] = r1.y;
-          g_a1[tid] = r1.z;
-          g_a2[tid] = r1.w;
-          g_ap[tid] = rec2[pid].x;
+          s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
+          s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
+          s_ap[tid] = rec2[pid].x;
         }
       }
     }
-    g_box[tid] = box;
+    s_box[tid] = box;
     __syncthreads();
     const int nb = (int)min((uint32_t)kBlock, it.z - base);
-    for (int g = 0; g < nb; ++g) {
-      const uint32_t bx = g_box[g];
-      const int li0 = bx & 0xff, li1 = (bx >> 8) & 0xff, lj0 = (bx >> 16) & 0xff,
-                lj1 = bx >> 24;
-      if (li0 > li1 || lj1 < wr0 || lj0 > wr1) continue;  // uniform across the wave
-      if (pc < li0 || pc > li1) continue;
-      const float dx = ((float)pc - g_ox[g]) + g_fx[g];
-      const float dx2 = dx * dx;
-      const float is2 = g_is2[g], oy = g_oy[g], fy = g_fy[g], ap = g_ap[g];
 #pragma unroll
-      for (int m = 0; m < PX; ++m) {
-        const int row = pr0 + m;
-        if (row < lj0 || row > lj1) continue;
-        const float dy = ((float)row - oy) + fy;
-        const float q = (dx2 + dy * dy) * is2;
-        if (q <= nu2) {
-          const float e = __expf(-q);
-          const float x = ap * e;
-          const float em = expm1f(-x);                       // exp(-x) - 1
-          const float w = (x > 1e-6f) ? (-em / x) : (1.0f - 0.5f * x);  // (1 - e^-x) / x
-          const float tw = Tr[m] * e * w;
-          Cb[m][0] += tw * g_a0[g];
-          Cb[m][1] += tw * g_a1[g];
-          Cb[m][2] += tw * g_a2[g];
-          Tr[m] *= (1.0f + em);
+    for (int m = 0; m < MT; ++m) {
+      const int q = grp + 16 * m;
+      const int mx0 = (q % MX) * 4, my0 = (q / MX) * 4;
+      int cnt = 0;
+      for (int s0 = 0; s0 < nb; s0 += 16) {
+        const int j = s0 + l;
+        const uint32_t b = s_box[j];
+        const int bi0 = (int)(b & 0xffu), bi1 = (int)((b >> 8) & 0xffu);
+        const int bj0 = (int)((b >> 16) & 0xffu), bj1 = (int)(b >> 24);
+        const bool hit = (bi0 <= mx0 + 3) & (bi1 >= mx0) & (bj0 <= my0 + 3) & (bj1 >= my0);
+        const uint32_t bits = (uint32_t)(__ballot(hit) >> (16 * gw)) & 0xffffu;
+        if (hit) my_list[cnt + __popc(bits & ((1u << l) - 1u))] = (uint8_t)j;
+        cnt += __popc(bits);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const float px = (float)(mx0 + lx), py = (float)(my0 + ly);
+      float b0 = 0.f, b1 = 0.f, b2 = 0.f, tr = Tr[m];
+      for (int i = 0; i < cnt; ++i) {
+        const int j = my_list[i];
+        const float4 p = s_pos[j];
+        const float4 c = s_col[j];
+        const float dx = (px - p.x) + p.y;
+        const float dy = (py - p.z) + p.w;
+        const float qq = (dx * dx + dy * dy) * c.x;
+        if (qq <= qmax) {
+          const float e = __builtin_amdgcn_exp2f(-qq);
+          const float x = s_ap[j] * e;
+          float phi, em;  // phi(x), exp(-x) - 1
+          if (x < 0.5f) {
+            phi = fmaf(x, -1.f / 40320.f, 1.f / 5040.f);
+            phi = fmaf(x, phi, -1.f / 720.f);
+            phi = fmaf(x, phi, 1.f / 120.f);
+            phi = fmaf(x, phi, -1.f / 24.f);
+            phi = fmaf(x, phi, 1.f / 6.f);
+            phi = fmaf(x, phi, -0.5f);
+            phi = fmaf(x, phi, 1.f);
+            em = -x * phi;
+          } else {
+            em = __builtin_amdgcn_exp2f(-x * kLog2e) - 1.f;
+            phi = -em / x;
+          }
+          const float tw = tr * e * phi;
+          b0 = fmaf(tw, c.y, b0);
+          b1 = fmaf(tw, c.z, b1);
+          b2 = fmaf(tw, c.w, b2);
+          tr = fmaf(tr, em, tr);
         }
       }
+      Tr[m] = tr;
+      neumaier(C[m][0], Cc[m][0], b0);
+      neumaier(C[m][1], Cc[m][1], b1);
+      neumaier(C[m][2], Cc[m][2], b2);
+      __builtin_amdgcn_wave_barrier();
     }
-#pragma unroll
-    for (int m = 0; m < PX; ++m)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        neumaier(C[m][c], Cc[m][c], Cb[m][c]);
-        Cb[m][c] = 0.f;
-      }
     __syncthreads();
   }
 #pragma unroll
-  for (int m = 0; m < PX; ++m) {
-    const int lx = pc, ly = pr0 + m;
+  for (int m = 0; m < MT; ++m) {
+    const int q = grp + 16 * m;
+    const int lpx = (q % MX) * 4 + lx, lpy = (q / MX) * 4 + ly;
     if (multi) {
-      partial[(size_t)blockIdx.x * NP + ly * T + lx] =
+      partial[(size_t)blockIdx.x * NP + lpy * T + lpx] =
           make_float4(C[m][0] + Cc[m][0], C[m][1] + Cc[m][1], C[m][2] + Cc[m][2], Tr[m]);
     } else {
-      const int gx = x0 + lx, gy = y0 + ly;
+      const int gx = x0 + lpx, gy = y0 + lpy;
       if (gx < tk.W && gy < tk.H) {
         float *o = img + 3 * ((size_t)gy * tk.W + gx);
 #pragma unroll
