@@ -273,19 +273,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
                                                        Totals *__restrict__ tot) {
   __shared__ unsigned long long s[4][kScanThreads];
   __shared__ unsigned int s_max, s_nef, s_nec;
+  __shared__ unsigned long long s_l2;
   const int t = threadIdx.x;
   if (t == 0) {
     s_max = 0;
     s_nef = 0;
     s_nec = 0;
+    s_l2 = 0;
   }
   const int per = (nb + kScanThreads - 1) / kScanThreads;
   const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
   unsigned long long loc[4] = {0, 0, 0, 0};
   unsigned int mx = 0, nef = 0, nec = 0;
+  unsigned long long l2 = 0;
   for (int b = b0; b < b1; ++b) {
     const uint32_t c = counts[b];
     loc[0] += c;
+    if (items_for(c, b, n_fine, a.chunk[2], a.cchunk[2], a.minc[2])) l2 += c;
     for (int k = 0; k < 3; ++k) loc[1 + k] += items_for(c, b, n_fine, a.chunk[k], a.cchunk[k], a.minc[k]);
     if (b < n_fine && c > mx) mx = c;
     if (c) {
@@ -300,6 +304,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   if (mx) atomicMax(&s_max, mx);
   if (nef) atomicAdd(&s_nef, nef);
   if (nec) atomicAdd(&s_nec, nec);
+  if (l2) atomicAdd(&s_l2, l2);
   // inclusive Hillis-Steele scan of the per-thread sums
   for (int d = 1; d < kScanThreads; d <<= 1) {
     unsigned long long v[4];
@@ -337,6 +342,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
       tot->max_count = s_max;
       tot->n_fine_nonempty = s_nef;
       tot->n_coarse_nonempty = s_nec;
+      tot->n_list2_pairs = s_l2;
     }
   }
 }

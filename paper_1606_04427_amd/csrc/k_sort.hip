@@ -7,9 +7,8 @@
 //  k_sort_chunks  one workgroup per list chunk of <= 4096 keys: bitonic sort
 //                 in LDS (32 KB).  A list that fits one chunk is done.
 //  k_merge_pass   longer lists: sorted runs of length L merged pairwise into
-//                 runs of 2L; one workgroup per 2048 outputs, each lane finds
-//                 its start on the merge path by binary search and merges 8
-//                 keys.
+//                 runs of 2L; one workgroup per 2048 outputs stages its inputs
+//                 in LDS, each lane merges 8 keys.
 #include "spl_internal.h"
 
 namespace spl {
@@ -47,42 +46,88 @@ __global__ __launch_bounds__(kBlock) void k_sort_chunks(unsigned long long *__re
   for (int i = threadIdx.x; i < n; i += kBlock) keys[it.y + i] = s[i];
 }
 
+// First i in [lo, hi) with A[i] >= B[diag - 1 - i] (hi if none): the start
+// of the merge path's crossing of diagonal `diag`.  One wave tests 64 evenly
+// spaced candidates per round and keeps the bracket where the predicate turns,
+// so a search over L candidates takes log64(L) rounds of global loads.
+__device__ __forceinline__ int64_t wave_merge_split(const unsigned long long *__restrict__ A,
+                                                    const unsigned long long *__restrict__ B,
+                                                    int64_t diag, int64_t lo, int64_t hi) {
+  const int lane = __lane_id();
+  while (hi > lo) {  // uniform across the wave
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t i = lo + (int64_t)lane * step;
+    const bool p = i < hi && A[i] < B[diag - 1 - i];
+    const int c = __popcll(__ballot(p));  // the true candidates form a prefix
+    if (c == 0) {
+      hi = lo;
+    } else {
+      const int64_t nlo = lo + (int64_t)(c - 1) * step + 1;
+      hi = min(hi, lo + (int64_t)c * step);
+      lo = nlo;
+    }
+  }
+  return lo;
+}
+
+// One merge pass: sorted runs of length L merged pairwise into runs of 2L.
+// A workgroup owns kMergeOut consecutive outputs of one list (they fall in one
+// pair of runs because 2L is a multiple of kMergeOut).  Waves 0 and 1 find
+// where the merge path enters and leaves that output range, the inputs
+// between are staged in LDS with coalesced loads, and each lane merges 8
+// outputs from LDS after a binary search there.
 __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long *__restrict__ src,
                                                        unsigned long long *__restrict__ dst,
                                                        const Item *__restrict__ items,
                                                        const uint32_t *__restrict__ offsets,
                                                        const uint32_t *__restrict__ counts,
                                                        int64_t L) {
+  __shared__ unsigned long long s_k[kMergeOut];
+  __shared__ int64_t s_split[2];
   const Item it = items[blockIdx.x];
   const int64_t s0 = offsets[it.x];
   const int64_t n = counts[it.x];
-  const int64_t d = ((int64_t)it.y - s0) + 8 * (int64_t)threadIdx.x;
-  if (d >= (int64_t)it.z - s0) return;
-  const int64_t ps = (d / (2 * L)) * (2 * L);
+  const int64_t d0 = (int64_t)it.y - s0, d1 = (int64_t)it.z - s0;
+  const int64_t ps = (d0 / (2 * L)) * (2 * L);
   const int64_t la = min(L, n - ps);
   const int64_t lb = max((int64_t)0, min(L, n - ps - L));
-  const int64_t diag = d - ps;
   const unsigned long long *A = src + s0 + ps;
   const unsigned long long *B = A + L;
-  int64_t lo = max((int64_t)0, diag - lb), hi = min(diag, la);
+  const int wave = threadIdx.x >> 6;
+  if (wave < 2) {
+    const int64_t diag = (wave == 0 ? d0 : d1) - ps;
+    const int64_t a = wave_merge_split(A, B, diag, max((int64_t)0, diag - lb), min(diag, la));
+    if (__lane_id() == 0) s_split[wave] = a;
+  }
+  __syncthreads();
+  const int64_t a0 = s_split[0], a1 = s_split[1];
+  const int64_t b0 = (d0 - ps) - a0, b1 = (d1 - ps) - a1;
+  const int na = (int)(a1 - a0), nb = (int)(b1 - b0);
+  for (int i = threadIdx.x; i < na; i += kBlock) s_k[i] = A[a0 + i];
+  for (int i = threadIdx.x; i < nb; i += kBlock) s_k[na + i] = B[b0 + i];
+  __syncthreads();
+  const int tot = na + nb;
+  const int dl = 8 * (int)threadIdx.x;
+  if (dl >= tot) return;
+  const unsigned long long *As = s_k, *Bs = s_k + na;
+  int lo = max(0, dl - nb), hi = min(dl, na);
   while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (A[mid] < B[diag - 1 - mid])
+    const int mid = (lo + hi) >> 1;
+    if (As[mid] < Bs[dl - 1 - mid])
       lo = mid + 1;
     else
       hi = mid;
   }
-  int64_t i = lo, j = diag - lo;
-  unsigned long long *out = dst + s0 + ps;
-  for (int o = 0; o < 8; ++o) {
-    const int64_t q = diag + o;
-    if (q >= la + lb) break;
+  int i = lo, j = dl - lo;
+  unsigned long long *out = dst + s0 + d0 + dl;
+  const int cnt = min(8, tot - dl);
+  for (int o = 0; o < cnt; ++o) {
     unsigned long long v;
-    if (j >= lb || (i < la && A[i] < B[j]))
-      v = A[i++];
+    if (j >= nb || (i < na && As[i] < Bs[j]))
+      v = As[i++];
     else
-      v = B[j++];
-    out[q] = v;
+      v = Bs[j++];
+    out[o] = v;
   }
 }
 

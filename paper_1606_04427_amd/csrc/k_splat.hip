@@ -349,6 +349,8 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ items,
                                                       const unsigned long long *__restrict__ keys,
+                                                      const unsigned long long *__restrict__ keys_long,
+                                                      uint32_t long_min,
                                                       const float4 *__restrict__ rec,
                                                       const float2 *__restrict__ rec2,
                                                       const uint32_t *__restrict__ counts,
@@ -369,7 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   const Item it = items[blockIdx.x];
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
-  const bool multi = counts[it.x] > (uint32_t)chunk;
+  const uint32_t cnt_tile = counts[it.x];
+  const bool multi = cnt_tile > (uint32_t)chunk;
+  // lists longer than long_min were merged and may live in the other buffer
+  const unsigned long long *const src = cnt_tile > long_min ? keys_long : keys;
   const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
@@ -389,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
     const uint32_t k = base + tid;
     uint32_t box = kEmpty;
     if (k < it.z) {
-      const uint32_t pid = (uint32_t)(keys[k] & 0xffffffffull);
+      const uint32_t pid = (uint32_t)(src[k] & 0xffffffffull);
       const float4 r0 = rec[2 * (size_t)pid];
       const float4 r1 = rec[2 * (size_t)pid + 1];
       int i0, i1, j0, j1;
@@ -562,7 +567,8 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
 }
 
 hipError_t launch_composite(int tile, const Item *items, int n_items,
-                            const unsigned long long *keys, const float *rec, const float *rec2,
+                            const unsigned long long *keys, const unsigned long long *keys_long,
+                            uint32_t long_min, const float *rec, const float *rec2,
                             const uint32_t *counts, int chunk, const TileK &tk, float *img,
                             float *partial, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
@@ -570,10 +576,10 @@ hipError_t launch_composite(int tile, const Item *items, int n_items,
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   float4 *pp = reinterpret_cast<float4 *>(partial);
   if (tile == 16)
-    hipLaunchKernelGGL(k_composite<16>, dim3(n_items), dim3(kBlock), 0, s, items, keys, r, r2,
+    hipLaunchKernelGGL(k_composite<16>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_long, long_min, r, r2,
                        counts, chunk, tk, img, pp);
   else if (tile == 32)
-    hipLaunchKernelGGL(k_composite<32>, dim3(n_items), dim3(kBlock), 0, s, items, keys, r, r2,
+    hipLaunchKernelGGL(k_composite<32>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_long, long_min, r, r2,
                        counts, chunk, tk, img, pp);
   else
     return hipErrorInvalidValue;

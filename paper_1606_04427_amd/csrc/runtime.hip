@@ -414,14 +414,15 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
                                   (int)L, s));
       ++passes;
     }
-    if (passes % 2)
-      HIPTRY(c, launch_copy_items(keysB, keysA, (const Item *)c->items[2].p, (int)T.n_items[2], s));
+    // merged lists end in B after an odd number of passes; the composite
+    // reads them there
+    unsigned long long *keys_long = passes % 2 ? keysB : keysA;
     mark(tf, 6, s);
     HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
     mark(tf, 7, s);
     const int ni = (int)T.n_items[0];
     TRY(ensure(c, c->partial, (size_t)ni * tk.tile * tk.tile * 16));
-    HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, f.rec, f.rec2, counts, kChunkSplat, tk,
+    HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, keys_long, (uint32_t)kSortChunk, f.rec, f.rec2, counts, kChunkSplat, tk,
                                f.out, (float *)c->partial.p, s));
     HIPTRY(c, launch_composite_merge(tk.tile, items0, ni, counts, kChunkSplat, tk,
                                      (const float *)c->partial.p, f.out, s));
@@ -443,7 +444,9 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     B[2] = 4.0 * nb * 3.0;
     B[3] = 16.0 * (double)(T.n_items[0] + T.n_items[1] + T.n_items[2]);
     B[4] = n * 8.0 + pairs * (sorted ? 8.0 : 4.0);
-    B[5] = sorted ? pairs * 16.0 * (1.0 + passes) : 0.0;
+    // chunk sort: every key read and written once; each merge pass: the
+    // keys of the merged lists
+    B[5] = sorted ? pairs * 16.0 + (double)T.n_list2_pairs * 16.0 * passes : 0.0;
     if (!sorted) {
       B[6] = 12.0 * npx + large * 36.0 +
              24.0 * std::min((double)npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);

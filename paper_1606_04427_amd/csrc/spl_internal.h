@@ -77,6 +77,7 @@ struct Totals {
   unsigned int n_fine_nonempty;     // fine bins with at least one entry
   unsigned int n_coarse_nonempty;   // large-particle bins with at least one entry
   unsigned int pad;
+  unsigned long long n_list2_pairs; // entries of the bins counted by item list 2
 };
 
 // ---------------------------------------------------------------------------
@@ -220,8 +221,8 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
                               uint32_t *next_large, int chunk, int cchunk, int grid, hipStream_t s);
 hipError_t launch_composite(int tile, const Item *items, int n_items,
-                            const unsigned long long *keys, const float *rec,
-                            const float *rec2, const uint32_t *counts, int chunk,
+                            const unsigned long long *keys, const unsigned long long *keys_long,
+                            uint32_t long_min, const float *rec, const float *rec2, const uint32_t *counts, int chunk,
                             const TileK &tk, float *img, float *partial, hipStream_t s);
 hipError_t launch_composite_merge(int tile, const Item *items, int n_items,
                                   const uint32_t *counts, int chunk, const TileK &tk,
