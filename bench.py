@@ -158,6 +158,35 @@ def roofline_for(B, ms, by, frames, updates_per_frame=None):
             "ms_per_launch": per_launch, "bytes_per_launch": by[dom] / max(frames, 1)}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_splat_additive_10M_1024x1024.txt")
+
+
+def source_digest(names):
+    import hashlib
+
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1606_04427_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, n, tile, cut):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    profile (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    there is none for this kernel, workload and configuration, or when the
+    kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.loads(f.read().split("```json")[1].split("```")[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if (rec.get("kernel") != kernel or rec.get("n") != n or rec.get("tile") != tile
+            or rec.get("cut") != cut or rec.get("digest") != source_digest(rec["sources"])):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def base_record(args, value, ms_per_step, dtype, config):
     return {"metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -178,7 +207,12 @@ def run_additive(args, torch, B):
     torch.cuda.synchronize()
 
     tile, cut = 16, 32.0
-    if not args.no_autotune:
+    if args.tile:
+        # fixed configuration (profiling runs repeat the tuned one)
+        tile, cut = args.tile, args.cut
+        prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals, dev), looks, tile=tile,
+                            large_cut=cut)
+    elif not args.no_autotune:
         tile, cut = ctx.spl_autotune(parts, poses[0], prm)
         log(f"autotune: tile {tile}, large cut {cut}")
 
@@ -203,6 +237,7 @@ def run_additive(args, torch, B):
         del rec
     updates /= len(poses)
     roofline = roofline_for(B, ms, by, frames, updates)
+    roofline["traffic"] = measured_traffic(roofline["kernel"], ps.n, tile, cut)
 
     # the same step through the batched entry point (one call for all poses)
     batched = {}
@@ -226,6 +261,15 @@ def run_additive(args, torch, B):
             "particles_per_s": args.steps * len(poses) * ps.n / dt}
     ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
     log("batched: " + json.dumps(batched))
+    if args.copy_probe_gib:
+        # a plain device copy of known size: the reference point that scales
+        # the HBM byte counters of a profiling run
+        nb = int(args.copy_probe_gib * (1 << 30)) // 4
+        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     frame_bytes = sum(by[k] for k in range(len(B.STAGES)) if B.STAGES[k] != "host_gap_items")
     frame_bytes /= max(frames, 1)
@@ -282,11 +326,14 @@ def run_sorted(args, torch, B):
         "workload": "Soneira-Peebles clustered set, 10M particles with absorption U[0.01,0.5], "
                     "2048x2048, depth-sorted transfer, FP32", "n_particles": ps.n,
         "image": [2048, 2048], "poses": 1, "tile": st["tile"]})
-    out.update({"roofline": roofline_for(B, ms, by, frames), "stages": stage_table(B, ms, by, frames),
+    roof = roofline_for(B, ms, by, frames)
+    if roof["kernel"] == "k_splat_add":
+        roof["kernel"] = "k_composite"  # the sorted mode's splat stage
+    out.update({"roofline": roof, "stages": stage_table(B, ms, by, frames),
                 "frame": {"n_active": st["n_active"], "n_pairs": st["n_pairs"]}})
     ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ps, [pose], looks, pals, args.cpu_sample or 2_000_000,
+        out["cpu_baseline"] = cpu_baseline(ps, [pose], looks, pals, args.cpu_sample or ps.n,
                                            B.SPL_SORTED)
     return out
 
@@ -344,6 +391,7 @@ def run_batched(args, torch, B):
         L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
         RP = R.Particles(sub)
         errs = []
+        t_err = time.time()
         for p in poses[: args.error_views]:
             g, _ = ctx.spl_render(sparts, p, prm)
             want = R.render(RP, p, R.params(R.ADD_AEQE, L))
@@ -354,6 +402,8 @@ def run_batched(args, torch, B):
                          "max_abs": float(np.abs(got - want).max()),
                          "max_ref": float(np.abs(want).max())})
         res["error_vs_fp64_oracle_1M_subsample"] = errs
+        log(f"{dt_name} error check on {len(errs)} views in {time.time() - t_err:.1f} s: "
+            + ", ".join(f"{e['rel_l2']:.2e}" for e in errs))
         results[dt_name] = res
         ctx.close()
         del sparts
@@ -401,7 +451,10 @@ def run_serving(args, torch, B):
     result = {}
     # plain path: one request per call on one stream, closed loop (capacity)
     ex = serve.GpuExecutor(parts, bank)
-    serve.one_per_call(ex, make(args.warm_requests, 10_000), keep=keep)
+    warm = make(args.warm_requests, 10_000)
+    for r in warm:
+        r.pose.width = r.pose.height = max(sizes)
+    serve.one_per_call(ex, warm, keep=keep)
     base = serve.one_per_call(ex, make(args.requests, 20_000), keep=keep)
     cap = serve.summary(base)
     result["one_per_call_closed_loop"] = cap
@@ -414,7 +467,12 @@ def run_serving(args, torch, B):
                             max_views=args.max_views, cost=cost, keep=keep).start()
 
     srv = server()
-    serve.drive(srv, make(args.warm_requests, 30_000), np.zeros(args.warm_requests))
+    # warm-up: full batches of the largest views on every worker, so the
+    # workspaces reach their final size before timing
+    warm = make(args.workers * args.max_views, 30_000)
+    for r in warm:
+        r.pose.width = r.pose.height = max(sizes)
+    serve.drive(srv, warm, np.zeros(len(warm)))
     reqs = make(args.requests, 40_000)
     serve.drive(srv, reqs, np.zeros(len(reqs)))
     closed = serve.summary(reqs)
@@ -459,6 +517,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="additive: fixed tile (no autotune)")
+    ap.add_argument("--cut", type=float, default=32.0, help="additive: fixed large cut with --tile")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="additive: also run one plain device copy of this size")
     ap.add_argument("--dtypes", default="bf16,f16", help="batched: attribute dtypes")
     ap.add_argument("--views", type=int, default=64, help="batched: views per step")
     ap.add_argument("--error-views", type=int, default=4, help="batched: views checked")
