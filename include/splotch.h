@@ -214,8 +214,13 @@ spl_status spl_set_timing(spl_ctx *ctx, int32_t enable);
  *                       list-size synchronisation as a HIP graph and replays it.
  *  SPL_OPT_BATCH_BYTES  device bytes spl_render_batch may use for per-view
  *                       workspace; views beyond it go to later launches
- *                       (default 48 GiB). */
-enum { SPL_OPT_TIMING = 0, SPL_OPT_GRAPHS = 1, SPL_OPT_BATCH_BYTES = 2 };
+ *                       (default 48 GiB).
+ *  SPL_OPT_BATCH_PAIRS  tile-list entries one persistent splat launch of
+ *                       spl_render_batch may hold (1 .. 2^32 - 2, the default);
+ *                       views beyond it go to the next launch, which reuses
+ *                       the list buffers.  A single view with more entries
+ *                       is rendered alone. */
+enum { SPL_OPT_TIMING = 0, SPL_OPT_GRAPHS = 1, SPL_OPT_BATCH_BYTES = 2, SPL_OPT_BATCH_PAIRS = 3 };
 spl_status spl_set_option(spl_ctx *ctx, int32_t option, int64_t value);
 spl_status spl_get_timing(spl_ctx *ctx, double *ms, double *bytes, int64_t *frames);
 

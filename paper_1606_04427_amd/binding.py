@@ -24,7 +24,7 @@ EXPORTS = ["spl_create", "spl_destroy", "spl_last_error", "spl_workspace_bytes",
            "spl_scalar_range", "spl_project", "spl_bin", "spl_render_records", "spl_render",
            "spl_render_batch", "spl_autotune", "spl_set_timing", "spl_get_timing",
            "spl_set_option"]
-SPL_OPT_TIMING, SPL_OPT_GRAPHS, SPL_OPT_BATCH_BYTES = 0, 1, 2
+SPL_OPT_TIMING, SPL_OPT_GRAPHS, SPL_OPT_BATCH_BYTES, SPL_OPT_BATCH_PAIRS = 0, 1, 2, 3
 SPL_N_STAGES = 9
 STAGES = ["project", "count", "scan", "host_gap_items", "scatter", "sort", "large_splat",
           "splat", "finalise"]

@@ -550,17 +550,30 @@ hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pa
   return hipGetLastError();
 }
 
+// Persistent launches: as many workgroups as the device holds at once.
+template <class K>
+static int resident_grid(K kernel, int threads, int n_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * n_cu;
+}
+
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
-                              uint32_t *next_large, int chunk, int cchunk, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_splat_large_views, dim3(grid), dim3(kLargeThreads), 0, s, views, large,
-                     n_large, next_large, cchunk);
+                              uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s) {
+  hipLaunchKernelGGL(k_splat_large_views,
+                     dim3(resident_grid(k_splat_large_views, kLargeThreads, n_cu)),
+                     dim3(kLargeThreads), 0, s, views, large, n_large, next_large, cchunk);
   if (tile == 16)
-    hipLaunchKernelGGL((k_splat_add_views<16>), dim3(grid), dim3(kBlock), 0, s, views, fine,
-                       n_fine, next_fine, chunk);
+    hipLaunchKernelGGL((k_splat_add_views<16>),
+                       dim3(resident_grid(k_splat_add_views<16>, kBlock, n_cu)), dim3(kBlock), 0,
+                       s, views, fine, n_fine, next_fine, chunk);
   else if (tile == 32)
-    hipLaunchKernelGGL((k_splat_add_views<32>), dim3(grid), dim3(kBlock), 0, s, views, fine,
-                       n_fine, next_fine, chunk);
+    hipLaunchKernelGGL((k_splat_add_views<32>),
+                       dim3(resident_grid(k_splat_add_views<32>, kBlock, n_cu)), dim3(kBlock), 0,
+                       s, views, fine, n_fine, next_fine, chunk);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

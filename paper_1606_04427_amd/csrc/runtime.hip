@@ -74,6 +74,7 @@ struct spl_ctx {
   hipStream_t cap_stream = nullptr;   // capture stream for batch graphs
   hipGraphExec_t gexec = nullptr;     // last instantiated batch graph
   int64_t budget = (int64_t)48 << 30;
+  uint64_t group_pairs = 0xfffffffeull;  // list entries per persistent launch
   int n_cu = 256;
 };
 
@@ -548,7 +549,7 @@ spl_status ensure_host(spl_ctx *c, int views) {
   c->h_cap = 0;
   if (hipHostMalloc((void **)&c->h_btot, sizeof(Totals) * views, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_views, sizeof(ViewK) * views, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_ctr, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_ctr, 2 * sizeof(uint32_t) * views, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_bstats, 8 * sizeof(double) * views, hipHostMallocDefault) != hipSuccess)
     return fail(c, SPL_ENOMEM, "pinned host allocation failed");
   c->h_cap = views;
@@ -598,23 +599,45 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   }
   HIPTRY(c, hipMemcpyAsync(c->h_btot, tot, sizeof(Totals) * nv, hipMemcpyDeviceToHost, s));
   HIPTRY(c, hipStreamSynchronize(s));
-  std::vector<uint64_t> pb(nv), fb(nv), cb(nv);
-  uint64_t pairs_total = 0, fine_total = 0, coarse_total = 0;
-  for (int v = 0; v < nv; ++v) {
-    const Totals &T = c->h_btot[v];
-    pb[v] = pairs_total;
-    fb[v] = fine_total;
-    cb[v] = coarse_total;
-    pairs_total += T.n_pairs;
-    fine_total += T.n_fine_items[0];
-    coarse_total += T.n_items[0] - T.n_fine_items[0];
+  // views are split into groups whose lists fit 32-bit offsets; the groups
+  // run one after another on the stream and reuse the list buffers
+  std::vector<int> g0s;
+  std::vector<uint64_t> pb(nv), fb(nv), cb(nv), gfine, gcoarse;
+  uint64_t max_p = 0, max_f = 0, max_c = 0;
+  {
+    uint64_t p_run = 0, f_run = 0, c_run = 0;
+    for (int v = 0; v < nv; ++v) {
+      const Totals &T = c->h_btot[v];
+      const uint64_t fi = T.n_fine_items[0], ci = T.n_items[0] - T.n_fine_items[0];
+      if (T.n_pairs >= 0xffffffffull || fi > 0x7fffffffull || ci > 0x7fffffffull)
+        return fail(c, SPL_EUNSUPPORTED, "view %d: lists too long (%llu entries)", v,
+                    (unsigned long long)T.n_pairs);
+      if (g0s.empty() || p_run + T.n_pairs > c->group_pairs || f_run + fi > 0x7fffffffull ||
+          c_run + ci > 0x7fffffffull) {
+        g0s.push_back(v);
+        gfine.push_back(0);
+        gcoarse.push_back(0);
+        p_run = f_run = c_run = 0;
+      }
+      pb[v] = p_run;
+      fb[v] = f_run;
+      cb[v] = c_run;
+      p_run += T.n_pairs;
+      f_run += fi;
+      c_run += ci;
+      gfine.back() = f_run;
+      gcoarse.back() = c_run;
+      max_p = std::max(max_p, p_run);
+      max_f = std::max(max_f, f_run);
+      max_c = std::max(max_c, c_run);
+    }
   }
-  if (pairs_total >= 0xffffffffull || fine_total > 0x7fffffffull || coarse_total > 0x7fffffffull)
-    return fail(c, SPL_EUNSUPPORTED, "batch lists too long (%llu entries)",
-                (unsigned long long)pairs_total);
-  TRY(ensure(c, c->b_pairs, pairs_total * 4));
-  TRY(ensure(c, c->b_itf, fine_total * sizeof(Item)));
-  TRY(ensure(c, c->b_itc, coarse_total * sizeof(Item)));
+  const int ng = (int)g0s.size();
+  g0s.push_back(nv);
+  TRY(ensure(c, c->b_pairs, max_p * 4));
+  TRY(ensure(c, c->b_itf, max_f * sizeof(Item)));
+  TRY(ensure(c, c->b_itc, max_c * sizeof(Item)));
+  TRY(ensure(c, c->b_ctr, (size_t)ng * 4 * sizeof(uint32_t)));
   uint32_t *pairs = (uint32_t *)c->b_pairs.p;
   Item *itf = (Item *)c->b_itf.p, *itc = (Item *)c->b_itc.p;
   for (int v = 0; v < nv; ++v) {
@@ -625,38 +648,45 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     vk.rec = reinterpret_cast<const float4 *>(rec + (size_t)v * n * 8);
     vk.img = outs[v];
   }
-  c->h_ctr[0] = (uint32_t)fine_total;
-  c->h_ctr[1] = (uint32_t)coarse_total;
+  for (int g = 0; g < ng; ++g) {
+    c->h_ctr[2 * g] = (uint32_t)gfine[g];
+    c->h_ctr[2 * g + 1] = (uint32_t)gcoarse[g];
+  }
   // everything after the synchronisation depends only on the list sizes just
   // read; it is enqueued as one unit, directly or as a captured graph
   auto post = [&](hipStream_t q) -> spl_status {
-    for (int v = 0; v < nv; ++v) {
-      const Totals &T = c->h_btot[v];
-      const int nb = tk[v].n_tiles + tk[v].n_ctiles;
-      if (T.n_items[0])
-        HIPTRY(c, launch_build_items(counts + v * bstride, offsets + v * bstride, nb,
-                                     tk[v].n_tiles, kChunkSplat, kChunkLarge, 1,
-                                     itemoff + v * 3 * bstride, itf + fb[v], q, itc + cb[v],
-                                     (uint32_t)T.n_fine_items[0], (uint32_t)v));
-      HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n, tk[v],
-                               cursor + v * bstride, pairs + pb[v], nullptr, q));
-      HIPTRY(c, launch_fill_f32(outs[v], 0.0f, 3 * (int64_t)tk[v].W * tk[v].H, q));
-    }
-    HIPTRY(c, hipMemcpyAsync(c->b_views.p, c->h_views, sizeof(ViewK) * nv, hipMemcpyHostToDevice,
-                             q));
-    HIPTRY(c, hipMemcpyAsync(c->b_ctr.p, c->h_ctr, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, q));
-    uint32_t *ctr = (uint32_t *)c->b_ctr.p;
-    HIPTRY(c, launch_fill_u32(ctr + 2, 0u, 2, q));
-    HIPTRY(c, launch_splat_views(tk[0].tile, (const ViewK *)c->b_views.p, itf, ctr, ctr + 2, itc,
-                                 ctr + 1, ctr + 3, kChunkSplat, kChunkLarge, 4 * c->n_cu, q));
-    double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
-    for (int v = 0; v < nv; ++v) {
-      const int64_t npx = (int64_t)tk[v].W * tk[v].H;
-      const int fbk = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
-      HIPTRY(c, launch_finalise(outs[v], npx, prm[v]->mode == SPL_ADD_AEQE,
-                                fin + (size_t)v * kFinBlocks * 6, fbk, q));
-      HIPTRY(c, launch_reduce_stats(fin + (size_t)v * kFinBlocks * 6, fbk, stats + 8 * v, q));
-      if (prm[v]->normalise) HIPTRY(c, launch_normalise(outs[v], npx, stats + 8 * v, q));
+    for (int g = 0; g < ng; ++g) {
+      const int v0 = g0s[g], v1 = g0s[g + 1];
+      for (int v = v0; v < v1; ++v) {
+        const Totals &T = c->h_btot[v];
+        const int nb = tk[v].n_tiles + tk[v].n_ctiles;
+        if (T.n_items[0])
+          HIPTRY(c, launch_build_items(counts + v * bstride, offsets + v * bstride, nb,
+                                       tk[v].n_tiles, kChunkSplat, kChunkLarge, 1,
+                                       itemoff + v * 3 * bstride, itf + fb[v], q, itc + cb[v],
+                                       (uint32_t)T.n_fine_items[0], (uint32_t)(v - v0)));
+        HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n,
+                                 tk[v], cursor + v * bstride, pairs + pb[v], nullptr, q));
+        HIPTRY(c, launch_fill_f32(outs[v], 0.0f, 3 * (int64_t)tk[v].W * tk[v].H, q));
+      }
+      ViewK *dviews = (ViewK *)c->b_views.p + v0;
+      uint32_t *ctr = (uint32_t *)c->b_ctr.p + 4 * g;
+      HIPTRY(c, hipMemcpyAsync(dviews, c->h_views + v0, sizeof(ViewK) * (v1 - v0),
+                               hipMemcpyHostToDevice, q));
+      HIPTRY(c, hipMemcpyAsync(ctr, c->h_ctr + 2 * g, 2 * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               q));
+      HIPTRY(c, launch_fill_u32(ctr + 2, 0u, 2, q));
+      HIPTRY(c, launch_splat_views(tk[0].tile, dviews, itf, ctr, ctr + 2, itc, ctr + 1, ctr + 3,
+                                   kChunkSplat, kChunkLarge, c->n_cu, q));
+      double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
+      for (int v = v0; v < v1; ++v) {
+        const int64_t npx = (int64_t)tk[v].W * tk[v].H;
+        const int fbk = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
+        HIPTRY(c, launch_finalise(outs[v], npx, prm[v]->mode == SPL_ADD_AEQE,
+                                  fin + (size_t)v * kFinBlocks * 6, fbk, q));
+        HIPTRY(c, launch_reduce_stats(fin + (size_t)v * kFinBlocks * 6, fbk, stats + 8 * v, q));
+        if (prm[v]->normalise) HIPTRY(c, launch_normalise(outs[v], npx, stats + 8 * v, q));
+      }
     }
     return SPL_OK;
   };
@@ -1043,6 +1073,11 @@ spl_status spl_set_option(spl_ctx *c, int32_t option, int64_t value) {
     case SPL_OPT_BATCH_BYTES:
       if (value <= 0) return fail(c, SPL_EINVAL, "batch budget must be > 0");
       c->budget = value;
+      return SPL_OK;
+    case SPL_OPT_BATCH_PAIRS:
+      if (value < 1 || value > (int64_t)0xfffffffell)
+        return fail(c, SPL_EINVAL, "list entries per launch must be in 1..2^32-2");
+      c->group_pairs = (uint64_t)value;
       return SPL_OK;
     default:
       return fail(c, SPL_EINVAL, "unknown option %d", option);

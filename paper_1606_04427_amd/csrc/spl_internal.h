@@ -219,7 +219,7 @@ hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pa
 // items first, then fine items; n_* and next_* are device counters.
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
-                              uint32_t *next_large, int chunk, int cchunk, int grid, hipStream_t s);
+                              uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s);
 hipError_t launch_composite(int tile, const Item *items, int n_items,
                             const unsigned long long *keys, const unsigned long long *keys_long,
                             uint32_t long_min, const float *rec, const float *rec2, const uint32_t *counts, int chunk,

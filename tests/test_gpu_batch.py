@@ -93,6 +93,34 @@ def test_batch_budget_splits_launches(env):
         assert rel_l2(y.cpu().numpy(), x) < 1e-6
 
 
+def test_batch_list_limit_splits_launches(env):
+    """A small list-entry limit per persistent launch splits the views into
+    groups that reuse the list buffers; the images must not change."""
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals = _setup(B, n=50_000, seed=54)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    poses = _poses()
+    prms = [B.make_params(1, P, looks, tile=16, large_cut=16.0) for _ in poses]
+    a, sa = ctx.spl_render_batch(parts, poses, prms)
+    torch.cuda.synchronize()
+    a = [x.cpu().numpy() for x in a]
+    for graphs in (0, 1):
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, graphs)
+        ctx.spl_set_option(B.SPL_OPT_BATCH_PAIRS, 60_000)
+        b, sb = ctx.spl_render_batch(parts, poses, prms)
+        ctx.spl_set_option(B.SPL_OPT_BATCH_PAIRS, 0xFFFFFFFE)
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+        torch.cuda.synchronize()
+        for x, y, s1, s2 in zip(a, b, sa, sb):
+            assert rel_l2(y.cpu().numpy(), x) < 1e-6
+            assert s1["n_pairs"] == s2["n_pairs"]
+    with pytest.raises(B.SplotchError):
+        ctx.spl_set_option(B.SPL_OPT_BATCH_PAIRS, 0)
+
+
 def test_batch_rejects_bad_view(env):
     B, ctx, _ = env
     ps, looks, pals = _setup(B, n=1000, seed=53)
