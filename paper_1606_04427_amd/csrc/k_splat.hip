@@ -40,48 +40,47 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 }
 
 // A batch of up to 256 list entries is staged in LDS (offsets, width,
-// premultiplied colour, box inside the tile).  The tile is split into 4 x 4
-// micro-tiles; a 16-lane group owns one micro-tile (T = 16) or four (T = 32),
-// one pixel per lane.  For each of its micro-tiles the group lists, in list
-// order, the staged entries whose box meets the micro-tile (ballot and
-// population count, no atomics), then every lane evaluates its pixel for each
-// listed entry and accumulates in registers.  Batch sums are folded into
-// per-pixel Neumaier-compensated FP32 sums.
+// premultiplied colour).  The tile is split into 4 x 4 micro-tiles and each
+// staged entry appends itself to the list of every micro-tile its box meets
+// (LDS integer atomics; order inside a list is free for a sum).  The
+// micro-tiles are then ranked by list length and handed to the 16-lane groups
+// in rank order, so the four groups of a wave, which run in lockstep, work on
+// lists of similar length; one pixel per lane, sums in registers.  Each
+// pixel's running Neumaier-compensated FP32 sum lives in LDS between batches.
 template <int T>
 __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__restrict__ pairs,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ counts, int chunk,
                                                const TileK &tk, float *__restrict__ img) {
+  constexpr int NP = T * T;
   constexpr int MX = T / 4;            // micro-tiles per tile row
-  constexpr int MT = MX * MX / 16;     // micro-tiles per group
+  constexpr int NQ = MX * MX;          // micro-tiles per tile (16 or 64)
+  constexpr int MT = NQ / 16;          // micro-tiles per group and batch
   constexpr float kLog2e = 1.4426950408889634f;
-  constexpr uint32_t kEmpty = 0x000000ffu | 0x00ff0000u;  // li0 = lj0 = 255 > li1 = lj1 = 0
   __shared__ float4 s_pos[kBlock];     // Xi - x0, 0.5 - Xf, Yi - y0, 0.5 - Yf
   __shared__ float4 s_col[kBlock];     // log2(e)/sigma^2, premultiplied colour
-  __shared__ uint32_t s_box[kBlock];   // li0 | li1 << 8 | lj0 << 16 | lj1 << 24
-  __shared__ __align__(4) uint8_t s_list[16][kBlock];
+  __shared__ __align__(4) uint8_t s_list[NQ][kBlock];
+  __shared__ int s_len[2][NQ];         // list lengths; batches alternate buffers
+  __shared__ int s_order[NQ];          // micro-tiles by decreasing list length
+  __shared__ float s_acc[6][NP];       // per pixel: sum and compensation, 3 channels
 
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
-  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
+  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
-  uint8_t *const my_list = s_list[grp];
 
-  float sum[MT][3], comp[MT][3];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      sum[m][c] = 0.f;
-      comp[m][c] = 0.f;
-    }
+  for (int i = tid; i < 6 * NP; i += kBlock) (&s_acc[0][0])[i] = 0.f;
+  if (tid < 2 * NQ) (&s_len[0][0])[tid] = 0;
+  __syncthreads();
 
-  for (uint32_t base = it.y; base < it.z; base += kBlock) {
-    // stage one list entry per lane
+  int cur = 0;
+  for (uint32_t base = it.y; base < it.z; base += kBlock, cur ^= 1) {
+    int *const len = s_len[cur];
+    // stage one list entry per lane and append it to the list of every
+    // micro-tile its box meets
     const uint32_t k = base + tid;
-    uint32_t box = kEmpty;
     if (k < it.z) {
       const uint32_t pid = pairs[k];
       const float4 r0 = rec[2 * (size_t)pid];
@@ -91,36 +90,36 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
         const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
         if (li0 <= li1 && lj0 <= lj1) {
-          box = pack_box(li0, li1, lj0, lj1);
           s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
           s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
+          for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy)
+            for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
+              const int q = qy * MX + qx;
+              s_list[q][atomicAdd(&len[q], 1)] = (uint8_t)tid;
+            }
         }
       }
     }
-    s_box[tid] = box;
     __syncthreads();
-    const int nb = (int)min((uint32_t)kBlock, it.z - base);
+    // rank the micro-tiles by list length (ties by index)
+    if (tid < NQ) {
+      const int my_len = len[tid];
+      int r = 0;
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const int lu = len[u];
+        r += (lu > my_len) | ((lu == my_len) & (u < tid));
+      }
+      s_order[r] = tid;
+    }
+    __syncthreads();
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-      const int q = grp + 16 * m;
+      const int q = s_order[grp + 16 * m];
+      const int cnt = len[q];
+      if (cnt == 0) continue;  // uniform across the group
+      const uint8_t *const lst = s_list[q];
       const int mx0 = (q % MX) * 4, my0 = (q / MX) * 4;
-      // the group's list: staged entries whose box meets its micro-tile
-      int cnt = 0;
-      for (int s0 = 0; s0 < nb; s0 += 16) {
-        // every slot holds a box (empty past the end of the list)
-        const int j = s0 + l;
-        const uint32_t b = s_box[j];
-        const int bi0 = (int)(b & 0xffu), bi1 = (int)((b >> 8) & 0xffu);
-        const int bj0 = (int)((b >> 16) & 0xffu), bj1 = (int)(b >> 24);
-        const bool hit = (bi0 <= mx0 + 3) & (bi1 >= mx0) & (bj0 <= my0 + 3) & (bj1 >= my0);
-        const uint32_t bits = (uint32_t)(__ballot(hit) >> (16 * gw)) & 0xffffu;
-        if (hit) my_list[cnt + __popc(bits & ((1u << l) - 1u))] = (uint8_t)j;
-        cnt += __popc(bits);
-      }
-      // the list is written and read by the same wave
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const float px = (float)(mx0 + lx), py = (float)(my0 + ly);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
       auto eval = [&](int j) {
@@ -138,30 +137,41 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       };
       int i = 0;
       for (; i + 4 <= cnt; i += 4) {
-        const uint32_t w4 = *reinterpret_cast<const uint32_t *>(my_list + i);
+        const uint32_t w4 = *reinterpret_cast<const uint32_t *>(lst + i);
         eval((int)(w4 & 0xffu));
         eval((int)((w4 >> 8) & 0xffu));
         eval((int)((w4 >> 16) & 0xffu));
         eval((int)(w4 >> 24));
       }
-      for (; i < cnt; ++i) eval((int)my_list[i]);
-      neumaier(sum[m][0], comp[m][0], a0);
-      neumaier(sum[m][1], comp[m][1], a1);
-      neumaier(sum[m][2], comp[m][2], a2);
-      // the next micro-tile's list overwrites this one
-      __builtin_amdgcn_wave_barrier();
+      for (; i < cnt; ++i) eval((int)lst[i]);
+      // fold the batch sums into the pixel's compensated sums; a micro-tile
+      // is handled by one group per batch
+      const int pix = (my0 + ly) * T + (mx0 + lx);
+      float sm0 = s_acc[0][pix], cp0 = s_acc[1][pix];
+      float sm1 = s_acc[2][pix], cp1 = s_acc[3][pix];
+      float sm2 = s_acc[4][pix], cp2 = s_acc[5][pix];
+      neumaier(sm0, cp0, a0);
+      neumaier(sm1, cp1, a1);
+      neumaier(sm2, cp2, a2);
+      s_acc[0][pix] = sm0;
+      s_acc[1][pix] = cp0;
+      s_acc[2][pix] = sm1;
+      s_acc[3][pix] = cp1;
+      s_acc[4][pix] = sm2;
+      s_acc[5][pix] = cp2;
     }
+    // the other length buffer was last read before the previous batch's
+    // final barrier and is next written after this batch's
+    if (tid < NQ) s_len[cur ^ 1][tid] = 0;
     __syncthreads();
   }
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int q = grp + 16 * m;
-    const int gx = x0 + (q % MX) * 4 + lx, gy = y0 + (q / MX) * 4 + ly;
+  for (int pix = tid; pix < NP; pix += kBlock) {
+    const int gx = x0 + pix % T, gy = y0 + pix / T;
     if (gx < tk.W && gy < tk.H) {
       float *o = img + 3 * ((size_t)gy * tk.W + gx);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float v = sum[m][c] + comp[m][c];
+        const float v = s_acc[2 * c][pix] + s_acc[2 * c + 1][pix];
         if (multi)
           unsafeAtomicAdd(o + c, v);
         else
