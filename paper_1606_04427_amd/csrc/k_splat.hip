@@ -42,45 +42,62 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 // A batch of up to 256 list entries is staged in LDS (offsets, width,
 // premultiplied colour).  The tile is split into 4 x 4 micro-tiles and each
 // staged entry appends itself to the list of every micro-tile its box meets
-// (LDS integer atomics; order inside a list is free for a sum).  The
-// micro-tiles are then ranked by list length and handed to the 16-lane groups
-// in rank order, so the four groups of a wave, which run in lockstep, work on
-// lists of similar length; one pixel per lane, sums in registers.  Each
-// pixel's running Neumaier-compensated FP32 sum lives in LDS between batches.
+// (LDS integer atomics; order inside a list is free for a sum).  The lists,
+// laid end to end, are cut into 16 equal ranges, one per 16-lane group; all
+// groups step through their ranges together, one list entry per step, so the
+// four groups of a wave, which run in lockstep, take the same number of steps
+// however unevenly the entries fall on the micro-tiles.  One pixel per lane;
+// the running sum stays in registers while consecutive entries belong to the
+// same micro-tile and is added into a 32-bit fixed-point LDS accumulator
+// (integer atomics: neighbouring ranges may share a micro-tile) when the
+// group moves on.  The batch scale 2^S keeps the batch's summed peak
+// amplitude below 2^30, so no pixel sum overflows.  After each batch the
+// integer sums are folded into per-pixel Neumaier-compensated FP32 sums in
+// registers.
 template <int T>
 __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__restrict__ pairs,
                                                const float4 *__restrict__ rec,
                                                const uint32_t *__restrict__ counts, int chunk,
                                                const TileK &tk, float *__restrict__ img) {
   constexpr int NP = T * T;
+  constexpr int PX = NP / kBlock;      // pixels per lane in the fold
   constexpr int MX = T / 4;            // micro-tiles per tile row
   constexpr int NQ = MX * MX;          // micro-tiles per tile (16 or 64)
-  constexpr int MT = NQ / 16;          // micro-tiles per group and batch
   constexpr float kLog2e = 1.4426950408889634f;
   __shared__ float4 s_pos[kBlock];     // Xi - x0, 0.5 - Xf, Yi - y0, 0.5 - Yf
   __shared__ float4 s_col[kBlock];     // log2(e)/sigma^2, premultiplied colour
   __shared__ __align__(4) uint8_t s_list[NQ][kBlock];
   __shared__ int s_len[2][NQ];         // list lengths; batches alternate buffers
-  __shared__ int s_order[NQ];          // micro-tiles by decreasing list length
-  __shared__ float s_acc[6][NP];       // per pixel: sum and compensation, 3 channels
+  __shared__ int s_start[NQ + 1];      // list offsets laid end to end
+  __shared__ int s_iacc[3][NP];        // batch sums, fixed point
+  __shared__ float s_amp[4];           // per-wave summed peak amplitudes
 
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
-  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
+  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, wave = tid >> 6;
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
 
-  for (int i = tid; i < 6 * NP; i += kBlock) (&s_acc[0][0])[i] = 0.f;
+  float sum[PX][3], comp[PX][3];
+#pragma unroll
+  for (int m = 0; m < PX; ++m)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sum[m][c] = 0.f;
+      comp[m][c] = 0.f;
+    }
+  for (int i = tid; i < 3 * NP; i += kBlock) (&s_iacc[0][0])[i] = 0;
   if (tid < 2 * NQ) (&s_len[0][0])[tid] = 0;
   __syncthreads();
 
   int cur = 0;
   for (uint32_t base = it.y; base < it.z; base += kBlock, cur ^= 1) {
     int *const len = s_len[cur];
-    // stage one list entry per lane and append it to the list of every
-    // micro-tile its box meets
+    // stage one list entry per lane, append it to the list of every
+    // micro-tile its box meets, sum the peak amplitudes
     const uint32_t k = base + tid;
+    float amax = 0.f;
     if (k < it.z) {
       const uint32_t pid = pairs[k];
       const float4 r0 = rec[2 * (size_t)pid];
@@ -92,6 +109,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         if (li0 <= li1 && lj0 <= lj1) {
           s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
           s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
+          amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
           for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy)
             for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
               const int q = qy * MX + qx;
@@ -100,78 +118,102 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         }
       }
     }
-    __syncthreads();
-    // rank the micro-tiles by list length (ties by index)
-    if (tid < NQ) {
-      const int my_len = len[tid];
-      int r = 0;
 #pragma unroll
-      for (int u = 0; u < NQ; ++u) {
-        const int lu = len[u];
-        r += (lu > my_len) | ((lu == my_len) & (u < tid));
+    for (int o = 1; o < 64; o <<= 1) amax += __shfl_xor(amax, o);
+    if ((tid & 63) == 0) s_amp[wave] = amax;
+    __syncthreads();
+    // list offsets (one wave: NQ <= 64)
+    if (tid < 64) {
+      const int v = tid < NQ ? len[tid] : 0;
+      int incl = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (tid >= o) incl += u;
       }
-      s_order[r] = tid;
+      if (tid < NQ) s_start[tid] = incl - v;
+      if (tid == NQ - 1) s_start[NQ] = incl;
     }
     __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int q = s_order[grp + 16 * m];
-      const int cnt = len[q];
-      if (cnt == 0) continue;  // uniform across the group
-      const uint8_t *const lst = s_list[q];
-      const int mx0 = (q % MX) * 4, my0 = (q / MX) * 4;
-      const float px = (float)(mx0 + lx), py = (float)(my0 + ly);
+    int ex = 0;
+    (void)frexpf(s_amp[0] + s_amp[1] + s_amp[2] + s_amp[3], &ex);  // sum <= 2^ex
+    const int S = 30 - ex;
+    {
+      const int total = s_start[NQ];
+      const int steps = (total + 15) >> 4;
+      const int r0 = min(grp * steps, total), r1 = min(r0 + steps, total);
+      // the group's first micro-tile: the first whose list ends after r0
+      int q = 0;
+      while (q < NQ - 1 && s_start[q + 1] <= r0) ++q;
+      int qs = s_start[q], qe = s_start[q + 1];
+      int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
+      float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-      auto eval = [&](int j) {
-        const float4 p = s_pos[j];
-        const float4 c = s_col[j];
-        const float dx = (px - p.x) + p.y;
-        const float dy = (py - p.z) + p.w;
-        const float qq = (dx * dx + dy * dy) * c.x;
-        // qq <= qmax keeps the result far above the denormal range, so the
-        // hardware exponential needs no range fix-up
-        const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
-        a0 += c.y * e;
-        a1 += c.z * e;
-        a2 += c.w * e;
-      };
-      int i = 0;
-      for (; i + 4 <= cnt; i += 4) {
-        const uint32_t w4 = *reinterpret_cast<const uint32_t *>(lst + i);
-        eval((int)(w4 & 0xffu));
-        eval((int)((w4 >> 8) & 0xffu));
-        eval((int)((w4 >> 16) & 0xffu));
-        eval((int)(w4 >> 24));
+#pragma unroll 4
+      for (int t = 0; t < steps; ++t) {  // uniform across the workgroup
+        const int u = r0 + t;
+        if (u < r1) {
+          if (u >= qe) {
+            // next micro-tile: flush the running sums
+            atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
+            atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
+            atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
+            a0 = a1 = a2 = 0.f;
+            do {
+              ++q;
+            } while (s_start[q + 1] <= u);
+            qs = s_start[q];
+            qe = s_start[q + 1];
+            pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
+            px = (float)((q % MX) * 4 + lx);
+            py = (float)((q / MX) * 4 + ly);
+          }
+          const int j = s_list[q][u - qs];
+          const float4 p = s_pos[j];
+          const float4 c = s_col[j];
+          const float dx = (px - p.x) + p.y;
+          const float dy = (py - p.z) + p.w;
+          const float qq = (dx * dx + dy * dy) * c.x;
+          // qq <= qmax keeps the result far above the denormal range, so
+          // the hardware exponential needs no range fix-up
+          const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
+          a0 += c.y * e;
+          a1 += c.z * e;
+          a2 += c.w * e;
+        }
       }
-      for (; i < cnt; ++i) eval((int)lst[i]);
-      // fold the batch sums into the pixel's compensated sums; a micro-tile
-      // is handled by one group per batch
-      const int pix = (my0 + ly) * T + (mx0 + lx);
-      float sm0 = s_acc[0][pix], cp0 = s_acc[1][pix];
-      float sm1 = s_acc[2][pix], cp1 = s_acc[3][pix];
-      float sm2 = s_acc[4][pix], cp2 = s_acc[5][pix];
-      neumaier(sm0, cp0, a0);
-      neumaier(sm1, cp1, a1);
-      neumaier(sm2, cp2, a2);
-      s_acc[0][pix] = sm0;
-      s_acc[1][pix] = cp0;
-      s_acc[2][pix] = sm1;
-      s_acc[3][pix] = cp1;
-      s_acc[4][pix] = sm2;
-      s_acc[5][pix] = cp2;
+      if (r0 < r1) {
+        atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
+        atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
+        atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
+      }
     }
     // the other length buffer was last read before the previous batch's
     // final barrier and is next written after this batch's
     if (tid < NQ) s_len[cur ^ 1][tid] = 0;
     __syncthreads();
+    // fold the batch sums into the compensated per-pixel sums
+#pragma unroll
+    for (int m = 0; m < PX; ++m) {
+      const int p2 = tid + m * kBlock;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int v = s_iacc[c][p2];
+        s_iacc[c][p2] = 0;
+        neumaier(sum[m][c], comp[m][c], ldexpf((float)v, -S));
+      }
+    }
+    __syncthreads();
   }
-  for (int pix = tid; pix < NP; pix += kBlock) {
-    const int gx = x0 + pix % T, gy = y0 + pix / T;
+#pragma unroll
+  for (int m = 0; m < PX; ++m) {
+    const int p2 = tid + m * kBlock;
+    const int gx = x0 + p2 % T, gy = y0 + p2 / T;
     if (gx < tk.W && gy < tk.H) {
       float *o = img + 3 * ((size_t)gy * tk.W + gx);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float v = s_acc[2 * c][pix] + s_acc[2 * c + 1][pix];
+        const float v = sum[m][c] + comp[m][c];
         if (multi)
           unsafeAtomicAdd(o + c, v);
         else
