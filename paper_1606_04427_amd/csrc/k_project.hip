@@ -8,7 +8,7 @@
 // screen position as integer part + fraction.  The colour map lookup runs in
 // FP32.  Output per active particle: a 32-byte record, optionally the 8-byte
 // sorted-mode record, and the 8-byte tile span read by the binning kernels.
-#include "spl_internal.h"
+#include "bin_device.h"
 
 namespace spl {
 
@@ -25,100 +25,122 @@ __device__ __forceinline__ float load_attr(const void *p, int dtype, int64_t i) 
 
 __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
 
+// kCount: the tile counts of the binning stage are accumulated here too, in
+// an LDS histogram per workgroup flushed once at the end, which saves a pass
+// over the spans.
+template <bool kCount>
 __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *__restrict__ rec,
                                                     float2 *__restrict__ rec2,
                                                     uint2 *__restrict__ span, int write_inactive,
-                                                    Totals *__restrict__ tot) {
+                                                    Totals *__restrict__ tot,
+                                                    uint32_t *__restrict__ counts) {
+  extern __shared__ uint32_t hist[];
   __shared__ unsigned int s_act, s_large;
+  const int nb = tk.n_tiles + tk.n_ctiles;
   if (threadIdx.x == 0) {
     s_act = 0;
     s_large = 0;
   }
+  if (kCount)
+    for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
   __syncthreads();
   unsigned int my_act = 0, my_large = 0;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
-  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < P.n; k += stride) {
-    const float x = P.x[k], y = P.y[k], z = P.z[k];
-    const float h = load_attr(P.h, P.dtype, k) * P.h_scale;
-    const float I = load_attr(P.inten, P.dtype, k) * P.i_scale;
-    const float s = load_attr(P.scal, P.dtype, k) * P.s_scale;
-    const int sp = P.species ? (int)P.species[k] : 0;
-    const float a = (P.mode == SPL_SORTED) ? P.absorb[k] : 0.0f;
-    float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    float2 o2 = make_float2(0.f, 0.f);
+  // uniform trip count: the counting helpers need every lane of the wave
+  for (int64_t kb = (int64_t)blockIdx.x * kBlock; kb < P.n; kb += stride) {
+    const int64_t k = kb + threadIdx.x;
     uint2 spn = make_uint2(kInactive, kInactive);
-    bool active = false;
-    if (finitef(x) && finitef(y) && finitef(z) && finitef(h) && finitef(I) && finitef(s) &&
-        finitef(a) && h > 0.0f && a >= 0.0f && sp < P.n_species) {
-      const double vx = (double)x - P.e[0], vy = (double)y - P.e[1], vz = (double)z - P.e[2];
-      const double zv = vx * P.f[0] + vy * P.f[1] + vz * P.f[2];
-      if (zv > P.z_near) {
-        const double xv = vx * P.r[0] + vy * P.r[1] + vz * P.r[2];
-        const double yv = vx * P.u[0] + vy * P.u[1] + vz * P.u[2];
-        const double iz = 1.0 / zv;
-        const double X = P.cx + P.F * xv * iz;
-        const double Y = P.cy - P.F * yv * iz;
-        const double rho = P.F * (double)h * iz;
-        const double ks = P.k_sigma * rho;
-        const double sig = sqrt(ks * ks + P.sigma_min * P.sigma_min);
-        const double R = P.nu * sig;
-        if (fabs(X - P.cx) <= 4194304.0 && fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0) {
-          LookK L = P.looks[0];
-#pragma unroll
-          for (int j = 1; j < SPL_MAX_SPECIES; ++j)
-            if (sp == j) L = P.looks[j];
-          float t;
-          if (L.log10)
-            t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
-          else
-            t = (s - L.lo) * L.inv_range;
-          t = fminf(fmaxf(t, 0.0f), 1.0f);
-          float c0, c1, c2;
-          if (L.M == 1) {
-            c0 = L.rgb[0];
-            c1 = L.rgb[1];
-            c2 = L.rgb[2];
-          } else {
-            const float u = t * (float)(L.M - 1);
-            int j = (int)floorf(u);
-            j = min(max(j, 0), L.M - 2);
-            const float fr = u - (float)j;
-            const float *p0 = L.rgb + 3 * j;
-            c0 = (1.0f - fr) * p0[0] + fr * p0[3];
-            c1 = (1.0f - fr) * p0[1] + fr * p0[4];
-            c2 = (1.0f - fr) * p0[2] + fr * p0[5];
-          }
-          const float bi = L.beta * I;
-          const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
-          const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
-          if (emits || (P.mode == SPL_SORTED && a > 0.0f)) {
-            const double amp = 1.0 / (3.14159265358979323846 * sig * sig);
-            const double fX = floor(X), fY = floor(Y);
-            o0 = make_float4((float)fX, (float)(X - fX), (float)fY, (float)(Y - fY));
-            o1 = make_float4((float)sig, (float)((double)E0 * amp), (float)((double)E1 * amp),
-                             (float)((double)E2 * amp));
-            o2 = make_float2((float)((double)a * amp), (float)zv);
-            spn = record_span(o0, o1.x, tk);
-            active = spn.x != kInactive;
+    if (k < P.n) {
+      const float x = P.x[k], y = P.y[k], z = P.z[k];
+      const float h = load_attr(P.h, P.dtype, k) * P.h_scale;
+      const float I = load_attr(P.inten, P.dtype, k) * P.i_scale;
+      const float s = load_attr(P.scal, P.dtype, k) * P.s_scale;
+      const int sp = P.species ? (int)P.species[k] : 0;
+      const float a = (P.mode == SPL_SORTED) ? P.absorb[k] : 0.0f;
+      float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = make_float4(0.f, 0.f, 0.f, 0.f);
+      float2 o2 = make_float2(0.f, 0.f);
+      bool active = false;
+      if (finitef(x) && finitef(y) && finitef(z) && finitef(h) && finitef(I) && finitef(s) &&
+          finitef(a) && h > 0.0f && a >= 0.0f && sp < P.n_species) {
+        const double vx = (double)x - P.e[0], vy = (double)y - P.e[1], vz = (double)z - P.e[2];
+        const double zv = vx * P.f[0] + vy * P.f[1] + vz * P.f[2];
+        if (zv > P.z_near) {
+          const double xv = vx * P.r[0] + vy * P.r[1] + vz * P.r[2];
+          const double yv = vx * P.u[0] + vy * P.u[1] + vz * P.u[2];
+          const double iz = 1.0 / zv;
+          const double X = P.cx + P.F * xv * iz;
+          const double Y = P.cy - P.F * yv * iz;
+          const double rho = P.F * (double)h * iz;
+          const double ks = P.k_sigma * rho;
+          const double sig = sqrt(ks * ks + P.sigma_min * P.sigma_min);
+          const double R = P.nu * sig;
+          if (fabs(X - P.cx) <= 4194304.0 && fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0) {
+            LookK L = P.looks[0];
+  #pragma unroll
+            for (int j = 1; j < SPL_MAX_SPECIES; ++j)
+              if (sp == j) L = P.looks[j];
+            float t;
+            if (L.log10)
+              t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
+            else
+              t = (s - L.lo) * L.inv_range;
+            t = fminf(fmaxf(t, 0.0f), 1.0f);
+            float c0, c1, c2;
+            if (L.M == 1) {
+              c0 = L.rgb[0];
+              c1 = L.rgb[1];
+              c2 = L.rgb[2];
+            } else {
+              const float u = t * (float)(L.M - 1);
+              int j = (int)floorf(u);
+              j = min(max(j, 0), L.M - 2);
+              const float fr = u - (float)j;
+              const float *p0 = L.rgb + 3 * j;
+              c0 = (1.0f - fr) * p0[0] + fr * p0[3];
+              c1 = (1.0f - fr) * p0[1] + fr * p0[4];
+              c2 = (1.0f - fr) * p0[2] + fr * p0[5];
+            }
+            const float bi = L.beta * I;
+            const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
+            const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
+            if (emits || (P.mode == SPL_SORTED && a > 0.0f)) {
+              const double amp = 1.0 / (3.14159265358979323846 * sig * sig);
+              const double fX = floor(X), fY = floor(Y);
+              o0 = make_float4((float)fX, (float)(X - fX), (float)fY, (float)(Y - fY));
+              o1 = make_float4((float)sig, (float)((double)E0 * amp), (float)((double)E1 * amp),
+                               (float)((double)E2 * amp));
+              o2 = make_float2((float)((double)a * amp), (float)zv);
+              spn = record_span(o0, o1.x, tk);
+              active = spn.x != kInactive;
+            }
           }
         }
       }
-    }
-    if (active) {
-      ++my_act;
-      if (spn.y & kLargeFlag) ++my_large;
-    }
-    if (active || write_inactive) {
-      if (!active) {
-        o0 = make_float4(0.f, 0.f, 0.f, 0.f);
-        o1 = o0;
-        o2 = make_float2(0.f, 0.f);
+      if (active) {
+        ++my_act;
+        if (spn.y & kLargeFlag) ++my_large;
       }
-      rec[2 * k] = o0;
-      rec[2 * k + 1] = o1;
-      if (rec2) rec2[k] = o2;
+      if (active || write_inactive) {
+        if (!active) {
+          o0 = make_float4(0.f, 0.f, 0.f, 0.f);
+          o1 = o0;
+          o2 = make_float2(0.f, 0.f);
+        }
+        rec[2 * k] = o0;
+        rec[2 * k + 1] = o1;
+        if (rec2) rec2[k] = o2;
+      }
+      span[k] = spn;
     }
-    span[k] = spn;
+    // every lane of the wave takes part
+    if (kCount) count_span(spn, k, rec, tk, hist);
+  }
+  if (kCount) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kBlock) {
+      const uint32_t v = hist[i];
+      if (v) atomicAdd(&counts[i], v);
+    }
   }
   if (my_act) atomicAdd(&s_act, my_act);
   if (my_large) atomicAdd(&s_large, my_large);
@@ -217,13 +239,24 @@ int grid_for(int64_t n, int per_block_items, int max_blocks) {
 
 }  // namespace
 
+bool project_counts(const TileK &tk) { return tk.n_tiles + tk.n_ctiles <= kProjectBins; }
+
 hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *rec2, uint2 *span,
-                          int write_inactive, Totals *tot, hipStream_t s) {
+                          int write_inactive, Totals *tot, hipStream_t s, uint32_t *counts) {
   if (pk.n == 0) return hipSuccess;
-  const int g = grid_for(pk.n, kBlock, 8192);
-  hipLaunchKernelGGL(k_project, dim3(g), dim3(kBlock), 0, s, pk, tk,
-                     reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
-                     write_inactive, tot);
+  if (counts && project_counts(tk)) {
+    // fewer, longer-lived workgroups: each flushes its histogram once
+    const int g = grid_for(pk.n, kBlock, 1024);
+    const size_t sh = (size_t)(tk.n_tiles + tk.n_ctiles) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_project<true>, dim3(g), dim3(kBlock), sh, s, pk, tk,
+                       reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
+                       write_inactive, tot, counts);
+  } else {
+    const int g = grid_for(pk.n, kBlock, 8192);
+    hipLaunchKernelGGL(k_project<false>, dim3(g), dim3(kBlock), 0, s, pk, tk,
+                       reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
+                       write_inactive, tot, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -293,6 +293,7 @@ struct Frame {
   float *out;
   double in_bytes_per_particle;  // bytes the first stage reads per particle
   double out_bytes_per_active;   // bytes it writes per active particle
+  bool counted;                  // the first stage already produced the tile counts
   TimedFrame *tf;                // NULL unless timing
 };
 
@@ -358,7 +359,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   const uint2 *span = (const uint2 *)c->span.p;
   TimedFrame *tf = f.tf;
 
-  HIPTRY(c, launch_count(span, f.rec, f.n, tk, counts, s));
+  if (!f.counted) HIPTRY(c, launch_count(span, f.rec, f.n, tk, counts, s));
   mark(tf, 2, s);
   const int chunk[3] = {kChunkSplat, sorted ? kSortChunk : 0, sorted ? kMergeOut : 0};
   const int cchunk[3] = {kChunkLarge, 0, 0};
@@ -441,7 +442,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     const double t2 = (double)tk.tile * tk.tile;
     double *B = tf->bytes;
     B[0] = n * f.in_bytes_per_particle + act * f.out_bytes_per_active + n * 8.0;
-    B[1] = n * 8.0 + 4.0 * nb;
+    B[1] = f.counted ? 0.0 : n * 8.0 + 4.0 * nb;
     B[2] = 4.0 * nb * 3.0;
     B[3] = 16.0 * (double)(T.n_items[0] + T.n_items[1] + T.n_items[2]);
     B[4] = n * 8.0 + pairs * (sorted ? 8.0 : 4.0);
@@ -523,13 +524,14 @@ spl_status render_one(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
   TimedFrame *tf = (c->timing && begin_timed(c, tfr)) ? &tfr : nullptr;
   mark(tf, 0, s);
   HIPTRY(c, launch_project(pk, tk, (float *)c->rec.p, sorted ? (float *)c->rec2.p : nullptr,
-                           (uint2 *)c->span.p, 0, (Totals *)c->totals.p, s));
+                           (uint2 *)c->span.p, 0, (Totals *)c->totals.p, s,
+                           (uint32_t *)c->counts.p));
   mark(tf, 1, s);
   const double attr = p->attr_dtype == SPL_F32 ? 4.0 : 2.0;
   Frame f{p->n, (const float *)c->rec.p, sorted ? (const float *)c->rec2.p : nullptr, tk,
           prm->mode, prm->normalise, out,
           12.0 + 3.0 * attr + (p->species ? 1.0 : 0.0) + (sorted ? 4.0 : 0.0),
-          32.0 + (sorted ? 8.0 : 0.0), nullptr};
+          32.0 + (sorted ? 8.0 : 0.0), project_counts(tk), nullptr};
   return render_timed(c, f, tf, st, s);
 }
 
@@ -591,8 +593,8 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     float *rv = rec + (size_t)v * n * 8;
     uint2 *sv = span + (size_t)v * n;
     HIPTRY(c, launch_fill_u32(counts + v * bstride, 0u, nb, s));
-    HIPTRY(c, launch_project(pk[v], tk[v], rv, nullptr, sv, 0, tot + v, s));
-    HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, s));
+    HIPTRY(c, launch_project(pk[v], tk[v], rv, nullptr, sv, 0, tot + v, s, counts + v * bstride));
+    if (!project_counts(tk[v])) HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, s));
     HIPTRY(c, launch_scan(counts + v * bstride, nb, tk[v].n_tiles, offsets + v * bstride,
                           cursor + v * bstride, chunk, cchunk, minc, itemoff + v * 3 * bstride,
                           tot + v, s));
@@ -1017,7 +1019,7 @@ spl_status spl_render_records(spl_ctx *c, int64_t n, const float *rec, const flo
   HIPTRY(c, launch_span_from_records(rec, n, tk, (uint2 *)c->span.p, (Totals *)c->totals.p, s));
   mark(tf, 1, s);
   Frame f{n, rec, prm->mode == SPL_SORTED ? rec2 : nullptr, tk, prm->mode, prm->normalise, out,
-          32.0, 0.0, nullptr};
+          32.0, 0.0, false, nullptr};
   return render_timed(c, f, tf, st, s);
 }
 

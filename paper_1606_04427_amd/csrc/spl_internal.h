@@ -171,8 +171,13 @@ __device__ __forceinline__ uint2 record_span(const float4 r0, float sigma, const
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 
+// With counts != NULL and project_counts(tk), the projection also adds the
+// tile counts of the binning stage into counts (zeroed by the caller).
+constexpr int kProjectBins = 8192;
+bool project_counts(const TileK &tk);
 hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *rec2,
-                          uint2 *span, int write_inactive, Totals *tot, hipStream_t s);
+                          uint2 *span, int write_inactive, Totals *tot, hipStream_t s,
+                          uint32_t *counts = nullptr);
 hipError_t launch_span_from_records(const float *rec, int64_t n, const TileK &tk, uint2 *span,
                                     Totals *tot, hipStream_t s);
 hipError_t launch_scalar_range(const ProjK &pk, int n_species, int log10, double *out_minmax,
