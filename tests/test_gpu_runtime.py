@@ -1,0 +1,155 @@
+"""Runtime services of the C ABI on the GPU: the autotuner, stage timers,
+workspace accounting, FP64 image statistics, reduced-precision attributes in
+the depth-sorted mode, and replays of the captured batch graph."""
+import numpy as np
+import pytest
+
+from paper_1606_04427_amd import synth
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(oracle):
+    import torch
+
+    from paper_1606_04427_amd import binding as B
+
+    assert torch.cuda.is_available()
+    ctx = B.Context(0)
+    yield B, ctx, oracle
+    ctx.close()
+
+
+def _case(n=80_000, seed=71, W=320, H=256, absorption=False):
+    ps = synth.soneira_peebles(n, seed=seed, absorption=absorption)
+    poses = synth.random_poses(3, seed=seed + 1, width=W, height=H)
+    looks, pals = [], []
+    for k in range(2):
+        s = ps.scalar[ps.species == k]
+        looks.append(dict(log10=1, brightness=0.05 * (1 + k), lo=float(np.log10(s.min())),
+                          hi=float(np.log10(s.max()))))
+        pals.append(synth.palette(k))
+    return ps, poses, looks, pals
+
+
+def _oracle(R, ps, pose, mode, looks, pals):
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    return R.render(R.Particles(ps), pose, R.params(mode, L))
+
+
+def test_autotune_choice_is_cached_and_renders_correctly(env):
+    import torch
+
+    B, ctx, R = env
+    ps, poses, looks, pals = _case()
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals), looks)  # tile 0, cut 0: library choice
+    tile, cut = ctx.spl_autotune(parts, poses[0], prm)
+    assert tile in (16, 32)
+    assert cut in (16.0, 32.0, 64.0, 128.0, -1.0)
+    img, st = ctx.spl_render(parts, poses[0], prm)
+    torch.cuda.synchronize()
+    assert st["tile"] == tile and st["large_cut"] == cut
+    ref = _oracle(R, ps, poses[0], B.SPL_ADD_AEQE, looks, pals)
+    assert rel_l2(img.cpu().numpy(), ref) < 1e-5
+
+
+def test_stage_timers_count_frames_and_reset(env):
+    import torch
+
+    B, ctx, _ = env
+    ps, poses, looks, pals = _case(n=40_000)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals), looks, tile=16, large_cut=16.0)
+    ctx.spl_set_timing(True)
+    ctx.spl_get_timing()
+    for p in poses:
+        ctx.spl_render(parts, p, prm, stats=False)
+    torch.cuda.synchronize()
+    ms, by, frames = ctx.spl_get_timing()
+    assert frames == len(poses)
+    assert all(m >= 0 for m in ms) and ms[B.STAGES.index("splat")] > 0
+    assert by[B.STAGES.index("project")] > 0 and by[B.STAGES.index("splat")] > 0
+    ms2, by2, frames2 = ctx.spl_get_timing()  # reset by the previous call
+    assert frames2 == 0 and sum(ms2) == 0
+    ctx.spl_set_timing(False)
+    ctx.spl_render(parts, poses[0], prm, stats=False)
+    assert ctx.spl_get_timing()[2] == 0
+    assert ctx.workspace_bytes() > 0
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_stats_are_fp64_reductions_of_the_image(env, mode):
+    import torch
+
+    B, ctx, _ = env
+    ps, poses, looks, pals = _case(n=50_000, absorption=True)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(mode, B.Palettes(pals), looks)
+    img, st = ctx.spl_render(parts, poses[1], prm)
+    torch.cuda.synchronize()
+    a = img.cpu().numpy().astype(np.float64)
+    flux = a.reshape(-1, 3).sum(axis=0)
+    mx = a.reshape(-1, 3).max(axis=0)
+    np.testing.assert_allclose(st["flux"], flux, rtol=1e-12, atol=1e-300)
+    np.testing.assert_array_equal(np.asarray(st["max"]), mx)
+    # normalised image: divided by the largest channel maximum
+    prm.normalise = 1
+    img2, st2 = ctx.spl_render(parts, poses[1], prm)
+    torch.cuda.synchronize()
+    b = img2.cpu().numpy().astype(np.float64)
+    if mx.max() > 0:
+        # a fresh render: tiles with several work items add with float
+        # atomics, so the two images agree to rounding, not bit for bit
+        np.testing.assert_allclose(b, a / mx.max(), rtol=1e-5, atol=1e-6)
+        assert abs(b.max() - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("dtype,tol", [("bf16", 2e-3), ("f16", 5e-4)])
+def test_reduced_precision_sorted_mode(env, dtype, tol):
+    """Depth-sorted transfer with BF16 / FP16 smoothing length, intensity and
+    colour scalar (absorption and positions FP32) against the FP64 oracle on
+    the FP32 originals."""
+    import torch
+
+    B, ctx, R = env
+    ps, poses, looks, pals = _case(n=120_000, absorption=True)
+    parts = B.DeviceParticles(ps, "cuda:0", dtype)
+    prm = B.make_params(B.SPL_SORTED, B.Palettes(pals), looks)
+    for pose in poses[:2]:
+        img, _ = ctx.spl_render(parts, pose, prm)
+        torch.cuda.synchronize()
+        ref = _oracle(R, ps, pose, B.SPL_SORTED, looks, pals)
+        if np.abs(ref).max() == 0:
+            continue
+        assert rel_l2(img.cpu().numpy(), ref) < tol
+
+
+def test_batch_graph_replays_match_direct_launches(env):
+    """The captured graph of the batch path is updated in place and replayed
+    on every call; eager work and synchronisations run between the calls, and
+    every replay must equal the launches without a graph."""
+    import torch
+
+    B, ctx, _ = env
+    ps, poses, looks, pals = _case(n=60_000)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    prms = [B.make_params(B.SPL_ADD_AEQE, P, looks, tile=16, large_cut=16.0) for _ in poses]
+    want, _ = ctx.spl_render_batch(parts, poses, prms, stats=False)
+    torch.cuda.synchronize()
+    want = [w.cpu().numpy() for w in want]
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, 1)
+    try:
+        scratch = torch.zeros(1 << 20, device="cuda:0")
+        for rep in range(4):
+            got, sts = ctx.spl_render_batch(parts, poses, prms)
+            scratch.add_(1.0)  # eager work between replays
+            torch.cuda.synchronize()
+            for g, w in zip(got, want):
+                assert rel_l2(g.cpu().numpy(), w) < 1e-6, rep
+            assert float(scratch[0]) == rep + 1
+    finally:
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
