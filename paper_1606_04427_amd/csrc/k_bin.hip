@@ -132,27 +132,34 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
 
 constexpr int kScanThreads = 1024;
 
-__device__ __forceinline__ uint32_t items_for(uint32_t c, int bin, int n_fine, int ch, int cch,
+// Work items of a bin of c entries in chunks of 2^shift (shift < 0: no
+// list; bins below minc entries get none).  Chunk sizes are powers of two.
+__device__ __forceinline__ uint32_t items_for(uint32_t c, int bin, int n_fine, int sh, int csh,
                                               int minc) {
-  const int chunk = bin < n_fine ? ch : cch;
-  if (c == 0 || chunk <= 0 || (int64_t)c < (int64_t)minc) return 0;
-  return (c + (uint32_t)chunk - 1) / (uint32_t)chunk;
+  const int shift = bin < n_fine ? sh : csh;
+  if (c == 0 || shift < 0 || (int64_t)c < (int64_t)minc) return 0;
+  return (c + (1u << shift) - 1u) >> shift;
 }
 
 struct ScanArgs {
-  int chunk[3], cchunk[3], minc[3];
+  int shift[3], cshift[3], minc[3];
 };
 
+// One workgroup: each thread sums a run of consecutive bins (entries and the
+// item counts of the three chunkings), the runs are scanned with wave
+// shuffles and one pass over the wave totals, and each thread writes its
+// bins' offsets.
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restrict__ counts,
                                                        int nb, int n_fine,
                                                        uint32_t *__restrict__ offsets,
                                                        uint32_t *__restrict__ cursor, ScanArgs a,
                                                        uint32_t *__restrict__ item_off,
                                                        Totals *__restrict__ tot) {
-  __shared__ unsigned long long s[4][kScanThreads];
+  constexpr int NW = kScanThreads / 64;
+  __shared__ unsigned long long s_w[4][NW];
   __shared__ unsigned int s_max, s_nef, s_nec;
   __shared__ unsigned long long s_l2;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   if (t == 0) {
     s_max = 0;
     s_nef = 0;
@@ -167,8 +174,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   for (int b = b0; b < b1; ++b) {
     const uint32_t c = counts[b];
     loc[0] += c;
-    if (items_for(c, b, n_fine, a.chunk[2], a.cchunk[2], a.minc[2])) l2 += c;
-    for (int k = 0; k < 3; ++k) loc[1 + k] += items_for(c, b, n_fine, a.chunk[k], a.cchunk[k], a.minc[k]);
+    uint32_t ik[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ik[k] = items_for(c, b, n_fine, a.shift[k], a.cshift[k], a.minc[k]);
+      loc[1 + k] += ik[k];
+    }
+    if (ik[2]) l2 += c;
     if (b < n_fine && c > mx) mx = c;
     if (c) {
       if (b < n_fine)
@@ -177,22 +189,40 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
         ++nec;
     }
   }
-  for (int q = 0; q < 4; ++q) s[q][t] = loc[q];
   __syncthreads();
   if (mx) atomicMax(&s_max, mx);
   if (nef) atomicAdd(&s_nef, nef);
   if (nec) atomicAdd(&s_nec, nec);
   if (l2) atomicAdd(&s_l2, l2);
-  // inclusive Hillis-Steele scan of the per-thread sums
-  for (int d = 1; d < kScanThreads; d <<= 1) {
-    unsigned long long v[4];
-    for (int q = 0; q < 4; ++q) v[q] = (t >= d) ? s[q][t - d] : 0ull;
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) s[q][t] += v[q];
-    __syncthreads();
+  // inclusive scan inside each wave, then over the wave totals
+  unsigned long long inc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    inc[q] = loc[q];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long v = __shfl_up(inc[q], o);
+      if (lane >= o) inc[q] += v;
+    }
+    if (lane == 63) s_w[q][wv] = inc[q];
   }
+  __syncthreads();
+  if (t < 64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      unsigned long long v = t < NW ? s_w[q][t] : 0ull;
+#pragma unroll
+      for (int o = 1; o < NW; o <<= 1) {
+        const unsigned long long u = __shfl_up(v, o);
+        if (t >= o) v += u;
+      }
+      if (t < NW) s_w[q][t] = v;  // inclusive over waves
+    }
+  }
+  __syncthreads();
   unsigned long long run[4];
-  for (int q = 0; q < 4; ++q) run[q] = s[q][t] - loc[q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) run[q] = (wv ? s_w[q][wv - 1] : 0ull) + inc[q] - loc[q];
   for (int b = b0; b < b1; ++b) {
     const uint32_t c = counts[b];
     if (b == n_fine && tot) {
@@ -202,20 +232,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
     offsets[b] = (uint32_t)run[0];
     cursor[b] = (uint32_t)run[0];
     run[0] += c;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
       item_off[k * (nb + 1) + b] = (uint32_t)run[1 + k];
-      run[1 + k] += items_for(c, b, n_fine, a.chunk[k], a.cchunk[k], a.minc[k]);
+      run[1 + k] += items_for(c, b, n_fine, a.shift[k], a.cshift[k], a.minc[k]);
     }
   }
   if (t == kScanThreads - 1) {
-    offsets[nb] = (uint32_t)s[0][t];
-    for (int k = 0; k < 3; ++k) item_off[k * (nb + 1) + nb] = (uint32_t)s[1 + k][t];
+    unsigned long long tt[4];
+    for (int q = 0; q < 4; ++q) tt[q] = s_w[q][NW - 1];
+    offsets[nb] = (uint32_t)tt[0];
+    for (int k = 0; k < 3; ++k) item_off[k * (nb + 1) + nb] = (uint32_t)tt[1 + k];
     if (tot) {
-      tot->n_pairs = s[0][t];
-      for (int k = 0; k < 3; ++k) tot->n_items[k] = s[1 + k][t];
+      tot->n_pairs = tt[0];
+      for (int k = 0; k < 3; ++k) tot->n_items[k] = tt[1 + k];
       if (n_fine == nb) {
-        tot->n_fine_pairs = s[0][t];
-        for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = s[1 + k][t];
+        tot->n_fine_pairs = tt[0];
+        for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = tt[1 + k];
       }
       tot->max_count = s_max;
       tot->n_fine_nonempty = s_nef;
@@ -235,7 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ c
   const int b = blockIdx.x * kBlock + threadIdx.x;
   if (b >= nb) return;
   const uint32_t c = counts[b];
-  const uint32_t k = items_for(c, b, n_fine, chunk, cchunk, minc);
+  const uint32_t k = items_for(c, b, n_fine, chunk > 0 ? __builtin_ctz((uint32_t)chunk) : -1,
+                               cchunk > 0 ? __builtin_ctz((uint32_t)cchunk) : -1, minc);
   if (k == 0) return;
   const uint32_t ch = (uint32_t)(b < n_fine ? chunk : cchunk);
   const uint32_t o = offsets[b], e = o + c;
@@ -268,9 +302,17 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
                        uint32_t *cursor, const int chunk[3], const int cchunk[3],
                        const int min_count[3], uint32_t *item_off, Totals *tot, hipStream_t s) {
   ScanArgs a;
+  auto shift_of = [](int ch) {
+    if (ch <= 0) return -1;
+    int sft = 0;
+    while ((1 << sft) < ch) ++sft;
+    return sft;
+  };
   for (int k = 0; k < 3; ++k) {
-    a.chunk[k] = chunk[k];
-    a.cchunk[k] = cchunk[k];
+    if ((chunk[k] > 0 && (chunk[k] & (chunk[k] - 1))) || (cchunk[k] > 0 && (cchunk[k] & (cchunk[k] - 1))))
+      return hipErrorInvalidValue;  // chunk sizes are powers of two
+    a.shift[k] = shift_of(chunk[k]);
+    a.cshift[k] = shift_of(cchunk[k]);
     a.minc[k] = min_count[k];
   }
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, n_bins, n_fine, offsets,

@@ -186,7 +186,7 @@ hipError_t launch_scalar_range(const ProjK &pk, int n_species, int log10, double
 hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
                         uint32_t *counts, hipStream_t s);
 // Exclusive scan of counts (n_bins) into offsets (n_bins + 1) and cursor; item
-// counts for up to three chunk sizes (chunk[k] > 0; bins below min_count[k]
+// counts for up to three chunk sizes (chunk[k] > 0, powers of two; bins below min_count[k]
 // get no item; fine chunk applies to fine bins, cchunk[k] to large bins).
 hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t *offsets,
                        uint32_t *cursor, const int chunk[3], const int cchunk[3],
