@@ -5,7 +5,8 @@
 // ascending (depth, index) and every key is unique.
 //
 //  k_sort_chunks  one workgroup per list chunk of <= 4096 keys: bitonic sort
-//                 in LDS (32 KB).  A list that fits one chunk is done.
+//                 with up to 16 keys per lane in registers.  A list that fits
+//                 one chunk is done.
 //  k_merge_pass   longer lists: sorted runs of length L merged pairwise into
 //                 runs of 2L; one workgroup per 2048 outputs stages its inputs
 //                 in LDS, each lane merges 8 keys.
@@ -18,32 +19,100 @@ namespace {
 constexpr int kSortChunk = 4096;
 constexpr int kMergeOut = 2048;  // outputs per workgroup = 256 lanes x 8
 
-__global__ __launch_bounds__(kBlock) void k_sort_chunks(unsigned long long *__restrict__ keys,
-                                                        const Item *__restrict__ items) {
-  __shared__ unsigned long long s[kSortChunk];
-  const Item it = items[blockIdx.x];
-  const int n = (int)(it.z - it.y);
-  int np = 1;
-  while (np < n) np <<= 1;
-  for (int i = threadIdx.x; i < np; i += kBlock) s[i] = (i < n) ? keys[it.y + i] : ~0ull;
-  __syncthreads();
-  // every lane takes compare-exchange pairs (i, i + j): i is the pair number
-  // with a zero bit inserted at bit log2(j)
-  for (int k = 2; k <= np; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int p = threadIdx.x; p < (np >> 1); p += kBlock) {
-        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-        const unsigned long long a = s[i], b = s[i + j];
-        const bool up = (i & k) == 0;
-        if ((a > b) == up) {
-          s[i] = b;
-          s[i + j] = a;
-        }
+__device__ __forceinline__ int padded(int pos) { return pos + (pos >> 4); }
+
+// Compare-exchange stage with partners J < E apart inside one thread's keys.
+template <int J, int E>
+__device__ __forceinline__ void reg_stage(unsigned long long (&v)[E], int t, int k) {
+  if constexpr (J < E) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if ((e & J) == 0) {
+        const bool up = ((t * E + e) & k) == 0;
+        const unsigned long long a = v[e], b = v[e + J];
+        const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
+        v[e] = up ? lo : hi;
+        v[e + J] = up ? hi : lo;
       }
-      __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < n; i += kBlock) keys[it.y + i] = s[i];
+}
+
+// Bitonic sort of one chunk of np = 256 E keys (padded with ~0): thread t
+// holds the E consecutive keys t E .. t E + E - 1 in registers.  Compare-
+// exchange partners closer than E sit in the same thread; partners up to
+// 64 E away sit in the same wave and are read with a lane shuffle; farther
+// ones go through LDS.  Loads and stores pass through LDS so that global
+// accesses stay coalesced.
+template <int E>
+__device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys, uint32_t b0,
+                                           int n, unsigned long long *s) {
+  constexpr int NP = kBlock * E;
+  const int t = threadIdx.x;
+  for (int p = t; p < NP; p += kBlock) s[padded(p)] = (p < n) ? keys[b0 + p] : ~0ull;
+  __syncthreads();
+  unsigned long long v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = s[padded(t * E + e)];
+#pragma unroll 1
+  for (int k = 2; k <= NP; k <<= 1) {
+#pragma unroll 1
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < E) {
+        switch (j) {
+          case 1: reg_stage<1, E>(v, t, k); break;
+          case 2: reg_stage<2, E>(v, t, k); break;
+          case 4: reg_stage<4, E>(v, t, k); break;
+          default: reg_stage<8, E>(v, t, k); break;
+        }
+      } else {
+        const int m = j / E;  // partner thread: t ^ m
+        if (m < 64) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = t * E + e;
+            const unsigned long long w = __shfl_xor(v[e], m);
+            const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+            v[e] = keep_min ? min(v[e], w) : max(v[e], w);
+          }
+        } else {
+          __syncthreads();
+#pragma unroll
+          for (int e = 0; e < E; ++e) s[padded(t * E + e)] = v[e];
+          __syncthreads();
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = t * E + e;
+            const unsigned long long w = s[padded((t ^ m) * E + e)];
+            const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+            v[e] = keep_min ? min(v[e], w) : max(v[e], w);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) s[padded(t * E + e)] = v[e];
+  __syncthreads();
+  for (int p = t; p < n; p += kBlock) keys[b0 + p] = s[padded(p)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_chunks(unsigned long long *__restrict__ keys,
+                                                        const Item *__restrict__ items) {
+  __shared__ unsigned long long s[kSortChunk + kSortChunk / 16];
+  const Item it = items[blockIdx.x];
+  const int n = (int)(it.z - it.y);
+  if (n <= kBlock)
+    sort_chunk<1>(keys, it.y, n, s);
+  else if (n <= 2 * kBlock)
+    sort_chunk<2>(keys, it.y, n, s);
+  else if (n <= 4 * kBlock)
+    sort_chunk<4>(keys, it.y, n, s);
+  else if (n <= 8 * kBlock)
+    sort_chunk<8>(keys, it.y, n, s);
+  else
+    sort_chunk<16>(keys, it.y, n, s);
 }
 
 // First i in [lo, hi) with A[i] >= B[diag - 1 - i] (hi if none): the start
