@@ -1,0 +1,136 @@
+"""Parity at the benchmark sizes, in the launch configurations the benchmark
+times, against the FP64 oracle on the whole image: the 10M-particle
+clustered set at 1024 x 1024 (additive, tile 16, with and without the
+large-particle path) and at 2048 x 2048 (depth-sorted).  Also the largest
+image sides the ABI accepts and the particle-count limit."""
+import numpy as np
+import pytest
+
+from paper_1606_04427_amd import synth
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+N_FULL = 10_000_000
+
+
+@pytest.fixture(scope="module")
+def env(oracle):
+    import torch
+
+    from paper_1606_04427_amd import binding as B
+
+    assert torch.cuda.is_available()
+    ctx = B.Context(0)
+    yield B, ctx, oracle
+    ctx.close()
+
+
+def _looks(ps):
+    looks, pals = [], []
+    for k in range(2):
+        s = ps.scalar[ps.species == k]
+        looks.append(dict(log10=1, brightness=0.02 * (1 + k), lo=float(np.log10(s.min())),
+                          hi=float(np.log10(s.max()))))
+        pals.append(synth.palette(k))
+    return looks, pals
+
+
+def _check(got, ref, tol):
+    e = rel_l2(got, ref)
+    assert e <= tol, f"rel-L2 {e:.3e} > {tol:.1e}"
+    bound = 1e-3 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+    bad = np.abs(got - ref) > bound
+    assert not bad.any(), f"{int(bad.sum())} pixels outside the max-pixel bound"
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    ps = synth.soneira_peebles(N_FULL, seed=1001, absorption=True)
+    return ps, _looks(ps)
+
+
+@pytest.mark.parametrize("cut", [-1.0, 32.0])
+def test_additive_10M_1024(env, clustered, cut):
+    import torch
+
+    B, ctx, R = env
+    ps, (looks, pals) = clustered
+    poses = synth.random_poses(8, seed=2001, width=1024, height=1024)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals), looks, tile=16, large_cut=cut)
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    RP = R.Particles(ps)
+    for k in (0, 2):  # a far pose and a pose inside the clusters
+        img, st = ctx.spl_render(parts, poses[k], prm)
+        torch.cuda.synchronize()
+        ref = R.render(RP, poses[k], R.params(R.ADD_AEQE, L))
+        _check(img.cpu().numpy().astype(np.float64), ref, 1e-5)
+        if cut > 0 and k == 2:
+            assert st["n_large"] > 0  # the large-particle path took part
+
+
+def test_sorted_10M_2048(env, clustered):
+    import torch
+
+    B, ctx, R = env
+    ps, (looks, pals) = clustered
+    pose = synth.random_poses(8, seed=2001, width=2048, height=2048)[0]
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(B.SPL_SORTED, B.Palettes(pals), looks, tile=16)
+    img, _ = ctx.spl_render(parts, pose, prm)
+    torch.cuda.synchronize()
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    ref = R.render(R.Particles(ps), pose, R.params(R.SORTED, L))
+    _check(img.cpu().numpy().astype(np.float64), ref, 1e-5)
+
+
+@pytest.mark.parametrize("W,H", [(32768, 8), (8, 32768)])
+def test_largest_image_sides(env, W, H):
+    import torch
+
+    B, ctx, R = env
+    ps = synth.blobs(30_000, seed=81)
+    looks, pals = _looks_single(ps)
+    pose = synth.Pose((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 40.0, 1e-3, W, H)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    for mode in (B.SPL_ADD_RAW, B.SPL_ADD_AEQE):
+        prm = B.make_params(mode, B.Palettes(pals), looks)
+        img, _ = ctx.spl_render(parts, pose, prm)
+        torch.cuda.synchronize()
+        L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+        ref = R.render(R.Particles(ps), pose, R.params(mode, L))
+        assert np.abs(ref).max() > 0
+        _check(img.cpu().numpy().astype(np.float64), ref, 1e-5)
+    bad = synth.Pose((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 40.0, 1e-3, W * (2 if W > 8 else 1),
+                     H * (2 if H > 8 else 1))
+    with pytest.raises(B.SplotchError) as ei:
+        ctx.spl_render(parts, bad, prm)
+    assert ei.value.status == B.SPL_EINVAL
+
+
+def _looks_single(ps):
+    s = ps.scalar[ps.scalar > 0]
+    return ([dict(log10=1, brightness=0.3, lo=float(np.log10(s.min())),
+                  hi=float(np.log10(s.max())))], [synth.palette(0)])
+
+
+def test_particle_count_limit(env):
+    import ctypes as C
+
+    import torch
+
+    B, ctx, _ = env
+    ps = synth.blobs(1000, seed=82)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    looks, pals = _looks_single(ps)
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals), looks)
+    cam = B.make_camera(synth.blobs_camera(64, 64))
+    out = torch.empty((64, 64, 3), device="cuda:0")
+    for n in (-1, 0xFFFFFFFF, 1 << 40):
+        st = B.spl_particles.from_buffer_copy(parts.st)
+        st.n = n
+        rc = ctx.L.spl_render(ctx.h, C.byref(st), C.byref(cam), C.byref(prm),
+                              C.c_void_p(out.data_ptr()), None, None)
+        assert rc == B.SPL_EINVAL
+        assert b"particle count" in ctx.L.spl_last_error(ctx.h)
