@@ -10,7 +10,9 @@ transfer, FP32 attributes.  One step renders all 8 poses; particles/s counts
 every input particle of every pose.  Inputs are resident in device memory
 before timing.
 
-Other workloads (--workload): `sorted` (the same 10M set with absorption,
+Other workloads (--workload): `blobs` (100k particles in Gaussian blobs at
+256^2, the small case, with the oracle timed on the same frame), `sorted` (the
+same 10M set with absorption,
 depth-sorted transfer, one 2048 x 2048 view), `batched` (200M particles with
 BF16 or FP16 attributes, 64 views of 4096^2 and 1024^2 in batched launches),
 `serving` (100M resident particles, a Poisson stream of mixed-size views).
@@ -88,6 +90,31 @@ def cpu_baseline(ps, poses, looks, pals, sample, mode):
             "kind": "oracle",
             "sample": f"random {sample}-particle subsample of the same set, {len(poses)} pose(s), "
                       f"FP64 single-threaded C oracle, {dt:.1f} s"}
+
+
+def cpu_baseline_all_cores(ps, poses, looks, pals, sample, mode):
+    """The same oracle runs on several host threads, one pose each (the C
+    oracle releases the interpreter lock and keeps no global state)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import splref as R
+
+    R.build(force=False)
+    rng = np.random.Generator(np.random.PCG64(7))
+    idx = np.sort(rng.choice(ps.n, sample, replace=False))
+    sub = ps.subset(idx)
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    prm = R.params(mode, L)
+    P = R.Particles(sub)
+    threads = max(1, min(len(poses), os.cpu_count() or 1, 16))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(lambda pose: R.render(P, pose, prm), poses))
+    dt = time.perf_counter() - t0
+    return {"value": sample * len(poses) / dt, "unit": "particles/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"random {sample}-particle subsample, {len(poses)} pose(s) on {threads} host "
+                      f"threads, {dt:.1f} s"}
 
 
 def box_pixels(rec, width, height, cut):
@@ -228,15 +255,29 @@ def run_additive(args, torch, B):
     # outside the timed region: per-pose statistics and the Gaussian updates
     # the splat had to evaluate (from the device's own records)
     stats = [ctx.spl_render(parts, p, prm, out=imgs[k])[1] for k, p in enumerate(poses)]
-    updates, small = 0.0, 0
+    updates, small, pose_updates = 0.0, 0, []
     for k, p in enumerate(poses):
         rec, _ = ctx.spl_project(parts, p, prm)
         u, s = box_pixels(rec.cpu().numpy(), p.width, p.height, stats[k]["large_cut"])
         updates += u
         small += s
+        pose_updates.append(u)
         del rec
     updates /= len(poses)
     roofline = roofline_for(B, ms, by, frames, updates)
+    # per pose: splat time and the footprint that drives it
+    per_pose = []
+    for k, p in enumerate(poses):
+        ctx.spl_set_timing(True)
+        ctx.spl_get_timing()
+        ctx.spl_render(parts, p, prm, out=imgs[k], stats=False)
+        pm, _, pf = ctx.spl_get_timing()
+        ctx.spl_set_timing(False)
+        per_pose.append({"n_active": stats[k]["n_active"], "n_pairs": stats[k]["n_pairs"],
+                         "box_px": pose_updates[k],
+                         "box_px_per_active": pose_updates[k] / max(stats[k]["n_active"], 1),
+                         "frame_ms": sum(pm) / max(pf, 1),
+                         "splat_ms": pm[B.STAGES.index("splat")] / max(pf, 1)})
     roofline["traffic"] = measured_traffic(roofline["kernel"], ps.n, tile, cut)
 
     # the same step through the batched entry point (one call for all poses)
@@ -271,6 +312,42 @@ def run_additive(args, torch, B):
         torch.cuda.synchronize()
         del src, dst
 
+    # bandwidth probe: the same particle count with the small radii of the
+    # blob set (0.5-8 px), where the splat moves more bytes per evaluation
+    probe = None
+    if not args.no_probe:
+        from paper_1606_04427_amd import synth
+
+        pb = synth.blobs(ps.n, seed=1000)
+        bparts = B.DeviceParticles(pb, dev, "f32")
+        s_ = pb.scalar[pb.scalar > 0]
+        blook = [dict(log10=1, brightness=0.3, lo=float(np.log10(s_.min())),
+                      hi=float(np.log10(s_.max())))]
+        bprm = B.make_params(B.SPL_ADD_AEQE, B.Palettes([synth.palette(0)], dev), blook, tile=16,
+                             large_cut=-1.0)
+        bcam = synth.blobs_camera(256, 256)
+        bimg = torch.empty((256, 256, 3), dtype=torch.float32, device=dev)
+        for _ in range(2):
+            ctx.spl_render(bparts, bcam, bprm, out=bimg, stats=False)
+        ctx.spl_set_timing(True)
+        ctx.spl_get_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.spl_render(bparts, bcam, bprm, out=bimg, stats=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pm, pby, pf = ctx.spl_get_timing()
+        ctx.spl_set_timing(False)
+        si = B.STAGES.index("splat")
+        probe = {"workload": f"{pb.n} particles in 64 Gaussian blobs, projected radii 0.5-8 px, "
+                             "256x256, fixed camera, additive",
+                 "particles_per_s": args.steps * pb.n / dt, "ms_per_frame": 1e3 * dt / args.steps,
+                 "splat_ms": pm[si] / pf, "splat_GBps": pby[si] / (pm[si] * 1e-3) / 1e9,
+                 "stages_ms": {B.STAGES[i]: pm[i] / pf for i in range(len(B.STAGES))}}
+        log("bandwidth probe: " + json.dumps(probe))
+        del bparts
+
     frame_bytes = sum(by[k] for k in range(len(B.STAGES)) if B.STAGES[k] != "host_gap_items")
     frame_bytes /= max(frames, 1)
     out = base_record(args, value, ms_per_step, "f32", {
@@ -284,6 +361,8 @@ def run_additive(args, torch, B):
         "roofline": roofline,
         "stages": stage_table(B, ms, by, frames),
         "batched_entry_point": batched,
+        "per_pose": per_pose,
+        "bandwidth_probe": probe,
         "mean_box_px_per_small_particle": updates * len(poses) / max(small, 1),
         "frames": [{"n_active": s["n_active"], "n_pairs": s["n_pairs"], "n_large": s["n_large"],
                     "n_large_pairs": s["n_large_pairs"]} for s in stats],
@@ -293,11 +372,57 @@ def run_additive(args, torch, B):
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(ps, poses, looks, pals, args.cpu_sample or 5_000_000,
                                            B.SPL_ADD_AEQE)
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
+            ps, poses, looks, pals, args.cpu_sample or 5_000_000, B.SPL_ADD_AEQE)
         log(f"cpu baseline in {time.time() - t:.1f} s")
     return out
 
 
 # ----------------------------------------------------------------------------
+def run_blobs(args, torch, B):
+    """The small case: 100k particles in 64 Gaussian blobs at 256^2, fixed
+    camera, additive absorption = emission; GPU time per frame against the
+    oracle's on the same frame, and the image error."""
+    from oracle import splref as R
+    from paper_1606_04427_amd import synth
+
+    ps = synth.blobs(args.n or 100_000, seed=1000)
+    cam = synth.blobs_camera(256, 256)
+    s_ = ps.scalar[ps.scalar > 0]
+    looks = [dict(log10=1, brightness=0.3, lo=float(np.log10(s_.min())),
+                  hi=float(np.log10(s_.max())))]
+    pals = [synth.palette(0)]
+    dev = "cuda:0"
+    ctx = B.Context(0)
+    parts = B.DeviceParticles(ps, dev, "f32")
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals, dev), looks)
+    img = torch.empty((256, 256, 3), dtype=torch.float32, device=dev)
+
+    def step():
+        ctx.spl_render(parts, cam, prm, out=img, stats=False)
+
+    elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
+    ms_per_step = 1e3 * elapsed / args.steps
+    R.build(force=False)
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    P = R.Particles(ps)
+    t0 = time.perf_counter()
+    ref = R.render(P, cam, R.params(R.ADD_AEQE, L))
+    dt = time.perf_counter() - t0
+    got = img.cpu().numpy().astype(np.float64)
+    out = base_record(args, ps.n / (ms_per_step * 1e-3), ms_per_step, "f32", {
+        "workload": f"{ps.n} particles in 64 Gaussian blobs, 256x256, fixed camera, additive "
+                    "absorption=emission, FP32", "n_particles": ps.n, "image": [256, 256]})
+    out.update({"roofline": roofline_for(B, ms, by, frames), "stages": stage_table(B, ms, by, frames),
+                "rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                "cpu_baseline": {"value": ps.n / dt, "unit": "particles/s", "cores": 1,
+                                 "kind": "oracle",
+                                 "sample": f"the whole frame, FP64 single-threaded C oracle, "
+                                           f"{dt:.2f} s"}})
+    ctx.close()
+    return out
+
+
 def run_sorted(args, torch, B):
     t = time.time()
     ps, poses, looks, pals = workload(args.n or 10_000_000, width=2048, height=2048,
@@ -512,13 +637,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="additive",
-                    choices=["additive", "sorted", "batched", "serving"])
+                    choices=["additive", "blobs", "sorted", "batched", "serving"])
     ap.add_argument("--n", type=int, default=0, help="particles (0: the workload's size)")
     ap.add_argument("--cpu-sample", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="additive: fixed tile (no autotune)")
     ap.add_argument("--cut", type=float, default=32.0, help="additive: fixed large cut with --tile")
+    ap.add_argument("--no-probe", action="store_true", help="additive: skip the bandwidth probe")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="additive: also run one plain device copy of this size")
     ap.add_argument("--dtypes", default="bf16,f16", help="batched: attribute dtypes")
@@ -539,8 +665,8 @@ def main():
 
     from paper_1606_04427_amd import binding as B
 
-    run = {"additive": run_additive, "sorted": run_sorted, "batched": run_batched,
-           "serving": run_serving}[args.workload]
+    run = {"additive": run_additive, "blobs": run_blobs, "sorted": run_sorted,
+           "batched": run_batched, "serving": run_serving}[args.workload]
     out = run(args, torch, B)
     print(json.dumps(out), flush=True)
 

@@ -196,8 +196,11 @@ class Palettes:
 
 def make_params(mode, palettes: Palettes, looks, k_sigma=1.0 / 3.0, sigma_min=0.5, nu=3.0,
                 tile=0, bin_rule=0, large_cut=0.0, normalise=0) -> spl_params:
-    """looks: list of dicts with brightness, lo, hi, log10 (one per species)."""
+    """looks: list of dicts with brightness, lo, hi, log10 (one per species).
+    The returned parameters keep `palettes` alive: they hold its device
+    pointers."""
     p = spl_params()
+    p._palettes = palettes
     p.mode = mode
     p.n_species = len(looks)
     for k, l in enumerate(looks):

@@ -82,3 +82,33 @@ int main(void) {
     offs = [B.spl_params.k_sigma.offset, B.spl_params.large_cut.offset,
             B.spl_particles.species.offset, B.spl_stats.tile.offset]
     assert [int(v) for v in out] == sizes + offs
+
+
+def test_params_keep_their_palettes_alive():
+    """spl_params holds raw device pointers into the palette tensors, so the
+    Python object must keep the palettes referenced (a temporary Palettes
+    passed inline would otherwise be freed before the render reads it)."""
+    import gc
+    import weakref
+
+    from paper_1606_04427_amd import binding as B
+
+    class FakePalettes:
+        def __init__(self):
+            self.t = [FakeTensor()]
+
+    class FakeTensor:
+        shape = (256, 3)
+
+        def data_ptr(self):
+            return 0x1000
+
+    pal = FakePalettes()
+    ref = weakref.ref(pal)
+    prm = B.make_params(1, pal, [dict(log10=1, brightness=1.0, lo=0.0, hi=1.0)])
+    del pal
+    gc.collect()
+    assert ref() is not None
+    del prm
+    gc.collect()
+    assert ref() is None
