@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_finalise(float *__restrict__ img, in
   }
   __syncthreads();
   for (int d = kBlock / 2; d > 0; d >>= 1) {
-    if (threadIdx.x < d) {
+    if ((int)threadIdx.x < d) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         s_red[c][threadIdx.x] += s_red[c][threadIdx.x + d];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stats(const double *__restric
   }
   __syncthreads();
   for (int d = kBlock / 2; d > 0; d >>= 1) {
-    if (threadIdx.x < d) {
+    if ((int)threadIdx.x < d) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         s_red[c][threadIdx.x] += s_red[c][threadIdx.x + d];

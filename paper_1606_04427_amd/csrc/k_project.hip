@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar_range(ProjK P, int n_species,
     atomicMax(&s_mm[2 * sp + 1], key);
   }
   __syncthreads();
-  if (threadIdx.x < 2 * n_species) {
+  if ((int)threadIdx.x < 2 * n_species) {
     const unsigned long long v = s_mm[threadIdx.x];
     if (threadIdx.x & 1) {
       if (v != 0ull) atomicMax(&mm[threadIdx.x], v);

@@ -107,7 +107,7 @@ spl_status ensure(spl_ctx *c, DevBuf &b, size_t bytes) {
   if (want < bytes) want = bytes;
   want = (want + 255) & ~(size_t)255;
   if (b.p) {
-    hipFree(b.p);
+    (void)hipFree(b.p);
     c->bytes -= (int64_t)b.cap;
     b.p = nullptr;
     b.cap = 0;
@@ -320,7 +320,7 @@ bool begin_timed(spl_ctx *c, TimedFrame &tf) {
 }
 
 void mark(TimedFrame *tf, int k, hipStream_t s) {
-  if (tf) hipEventRecord(tf->ev[k], s);
+  if (tf) (void)hipEventRecord(tf->ev[k], s);  // timing is best effort
 }
 
 // Accumulates every pending frame whose last event has completed (all of
@@ -540,10 +540,10 @@ constexpr int kMaxBatchViews = 255;
 
 spl_status ensure_host(spl_ctx *c, int views) {
   if (c->h_cap >= views) return SPL_OK;
-  if (c->h_btot) hipHostFree(c->h_btot);
-  if (c->h_views) hipHostFree(c->h_views);
-  if (c->h_ctr) hipHostFree(c->h_ctr);
-  if (c->h_bstats) hipHostFree(c->h_bstats);
+  if (c->h_btot) (void)hipHostFree(c->h_btot);
+  if (c->h_views) (void)hipHostFree(c->h_views);
+  if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+  if (c->h_bstats) (void)hipHostFree(c->h_bstats);
   c->h_btot = nullptr;
   c->h_views = nullptr;
   c->h_ctr = nullptr;
@@ -704,7 +704,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     hipGraph_t graph = nullptr;
     const hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
     if (cs != SPL_OK) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return cs;
     }
     if (ce != hipSuccess) return fail(c, SPL_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
@@ -714,12 +714,12 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       hipGraphExecUpdateResult res;
       if (hipGraphExecUpdate(c->gexec, graph, &bad, &res) != hipSuccess) {
         (void)hipGetLastError();
-        hipGraphExecDestroy(c->gexec);
+        (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
       }
     }
     if (!c->gexec) e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(c->gexec, s);
     if (e != hipSuccess) return fail(c, SPL_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
   }
@@ -824,7 +824,7 @@ spl_status spl_create(int device, spl_ctx **out) {
     c->n_cu = ncu;
   if (hipHostMalloc((void **)&c->h_tot, sizeof(Totals), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    if (c->h_tot) hipHostFree(c->h_tot);
+    if (c->h_tot) (void)hipHostFree(c->h_tot);
     delete c;
     return SPL_ENOMEM;
   }
@@ -834,8 +834,8 @@ spl_status spl_create(int device, spl_ctx **out) {
 
 void spl_destroy(spl_ctx *c) {
   if (!c) return;
-  hipSetDevice(c->device);
-  hipDeviceSynchronize();
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
   DevBuf *bufs[] = {&c->rec, &c->rec2, &c->span, &c->counts, &c->offsets, &c->cursor,
                     &c->item_off, &c->items[0], &c->items[1], &c->items[2], &c->pairs,
                     &c->keysA, &c->keysB, &c->partial, &c->fin, &c->stats, &c->totals,
@@ -843,18 +843,18 @@ void spl_destroy(spl_ctx *c) {
                     &c->b_cursor, &c->b_itemoff, &c->b_totals, &c->b_pairs, &c->b_itf,
                     &c->b_itc, &c->b_views, &c->b_ctr, &c->b_fin, &c->b_stats};
   for (DevBuf *b : bufs)
-    if (b->p) hipFree(b->p);
+    if (b->p) (void)hipFree(b->p);
   for (TimedFrame &tf : c->pending)
-    for (hipEvent_t e : tf.ev) hipEventDestroy(e);
-  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
-  if (c->h_tot) hipHostFree(c->h_tot);
-  if (c->h_stats) hipHostFree(c->h_stats);
-  if (c->h_btot) hipHostFree(c->h_btot);
-  if (c->h_views) hipHostFree(c->h_views);
-  if (c->h_ctr) hipHostFree(c->h_ctr);
-  if (c->h_bstats) hipHostFree(c->h_bstats);
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+    for (hipEvent_t e : tf.ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->h_tot) (void)hipHostFree(c->h_tot);
+  if (c->h_stats) (void)hipHostFree(c->h_stats);
+  if (c->h_btot) (void)hipHostFree(c->h_btot);
+  if (c->h_views) (void)hipHostFree(c->h_views);
+  if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+  if (c->h_bstats) (void)hipHostFree(c->h_bstats);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
 }
 
@@ -1099,9 +1099,12 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
   float *img = nullptr;
   if (hipMalloc(&img, (size_t)cam->width * cam->height * 12) != hipSuccess)
     return fail(c, SPL_ENOMEM, "autotune image allocation failed");
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    (void)hipFree(img);
+    return fail(c, SPL_EDEVICE, "autotune event creation failed");
+  }
   const int tiles[2] = {16, 32};
   const double cuts_add[5] = {16.0, 32.0, 64.0, 128.0, -1.0};
   const double cuts_sorted[1] = {-1.0};
@@ -1118,12 +1121,14 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
       q.large_cut = cuts[ci];
       float tmin = INFINITY;
       for (int rep = 0; rep < 3 && rc == SPL_OK; ++rep) {
-        hipEventRecord(e0, s);
+        hipError_t e = hipEventRecord(e0, s);
         rc = render_one(c, p, cam, &q, img, nullptr, s);
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess && rc == SPL_OK)
+          rc = fail(c, SPL_EDEVICE, "autotune timing failed: %s", hipGetErrorString(e));
         if (rep > 0 && ms < tmin) tmin = ms;
       }
       if (tmin < best) {
@@ -1132,9 +1137,9 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
         best_cut = cuts[ci] < 0 ? -1.0 : cuts[ci];
       }
     }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipFree(img);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(img);
   if (rc != SPL_OK) return rc;
   c->tune[std::make_tuple(p->n, cam->width, cam->height, prm->mode)] =
       std::make_pair(best_tile, best_cut < 0 ? INFINITY : best_cut);
