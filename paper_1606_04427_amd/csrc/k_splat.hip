@@ -6,18 +6,19 @@
 // atomics (additive) or by an ordered merge of partial (colour,
 // transmittance) tiles (sorted).
 //
-// k_splat_add<T>   additive modes, T x T tile, 256 lanes, one pixel (T = 16)
-//                  or four (T = 32) per lane.  Each batch of list entries is
-//                  staged in LDS; 16-lane groups own 4 x 4 micro-tiles, list
-//                  the staged entries that meet their micro-tile and gather
-//                  them in registers: no atomics inside the tile, and a lane
-//                  only evaluates entries whose box meets its micro-tile.
+// k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of list
+//                  entries is staged in LDS and appended to the lists of the
+//                  4 x 4 micro-tiles it meets; the lists, laid end to end, are
+//                  cut into equal ranges for the 16-lane groups (one pixel per
+//                  lane), with running sums in registers flushed into a
+//                  32-bit fixed-point LDS accumulator at micro-tile changes.
 //                  Batch sums fold into per-pixel Neumaier-compensated FP32
 //                  sums.
 // k_splat_large    the large-particle path: 64 x 64 px tiles, 512 lanes, 8
 //                  pixels per lane, gather only (a large particle covers most
 //                  of the pixels it is tested against).
-// k_composite<T>   sorted mode: the same staging and micro-tile lists, with
+// k_composite<T>   sorted mode: staging as above, in-order micro-tile lists
+//                  built by ballots, one micro-tile per 16-lane group,
 //                  front-to-back slab compositing per pixel in list order;
 //                  transmittance per pixel in registers.
 #include "spl_internal.h"

@@ -2,7 +2,8 @@
 // workspace, and the order of kernel launches for one frame.
 //
 // Frame (Sect. 2.1 rasterisation + rendering; Sect. 3.1 tiles):
-//   project+colour -> count -> scan  [one stream sync: list sizes]
+//   project+colour (+ tile counts when the bins fit LDS) [-> count] -> scan
+//   [one stream sync: list sizes]
 //   -> build work items -> scatter -> (sort) -> splat / composite
 //   -> finalise (+ FP64 flux / max) [-> normalise]
 // The single host synchronisation per frame reads the list sizes so that
