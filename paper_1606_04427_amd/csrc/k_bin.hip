@@ -283,12 +283,17 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ c
 
 }  // namespace
 
+// Workgroups of the count and scatter passes: each one zeroes and flushes a
+// histogram of all bins, so fewer, longer-lived ones when there are many bins.
+static int64_t bin_pass_blocks(int nb) { return nb <= 6144 ? 4096 : (nb <= 12288 ? 2048 : 1024); }
+
 hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
                         uint32_t *counts, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
   int64_t g = (n + kChunk - 1) / kChunk;
-  if (g > 1024) g = 1024;
+  const int64_t cap = bin_pass_blocks(nb);
+  if (g > cap) g = cap;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   if (nb <= kLdsBins)
     hipLaunchKernelGGL(k_count<true>, dim3((int)g), dim3(kBlock), nb * sizeof(uint32_t), s,
@@ -337,7 +342,8 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
   int64_t g = (n + kChunk - 1) / kChunk;
-  if (g > 1024) g = 1024;
+  const int64_t cap = bin_pass_blocks(nb);
+  if (g > cap) g = cap;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   const bool lds = nb <= kLdsBins;

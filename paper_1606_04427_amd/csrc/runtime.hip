@@ -25,7 +25,7 @@ using namespace spl;
 
 namespace {
 
-constexpr int kChunkSplat = 2048;  // list entries per splat item, fine tiles
+constexpr int kChunkSplat = 1024;  // list entries per splat item, fine tiles
 constexpr int kChunkLarge = 512;   // list entries per large-particle item
 constexpr int kSortChunk = 4096;   // keys per in-LDS sort
 constexpr int kMergeOut = 2048;    // outputs per merge workgroup
