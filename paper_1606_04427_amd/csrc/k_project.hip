@@ -246,7 +246,7 @@ hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *r
   if (pk.n == 0) return hipSuccess;
   if (counts && project_counts(tk)) {
     // fewer, longer-lived workgroups: each flushes its histogram once
-    const int g = grid_for(pk.n, kBlock, 2048);
+    const int g = grid_for(pk.n, kBlock, 4096);
     const size_t sh = (size_t)(tk.n_tiles + tk.n_ctiles) * sizeof(uint32_t);
     hipLaunchKernelGGL(k_project<true>, dim3(g), dim3(kBlock), sh, s, pk, tk,
                        reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,

@@ -225,7 +225,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
 }
 
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ items,
+__global__ __launch_bounds__(kBlock, 8) void k_splat_add(const Item *__restrict__ items,
                                                       const uint32_t *__restrict__ pairs,
                                                       const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ counts,
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_splat_add(const Item *__restrict__ i
 // Persistent form for many views: workgroups take (view, tile chunk) items
 // from a device counter until the queue is empty; every workgroup exits.
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_splat_add_views(const ViewK *__restrict__ views,
+__global__ __launch_bounds__(kBlock, 8) void k_splat_add_views(const ViewK *__restrict__ views,
                                                             const Item *__restrict__ items,
                                                             const uint32_t *__restrict__ n_items,
                                                             uint32_t *__restrict__ next,
