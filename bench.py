@@ -6,9 +6,11 @@ levels, 8 sub-clusters per level), two species with their own palettes,
 smoothing length h = 1.3 n^(-1/3) from the local density (projected kernel
 radii from sub-pixel to hundreds of px over the poses), 1024 x 1024 images, 8
 random camera poses (some inside the cube), additive absorption-equals-emission
-transfer, FP32 attributes.  One step renders all 8 poses; particles/s counts
-every input particle of every pose.  Inputs are resident in device memory
-before timing.
+transfer, FP32 attributes.  One step renders all 8 poses with one call of the
+batched entry point (one list-size synchronisation and one persistent splat
+launch for the 8 views); the one-view-per-call path is timed beside it.
+particles/s counts every input particle of every pose.  Inputs are resident in
+device memory before timing.
 
 Other workloads (--workload): `blobs` (100k particles in Gaussian blobs at
 256^2, the small case, with the oracle timed on the same frame), `sorted` (the
@@ -162,11 +164,16 @@ def stage_table(B, ms, by, frames):
     return out
 
 
-def roofline_for(B, ms, by, frames, updates_per_frame=None):
+def roofline_for(B, ms, by, launches, updates_per_launch=None):
+    """Roofline of the dominant stage; `launches` is the number of launches
+    the accumulated stage times cover (frames for one view per call, steps
+    for the batched call)."""
     kern = [k for k in range(len(B.STAGES)) if B.STAGES[k] not in ("host_gap_items",)]
     dom = max(kern, key=lambda k: ms[k])
     name = B.STAGES[dom]
+    frames = launches
     per_launch = ms[dom] / max(frames, 1)
+    updates_per_frame = updates_per_launch
     if name == "splat" and updates_per_frame:
         # the splat evaluates a Gaussian per pixel of each particle's box: its
         # bound is the vector ALU, not HBM
@@ -243,9 +250,12 @@ def run_additive(args, torch, B):
         tile, cut = ctx.spl_autotune(parts, poses[0], prm)
         log(f"autotune: tile {tile}, large cut {cut}")
 
+    prms = [prm] * len(poses)
+
+    # one step: all poses in one call of the batched entry point (one list-size
+    # synchronisation, one persistent splat launch)
     def step():
-        for k, pose in enumerate(poses):
-            ctx.spl_render(parts, pose, prm, out=imgs[k], stats=False)
+        ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
 
     elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
     ms_per_step = 1e3 * elapsed / args.steps
@@ -263,8 +273,21 @@ def run_additive(args, torch, B):
         small += s
         pose_updates.append(u)
         del rec
-    updates /= len(poses)
-    roofline = roofline_for(B, ms, by, frames, updates)
+    # one persistent splat launch per step covers all poses
+    roofline = roofline_for(B, ms, by, args.steps, updates)
+    roofline["kernel"] = "k_splat_add_views" if roofline["kernel"] == "k_splat_add" else roofline["kernel"]
+    roofline["traffic"] = measured_traffic(roofline["kernel"], ps.n, tile, cut)
+
+    # the same step one view per call, with the library's per-stage events
+    def pstep():
+        for k, pose in enumerate(poses):
+            ctx.spl_render(parts, pose, prm, out=imgs[k], stats=False)
+
+    p_elapsed, p_ms, p_by, p_frames = timed_steps(ctx, pstep, args.steps, args.warmup, torch)
+    per_view = {"ms_per_step": 1e3 * p_elapsed / args.steps,
+                "particles_per_s": args.steps * len(poses) * ps.n / p_elapsed,
+                "stages": stage_table(B, p_ms, p_by, p_frames)}
+    log(f"one view per call: {per_view['ms_per_step']:.2f} ms/step")
     # per pose: splat time and the footprint that drives it
     per_pose = []
     for k, p in enumerate(poses):
@@ -278,30 +301,23 @@ def run_additive(args, torch, B):
                          "box_px_per_active": pose_updates[k] / max(stats[k]["n_active"], 1),
                          "frame_ms": sum(pm) / max(pf, 1),
                          "splat_ms": pm[B.STAGES.index("splat")] / max(pf, 1)})
-    roofline["traffic"] = measured_traffic(roofline["kernel"], ps.n, tile, cut)
 
-    # the same step through the batched entry point (one call for all poses)
-    batched = {}
-    for graphs in (0, 1):
-        ctx.spl_set_option(B.SPL_OPT_GRAPHS, graphs)
-        prms = [prm] * len(poses)
-
-        def bstep():
-            ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
-
+    # the batched step replayed as a captured graph
+    graphs = None
+    if not args.no_graph_replay:
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, 1)
         for _ in range(args.warmup):
-            bstep()
+            step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            bstep()
+            step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        batched["graphs" if graphs else "direct"] = {
-            "ms_per_step": 1e3 * dt / args.steps,
-            "particles_per_s": args.steps * len(poses) * ps.n / dt}
-    ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
-    log("batched: " + json.dumps(batched))
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+        graphs = {"ms_per_step": 1e3 * dt / args.steps,
+                  "particles_per_s": args.steps * len(poses) * ps.n / dt}
+        log("graph replay: " + json.dumps(graphs))
     if args.copy_probe_gib:
         # a plain device copy of known size: the reference point that scales
         # the HBM byte counters of a profiling run
@@ -352,7 +368,8 @@ def run_additive(args, torch, B):
     frame_bytes /= max(frames, 1)
     out = base_record(args, value, ms_per_step, "f32", {
         "workload": "Soneira-Peebles clustered set (4 levels x 8), 10M particles, 2 species, "
-                    "1024x1024, 8 random poses, additive absorption=emission, FP32",
+                    "1024x1024, 8 random poses per step in one batched call, additive "
+                    "absorption=emission, FP32",
         "n_particles": ps.n, "image": [1024, 1024], "poses": len(poses), "tile": tile,
         "large_cut_px": cut})
     out.update({
@@ -360,7 +377,8 @@ def run_additive(args, torch, B):
         "ms_per_frame": ms_per_step / len(poses),
         "roofline": roofline,
         "stages": stage_table(B, ms, by, frames),
-        "batched_entry_point": batched,
+        "one_view_per_call": per_view,
+        "batched_graph_replay": graphs,
         "per_pose": per_pose,
         "bandwidth_probe": probe,
         "mean_box_px_per_small_particle": updates * len(poses) / max(small, 1),
@@ -645,6 +663,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="additive: fixed tile (no autotune)")
     ap.add_argument("--cut", type=float, default=32.0, help="additive: fixed large cut with --tile")
     ap.add_argument("--no-probe", action="store_true", help="additive: skip the bandwidth probe")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="additive: skip the timing of the captured-graph replay")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="additive: also run one plain device copy of this size")
     ap.add_argument("--dtypes", default="bf16,f16", help="batched: attribute dtypes")

@@ -43,6 +43,7 @@ struct DevBuf {
 struct TimedFrame {
   hipEvent_t ev[SPL_N_STAGES + 1];
   double bytes[SPL_N_STAGES];
+  int frames = 1;  // views the events cover (a batch covers several)
 };
 
 }  // namespace
@@ -317,6 +318,7 @@ bool begin_timed(spl_ctx *c, TimedFrame &tf) {
     if (!tf.ev[k]) return false;
   }
   for (double &b : tf.bytes) b = 0.0;
+  tf.frames = 1;
   return true;
 }
 
@@ -341,7 +343,7 @@ void resolve_timing(spl_ctx *c, bool wait) {
       (void)hipGetLastError();
       c->acc_bytes[k] += tf.bytes[k];
     }
-    c->acc_frames += 1;
+    c->acc_frames += tf.frames;
     for (hipEvent_t e : tf.ev) c->event_pool.push_back(e);
   }
   c->pending.swap(keep);
@@ -588,6 +590,12 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   uint32_t *cursor = (uint32_t *)c->b_cursor.p, *itemoff = (uint32_t *)c->b_itemoff.p;
   Totals *tot = (Totals *)c->b_totals.p;
   const int chunk[3] = {kChunkSplat, 0, 0}, cchunk[3] = {kChunkLarge, 0, 0}, minc[3] = {1, 1, 1};
+  // stage timers cover the whole batch (launches without a captured graph):
+  // 0 projection, counts and scans of all views, 3 host gap, 4 items,
+  // scatter and image clears, 7 both persistent splat launches, 8 finalise
+  TimedFrame tfr;
+  TimedFrame *tf = (c->timing && !c->graphs && begin_timed(c, tfr)) ? &tfr : nullptr;
+  mark(tf, 0, s);
   HIPTRY(c, launch_fill_u32((uint32_t *)tot, 0u, (int64_t)nv * sizeof(Totals) / 4, s));
   for (int v = 0; v < nv; ++v) {
     const int nb = tk[v].n_tiles + tk[v].n_ctiles;
@@ -600,6 +608,9 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
                           cursor + v * bstride, chunk, cchunk, minc, itemoff + v * 3 * bstride,
                           tot + v, s));
   }
+  mark(tf, 1, s);
+  mark(tf, 2, s);
+  mark(tf, 3, s);
   HIPTRY(c, hipMemcpyAsync(c->h_btot, tot, sizeof(Totals) * nv, hipMemcpyDeviceToHost, s));
   HIPTRY(c, hipStreamSynchronize(s));
   // views are split into groups whose lists fit 32-bit offsets; the groups
@@ -657,7 +668,12 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   }
   // everything after the synchronisation depends only on the list sizes just
   // read; it is enqueued as one unit, directly or as a captured graph
+  if (ng != 1 && tf) {  // timers only for a single persistent launch
+    for (hipEvent_t e : tf->ev) c->event_pool.push_back(e);
+    tf = nullptr;
+  }
   auto post = [&](hipStream_t q) -> spl_status {
+    mark(tf, 4, q);
     for (int g = 0; g < ng; ++g) {
       const int v0 = g0s[g], v1 = g0s[g + 1];
       for (int v = v0; v < v1; ++v) {
@@ -679,8 +695,12 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       HIPTRY(c, hipMemcpyAsync(ctr, c->h_ctr + 2 * g, 2 * sizeof(uint32_t), hipMemcpyHostToDevice,
                                q));
       HIPTRY(c, launch_fill_u32(ctr + 2, 0u, 2, q));
+      mark(tf, 5, q);
+      mark(tf, 6, q);
+      mark(tf, 7, q);
       HIPTRY(c, launch_splat_views(tk[0].tile, dviews, itf, ctr, ctr + 2, itc, ctr + 1, ctr + 3,
                                    kChunkSplat, kChunkLarge, c->n_cu, q));
+      mark(tf, 8, q);
       double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
       for (int v = v0; v < v1; ++v) {
         const int64_t npx = (int64_t)tk[v].W * tk[v].H;
@@ -691,6 +711,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
         if (prm[v]->normalise) HIPTRY(c, launch_normalise(outs[v], npx, stats + 8 * v, q));
       }
     }
+    mark(tf, 9, q);
     return SPL_OK;
   };
   if (!c->graphs) {
@@ -723,6 +744,28 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     (void)hipGraphDestroy(graph);
     if (e == hipSuccess) e = hipGraphLaunch(c->gexec, s);
     if (e != hipSuccess) return fail(c, SPL_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
+  }
+  if (tf) {
+    // algorithmic bytes of the batch, summed over its views (same figures as
+    // the single-view frame)
+    const double attr = p->attr_dtype == SPL_F32 ? 4.0 : 2.0;
+    const double in_pp = 12.0 + 3.0 * attr + (p->species ? 1.0 : 0.0);
+    double *B = tf->bytes;
+    for (int v = 0; v < nv; ++v) {
+      const Totals &T = c->h_btot[v];
+      const double act = (double)T.n_active, pairs = (double)T.n_pairs;
+      const double fine = (double)T.n_fine_pairs, large = pairs - fine;
+      const double npx = (double)tk[v].W * tk[v].H, t2 = (double)tk[v].tile * tk[v].tile;
+      const double nbv = (double)(tk[v].n_tiles + tk[v].n_ctiles);
+      B[0] += (double)n * in_pp + act * 32.0 + (double)n * 8.0 +
+              (project_counts(tk[v]) ? 0.0 : (double)n * 8.0 + 4.0 * nbv) + 12.0 * nbv;
+      B[4] += 16.0 * (double)T.n_items[0] + (double)n * 8.0 + pairs * 4.0 + 12.0 * npx;
+      B[7] += fine * 36.0 + 24.0 * std::min(npx, (double)T.n_fine_nonempty * t2) + large * 36.0 +
+              24.0 * std::min(npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);
+      B[8] += 24.0 * npx;
+    }
+    tf->frames = nv;
+    c->pending.push_back(*tf);
   }
   double *stats = (double *)c->b_stats.p;
   bool any_stats = false;

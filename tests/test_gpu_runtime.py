@@ -74,6 +74,12 @@ def test_stage_timers_count_frames_and_reset(env):
     assert by[B.STAGES.index("project")] > 0 and by[B.STAGES.index("splat")] > 0
     ms2, by2, frames2 = ctx.spl_get_timing()  # reset by the previous call
     assert frames2 == 0 and sum(ms2) == 0
+    # the batched entry point times the whole batch and counts its views
+    ctx.spl_render_batch(parts, poses, [prm] * len(poses), stats=False)
+    torch.cuda.synchronize()
+    ms, by, frames = ctx.spl_get_timing()
+    assert frames == len(poses)
+    assert ms[B.STAGES.index("splat")] > 0 and by[B.STAGES.index("splat")] > 0
     ctx.spl_set_timing(False)
     ctx.spl_render(parts, poses[0], prm, stats=False)
     assert ctx.spl_get_timing()[2] == 0
