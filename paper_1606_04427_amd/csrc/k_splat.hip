@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_splat_add(const Item *__restrict_
 // Persistent form for many views: workgroups take (view, tile chunk) items
 // from a device counter until the queue is empty; every workgroup exits.
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_splat_add_views(const ViewK *__restrict__ views,
+__global__ __launch_bounds__(kBlock, 8) void k_splat_add_views(const ViewK *__restrict__ views,
                                                             const Item *__restrict__ items,
                                                             const uint32_t *__restrict__ n_items,
                                                             uint32_t *__restrict__ next,
