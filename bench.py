@@ -507,6 +507,13 @@ def run_batched(args, torch, B):
         parts = B.DeviceParticles(ps, dev, dt_name)
         torch.cuda.synchronize()
         prms = [prm] * len(poses)
+        if not args.no_autotune:
+            # one tuning per image size; the library keeps the choice per
+            # (particle count, image size, mode)
+            tuned = {}
+            for p in (big[0], small[0]):
+                tuned[f"{p.width}x{p.height}"] = ctx.spl_autotune(parts, p, prm)
+            log(f"{dt_name} autotune (tile, cut): {tuned}")
 
         def bstep():
             ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)

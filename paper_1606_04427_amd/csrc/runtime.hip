@@ -9,6 +9,7 @@
 // The single host synchronisation per frame reads the list sizes so that
 // every list and item buffer is sized exactly; no kernel can overflow a
 // buffer.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -27,6 +28,12 @@ namespace {
 
 constexpr int kChunkSplat = 1024;  // list entries per splat item, fine tiles
 constexpr int kChunkLarge = 512;   // list entries per large-particle item
+// List entries per splat item in the batch path.  A batch holds the items of
+// many views, so items four times longer still keep every slot of the device
+// busy, and a dense tile is then merged from a quarter as many partial
+// results (float atomics on the image); one view alone keeps the shorter
+// items, which balance better when a single view's lists are short.
+constexpr int kChunkViews = 4096;
 constexpr int kSortChunk = 4096;   // keys per in-LDS sort
 constexpr int kMergeOut = 2048;    // outputs per merge workgroup
 constexpr int kLargeTile = 64;     // px, tiles of the large-particle path
@@ -589,7 +596,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   uint32_t *counts = (uint32_t *)c->b_counts.p, *offsets = (uint32_t *)c->b_offsets.p;
   uint32_t *cursor = (uint32_t *)c->b_cursor.p, *itemoff = (uint32_t *)c->b_itemoff.p;
   Totals *tot = (Totals *)c->b_totals.p;
-  const int chunk[3] = {kChunkSplat, 0, 0}, cchunk[3] = {kChunkLarge, 0, 0}, minc[3] = {1, 1, 1};
+  const int chunk[3] = {kChunkViews, 0, 0}, cchunk[3] = {kChunkLarge, 0, 0}, minc[3] = {1, 1, 1};
   // stage timers cover the whole batch (launches without a captured graph):
   // 0 projection, counts and scans of all views, 3 host gap, 4 items,
   // scatter and image clears, 7 both persistent splat launches, 8 finalise
@@ -681,7 +688,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
         const int nb = tk[v].n_tiles + tk[v].n_ctiles;
         if (T.n_items[0])
           HIPTRY(c, launch_build_items(counts + v * bstride, offsets + v * bstride, nb,
-                                       tk[v].n_tiles, kChunkSplat, kChunkLarge, 1,
+                                       tk[v].n_tiles, kChunkViews, kChunkLarge, 1,
                                        itemoff + v * 3 * bstride, itf + fb[v], q, itc + cb[v],
                                        (uint32_t)T.n_fine_items[0], (uint32_t)(v - v0)));
         HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n,
@@ -699,7 +706,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       mark(tf, 6, q);
       mark(tf, 7, q);
       HIPTRY(c, launch_splat_views(tk[0].tile, dviews, itf, ctr, ctr + 2, itc, ctr + 1, ctr + 3,
-                                   kChunkSplat, kChunkLarge, c->n_cu, q));
+                                   kChunkViews, kChunkLarge, c->n_cu, q));
       mark(tf, 8, q);
       double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
       for (int v = v0; v < v1; ++v) {
@@ -801,7 +808,6 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
   std::vector<const spl_params *> pv;
   std::vector<float *> ov;
   std::vector<spl_stats *> sv;
-  int tile0 = 0;
   // every view is validated before any work is enqueued
   bool any_sorted = false;
   for (int v = 0; v < nv; ++v) {
@@ -824,9 +830,8 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
     int tile;
     double cut;
     choose(c, p->n, cams[v].width, cams[v].height, &prms[v], tile, cut);
-    if (!tile0) tile0 = tile;  // one tile size per persistent launch
     TileK t;
-    fill_tiles(t, cams[v].width, cams[v].height, tile0, prms[v].nu, cut, prms[v].bin_rule);
+    fill_tiles(t, cams[v].width, cams[v].height, tile, prms[v].nu, cut, prms[v].bin_rule);
     pk.push_back(k);
     tk.push_back(t);
     pv.push_back(&prms[v]);
@@ -835,13 +840,36 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
   }
   const int na = (int)pk.size();
   if (na == 0) return SPL_OK;
+  // one persistent launch serves one tile size: views are taken tile size by
+  // tile size (each keeps the tile it would get on its own), in call order
+  // within a size; the images are independent, so the order is free
+  std::vector<int> order(na);
+  for (int v = 0; v < na; ++v) order[v] = v;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return tk[a].tile < tk[b].tile; });
+  std::vector<ProjK> pk2(na);
+  std::vector<TileK> tk2(na);
+  std::vector<const spl_params *> pv2(na);
+  std::vector<float *> ov2(na);
+  std::vector<spl_stats *> sv2(na);
+  for (int i = 0; i < na; ++i) {
+    const int v = order[i];
+    pk2[i] = pk[v];
+    tk2[i] = tk[v];
+    pv2[i] = pv[v];
+    ov2[i] = ov[v];
+    sv2[i] = sv[v];
+  }
   // views per launch: what the memory budget allows (records, spans and about
   // two list entries per particle, per view)
   const int64_t per_view = p->n * (32 + 8 + 8) + ((int64_t)4 << 20);
-  int per = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBatchViews, c->budget / std::max<int64_t>(per_view, 1)));
-  for (int v0 = 0; v0 < na; v0 += per) {
-    const int m = std::min(per, na - v0);
-    TRY(render_views(c, p, m, &pk[v0], &tk[v0], &pv[v0], &ov[v0], &sv[v0], s));
+  const int per = (int)std::max<int64_t>(
+      1, std::min<int64_t>(kMaxBatchViews, c->budget / std::max<int64_t>(per_view, 1)));
+  for (int v0 = 0; v0 < na;) {
+    int m = 1;
+    while (m < per && v0 + m < na && tk2[v0 + m].tile == tk2[v0].tile) ++m;
+    TRY(render_views(c, p, m, &pk2[v0], &tk2[v0], &pv2[v0], &ov2[v0], &sv2[v0], s));
+    v0 += m;
   }
   return SPL_OK;
 }

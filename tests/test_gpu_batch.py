@@ -131,3 +131,59 @@ def test_batch_rejects_bad_view(env):
     prms = [B.make_params(1, P, looks) for _ in poses]
     with pytest.raises(B.SplotchError):
         ctx.spl_render_batch(parts, poses, prms)
+
+
+def test_batch_with_empty_views(env):
+    """A view that sees no particle (camera looking away from the set) and an
+    empty particle set give black images and zero statistics in a batch."""
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals = _setup(B, n=20_000, seed=55)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    away = synth.Pose((0.5, 0.5, 3.0), (0.5, 0.5, 6.0), (0, 1, 0), 50.0, 0.05, 128, 96)
+    poses = [away] + _poses()[:2]
+    prms = [B.make_params(1, P, looks, tile=16) for _ in poses]
+    outs, sts = ctx.spl_render_batch(parts, poses, prms)
+    torch.cuda.synchronize()
+    assert sts[0]["n_active"] == 0 and sts[0]["n_pairs"] == 0
+    assert not outs[0].any().item()
+    assert sts[0]["flux"] == [0.0, 0.0, 0.0]
+    for o, st in zip(outs[1:], sts[1:]):
+        assert st["n_active"] > 0 and o.any().item()
+    empty = synth.ParticleSet(*(np.zeros(0, np.float32) for _ in range(6)), np.zeros(0, np.uint8))
+    eparts = B.DeviceParticles(empty, "cuda:0")
+    outs, sts = ctx.spl_render_batch(eparts, poses, prms)
+    torch.cuda.synchronize()
+    assert all(s["n_active"] == 0 for s in sts)
+    assert not any(o.any().item() for o in outs)
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_batch_mixed_tile_sizes(env, graphs):
+    """Views asking for different tile sizes are served tile size by tile size;
+    each keeps its own tile and its image and statistics equal the single-view
+    render, whatever their order in the call."""
+    import torch
+
+    B, ctx, _ = env
+    ps, looks, pals = _setup(B, n=60_000, seed=56)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    poses = _poses()
+    tiles = [32, 16, 32, 16, 16, 32]
+    modes = [1, 1, 0, 2, 1, 1]
+    prms = [B.make_params(m, P, looks, tile=t, large_cut=32.0) for m, t in zip(modes, tiles)]
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, graphs)
+    try:
+        outs, sts = ctx.spl_render_batch(parts, poses, prms)
+        torch.cuda.synchronize()
+    finally:
+        ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+    for pose, prm, t, o, st in zip(poses, prms, tiles, outs, sts):
+        single, st1 = ctx.spl_render(parts, pose, prm)
+        torch.cuda.synchronize()
+        assert st["tile"] == t == st1["tile"]
+        assert st["n_pairs"] == st1["n_pairs"]
+        assert rel_l2(o.cpu().numpy(), single.cpu().numpy()) < 1e-6
