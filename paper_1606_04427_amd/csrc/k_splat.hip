@@ -9,8 +9,8 @@
 // k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of list
 //                  entries is staged in LDS and appended to the lists of the
 //                  4 x 4 micro-tiles it meets; the lists, laid end to end, are
-//                  cut into equal ranges for the 16-lane groups (one pixel per
-//                  lane), with running sums in registers flushed into a
+//                  cut into 16 near-equal ranges for the 16-lane groups (one
+//                  pixel per lane), with running sums in registers flushed into a
 //                  32-bit fixed-point LDS accumulator at micro-tile changes.
 //                  Batch sums fold into per-pixel Neumaier-compensated FP32
 //                  sums.
@@ -21,6 +21,8 @@
 //                  built by ballots, one micro-tile per 16-lane group,
 //                  front-to-back slab compositing per pixel in list order;
 //                  transmittance per pixel in registers.
+#include <type_traits>
+
 #include "spl_internal.h"
 
 namespace spl {
@@ -44,10 +46,13 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 // premultiplied colour).  The tile is split into 4 x 4 micro-tiles and each
 // staged entry appends itself to the list of every micro-tile its box meets
 // (LDS integer atomics; order inside a list is free for a sum).  The lists,
-// laid end to end, are cut into 16 equal ranges, one per 16-lane group; all
-// groups step through their ranges together, one list entry per step, so the
-// four groups of a wave, which run in lockstep, take the same number of steps
-// however unevenly the entries fall on the micro-tiles.  One pixel per lane;
+// laid end to end, are cut into 16 ranges whose lengths differ by at most
+// one, one per 16-lane group; all groups step through their ranges together,
+// one list entry per step, so the four groups of a wave, which run in
+// lockstep, take the same number of steps however unevenly the entries fall
+// on the micro-tiles.  The per-step work is one compare for the end of the
+// current list, the entry's staging offset and the Gaussian; the step that
+// only the longer ranges take is peeled off the loop.  One pixel per lane;
 // the running sum stays in registers while consecutive entries belong to the
 // same micro-tile and is added into a 32-bit fixed-point LDS accumulator
 // (integer atomics: neighbouring ranges may share a micro-tile) when the
@@ -67,7 +72,11 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   constexpr float kLog2e = 1.4426950408889634f;
   __shared__ float4 s_pos[kBlock];     // Xi - x0, 0.5 - Xf, Yi - y0, 0.5 - Yf
   __shared__ float4 s_col[kBlock];     // log2(e)/sigma^2, premultiplied colour
-  __shared__ __align__(4) uint8_t s_list[NQ][kBlock];
+  // list entries: byte offsets into s_pos / s_col (16-bit, 16 px tiles) or
+  // staging slots (8-bit, 32 px tiles, where the lists take 4x the LDS)
+  using LT = typename std::conditional<T == 16, uint16_t, uint8_t>::type;
+  constexpr int kShift = T == 16 ? 0 : 4;
+  __shared__ __align__(4) LT s_list[NQ][kBlock];
   __shared__ int s_len[2][NQ];         // list lengths; batches alternate buffers
   __shared__ int s_start[NQ + 1];      // list offsets laid end to end
   __shared__ int s_iacc[3][NP];        // batch sums, fixed point
@@ -114,7 +123,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
           for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy)
             for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
               const int q = qy * MX + qx;
-              s_list[q][atomicAdd(&len[q], 1)] = (uint8_t)tid;
+              s_list[q][atomicAdd(&len[q], 1)] = (LT)(tid << (4 - kShift));
             }
         }
       }
@@ -140,50 +149,56 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
     (void)frexpf(s_amp[0] + s_amp[1] + s_amp[2] + s_amp[3], &ex);  // sum <= 2^ex
     const int S = 30 - ex;
     {
+      // the lists laid end to end are cut into 16 ranges whose lengths differ
+      // by at most one: every group takes `steps` entries, the first `rem`
+      // groups one more
       const int total = s_start[NQ];
-      const int steps = (total + 15) >> 4;
-      const int r0 = min(grp * steps, total), r1 = min(r0 + steps, total);
-      // the group's first micro-tile: the first whose list ends after r0
+      const int steps = total >> 4, rem = total & 15;
+      const int r0 = grp * steps + min(grp, rem);
+      // the group's micro-tile at r0: the last list starting at or before it
       int q = 0;
-      while (q < NQ - 1 && s_start[q + 1] <= r0) ++q;
-      int qs = s_start[q], qe = s_start[q + 1];
+#pragma unroll
+      for (int h = NQ / 2; h >= 1; h >>= 1)
+        if (s_start[q + h] <= r0) q += h;
+      // lp: index in s_list of the next entry; le: end of the current list
+      int lp = q * kBlock + (r0 - s_start[q]);
+      int le = q * kBlock + (s_start[q + 1] - s_start[q]);
       int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
       float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll 4
-      for (int t = 0; t < steps; ++t) {  // uniform across the workgroup
-        const int u = r0 + t;
-        if (u < r1) {
-          if (u >= qe) {
-            // next micro-tile: flush the running sums
-            atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
-            atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
-            atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
-            a0 = a1 = a2 = 0.f;
-            do {
-              ++q;
-            } while (s_start[q + 1] <= u);
-            qs = s_start[q];
-            qe = s_start[q + 1];
-            pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
-            px = (float)((q % MX) * 4 + lx);
-            py = (float)((q / MX) * 4 + ly);
-          }
-          const int j = s_list[q][u - qs];
-          const float4 p = s_pos[j];
-          const float4 c = s_col[j];
-          const float dx = (px - p.x) + p.y;
-          const float dy = (py - p.z) + p.w;
-          const float qq = (dx * dx + dy * dy) * c.x;
-          // qq <= qmax keeps the result far above the denormal range, so
-          // the hardware exponential needs no range fix-up
-          const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
-          a0 += c.y * e;
-          a1 += c.z * e;
-          a2 += c.w * e;
+      auto step = [&]() {
+        if (lp == le) {
+          // next micro-tile: flush the running sums
+          atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
+          atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
+          atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
+          a0 = a1 = a2 = 0.f;
+          do {
+            ++q;
+          } while (s_start[q + 1] == s_start[q]);
+          lp = q * kBlock;
+          le = lp + (s_start[q + 1] - s_start[q]);
+          pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
+          px = (float)((q % MX) * 4 + lx);
+          py = (float)((q / MX) * 4 + ly);
         }
-      }
-      if (r0 < r1) {
+        const int jb = (int)(&s_list[0][0])[lp++] << kShift;  // byte offset
+        const float4 p = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_pos) + jb);
+        const float4 c = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_col) + jb);
+        const float dx = (px - p.x) + p.y;
+        const float dy = (py - p.z) + p.w;
+        const float qq = (dx * dx + dy * dy) * c.x;
+        // qq <= qmax keeps the result far above the denormal range, so
+        // the hardware exponential needs no range fix-up
+        const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
+        a0 += c.y * e;
+        a1 += c.z * e;
+        a2 += c.w * e;
+      };
+#pragma unroll 4
+      for (int t = 0; t < steps; ++t) step();  // uniform across the workgroup
+      if (grp < rem) step();
+      if (steps > 0 || grp < rem) {
         atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
         atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
         atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
