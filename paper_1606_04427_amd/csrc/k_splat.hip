@@ -409,11 +409,19 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
   }
 }
 
-// Sorted mode.  Staging and micro-tile lists as in splat_add_item; the lists
-// keep the depth order of the tile list, so each lane composites its pixel
-// front to back: C += T E tau phi(a tau), T *= exp(-a tau), with
+// Sorted mode.  Staging as in splat_add_item; each micro-tile's list is built
+// by ballots in the depth order of the tile list.  The lists, laid end to
+// end, are cut into 16 ranges whose lengths differ by at most one, one per
+// 16-lane group, and walked in lockstep as in the additive kernel.  A group
+// composites each piece of a micro-tile list it meets front to back from
+// (C, T) = (0, 1): C += T E tau phi(a tau), T *= exp(-a tau), with
 // phi(x) = (1 - e^-x)/x from its Taylor series below x = 1/2 (no
-// cancellation) and from the exponential above.
+// cancellation) and from the exponential above, and leaves the piece's
+// (C, T) in LDS.  After the walk each lane merges, for its pixels, the pieces
+// of the batch in list order into the running (C, T): C += T C_piece,
+// T *= T_piece.  The pieces of one batch fill at most NQ + 15 slots: the
+// (group, micro-tile) pairs of the walk form a staircase, so group + micro-tile
+// numbers them.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ items,
                                                       const unsigned long long *__restrict__ keys,
@@ -426,15 +434,21 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
                                                       float *__restrict__ img,
                                                       float4 *__restrict__ partial) {
   constexpr int NP = T * T;
+  constexpr int PX = NP / kBlock;      // pixels per lane in the merge
   constexpr int MX = T / 4;
-  constexpr int MT = MX * MX / 16;
+  constexpr int NQ = MX * MX;
+  constexpr int MT = NQ / 16;          // lists built per group
+  constexpr int NS = NQ + 15;          // piece slots
   constexpr float kLog2e = 1.4426950408889634f;
   constexpr uint32_t kEmpty = 0x000000ffu | 0x00ff0000u;
   __shared__ float4 s_pos[kBlock];
   __shared__ float4 s_col[kBlock];
   __shared__ float s_ap[kBlock];       // a / (pi sigma^2)
   __shared__ uint32_t s_box[kBlock];
-  __shared__ __align__(4) uint8_t s_list[16][kBlock];
+  __shared__ __align__(4) uint8_t s_list[NQ][kBlock];
+  __shared__ int s_len[NQ];
+  __shared__ int s_start[NQ + 1];
+  __shared__ float4 s_piece[NS][16];   // per slot and micro-tile pixel: C rgb, T
 
   const Item it = items[blockIdx.x];
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
@@ -446,11 +460,11 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
-  uint8_t *const my_list = s_list[grp];
 
-  float C[MT][3], Cc[MT][3], Tr[MT];
+  // running (C, T) of the lane's pixels p2 = tid + m * kBlock
+  float C[PX][3], Cc[PX][3], Tr[PX];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
+  for (int m = 0; m < PX; ++m) {
     Tr[m] = 1.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -479,6 +493,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
     }
     s_box[tid] = box;
     __syncthreads();
+    // in-order list of every micro-tile, built by ballots of its group
     const int nb = (int)min((uint32_t)kBlock, it.z - base);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -492,16 +507,52 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
         const int bj0 = (int)((b >> 16) & 0xffu), bj1 = (int)(b >> 24);
         const bool hit = (bi0 <= mx0 + 3) & (bi1 >= mx0) & (bj0 <= my0 + 3) & (bj1 >= my0);
         const uint32_t bits = (uint32_t)(__ballot(hit) >> (16 * gw)) & 0xffffu;
-        if (hit) my_list[cnt + __popc(bits & ((1u << l) - 1u))] = (uint8_t)j;
+        if (hit) s_list[q][cnt + __popc(bits & ((1u << l) - 1u))] = (uint8_t)j;
         cnt += __popc(bits);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const float px = (float)(mx0 + lx), py = (float)(my0 + ly);
-      float b0 = 0.f, b1 = 0.f, b2 = 0.f, tr = Tr[m];
-      for (int i = 0; i < cnt; ++i) {
-        const int j = my_list[i];
+      if (l == 0) s_len[q] = cnt;
+    }
+    __syncthreads();
+    // list offsets (one wave: NQ <= 64)
+    if (tid < 64) {
+      const int v = tid < NQ ? s_len[tid] : 0;
+      int incl = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (tid >= o) incl += u;
+      }
+      if (tid < NQ) s_start[tid] = incl - v;
+      if (tid == NQ - 1) s_start[NQ] = incl;
+    }
+    __syncthreads();
+    const int total = s_start[NQ];
+    const int steps = total >> 4, rem = total & 15;
+    {
+      const int r0 = grp * steps + min(grp, rem);
+      int q = 0;
+#pragma unroll
+      for (int h = NQ / 2; h >= 1; h >>= 1)
+        if (s_start[q + h] <= r0) q += h;
+      int lp = q * kBlock + (r0 - s_start[q]);
+      int le = q * kBlock + (s_start[q + 1] - s_start[q]);
+      float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
+      float b0 = 0.f, b1 = 0.f, b2 = 0.f, tr = 1.f;
+      auto step = [&]() {
+        if (lp == le) {
+          // end of this piece of the micro-tile's list
+          s_piece[grp + q][l] = make_float4(b0, b1, b2, tr);
+          b0 = b1 = b2 = 0.f;
+          tr = 1.f;
+          do {
+            ++q;
+          } while (s_start[q + 1] == s_start[q]);
+          lp = q * kBlock;
+          le = lp + (s_start[q + 1] - s_start[q]);
+          px = (float)((q % MX) * 4 + lx);
+          py = (float)((q / MX) * 4 + ly);
+        }
+        const int j = (&s_list[0][0])[lp++];
         const float4 p = s_pos[j];
         const float4 c = s_col[j];
         const float dx = (px - p.x) + p.y;
@@ -530,21 +581,42 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
           b2 = fmaf(tw, c.w, b2);
           tr = fmaf(tr, em, tr);
         }
+      };
+      for (int t = 0; t < steps; ++t) step();  // uniform across the workgroup
+      if (grp < rem) step();
+      if (steps > 0 || grp < rem) s_piece[grp + q][l] = make_float4(b0, b1, b2, tr);
+    }
+    __syncthreads();
+    // merge the pieces of each pixel's micro-tile in list order
+    if (total > 0) {
+      const int big = rem * (steps + 1);  // positions held by the longer ranges
+      auto group_of = [&](int r) { return r < big ? r / (steps + 1) : rem + (r - big) / steps; };
+#pragma unroll
+      for (int m = 0; m < PX; ++m) {
+        const int p2 = tid + m * kBlock;
+        const int lpx = p2 % T, lpy = p2 / T;
+        const int q = (lpy >> 2) * MX + (lpx >> 2), ql = (lpy & 3) * 4 + (lpx & 3);
+        const int a = s_start[q], e = s_start[q + 1];
+        if (a < e) {
+          const int g1 = group_of(e - 1);
+          for (int g = group_of(a); g <= g1; ++g) {
+            const float4 pc = s_piece[g + q][ql];
+            neumaier(C[m][0], Cc[m][0], Tr[m] * pc.x);
+            neumaier(C[m][1], Cc[m][1], Tr[m] * pc.y);
+            neumaier(C[m][2], Cc[m][2], Tr[m] * pc.z);
+            Tr[m] *= pc.w;
+          }
+        }
       }
-      Tr[m] = tr;
-      neumaier(C[m][0], Cc[m][0], b0);
-      neumaier(C[m][1], Cc[m][1], b1);
-      neumaier(C[m][2], Cc[m][2], b2);
-      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int q = grp + 16 * m;
-    const int lpx = (q % MX) * 4 + lx, lpy = (q / MX) * 4 + ly;
+  for (int m = 0; m < PX; ++m) {
+    const int p2 = tid + m * kBlock;
+    const int lpx = p2 % T, lpy = p2 / T;
     if (multi) {
-      partial[(size_t)blockIdx.x * NP + lpy * T + lpx] =
+      partial[(size_t)blockIdx.x * NP + p2] =
           make_float4(C[m][0] + Cc[m][0], C[m][1] + Cc[m][1], C[m][2] + Cc[m][2], Tr[m]);
     } else {
       const int gx = x0 + lpx, gy = y0 + lpy;
