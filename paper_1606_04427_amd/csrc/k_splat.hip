@@ -120,11 +120,24 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
           s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
           s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
           amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
-          for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy)
+          // micro-tiles of the box whose pixel centres the truncation disc
+          // can reach (tested against the micro-tile's rectangle of pixel
+          // centres, with a margin over the evaluation's rounding)
+          const float ux = (r0.x - (float)x0) + (r0.y - 0.5f);
+          const float uy = (r0.z - (float)y0) + (r0.w - 0.5f);
+          const float rr = tk.nu * r1.x;
+          const float r2m = fmaf(rr * rr, 1.0001f, 1e-3f);
+          for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy) {
+            const float ey = fmaxf(fmaxf((float)(4 * qy) - uy, uy - (float)(4 * qy + 3)), 0.f);
+            const float ey2 = ey * ey;
             for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
-              const int q = qy * MX + qx;
-              s_list[q][atomicAdd(&len[q], 1)] = (LT)(tid << (4 - kShift));
+              const float ex = fmaxf(fmaxf((float)(4 * qx) - ux, ux - (float)(4 * qx + 3)), 0.f);
+              if (fmaf(ex, ex, ey2) <= r2m) {
+                const int q = qy * MX + qx;
+                s_list[q][atomicAdd(&len[q], 1)] = (LT)(tid << (4 - kShift));
+              }
             }
+          }
         }
       }
     }
