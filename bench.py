@@ -518,12 +518,21 @@ def run_batched(args, torch, B):
         def bstep():
             ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
 
+        def gstep():
+            # the same call with the launches after each list-size
+            # synchronisation captured and replayed as a graph
+            ctx.spl_set_option(B.SPL_OPT_GRAPHS, 1)
+            try:
+                ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
+            finally:
+                ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+
         def pstep():
             for k, p in enumerate(poses):
                 ctx.spl_render(parts, p, prm, out=imgs[k], stats=False)
 
         res = {}
-        for name, fn in (("batched", bstep), ("per_view", pstep)):
+        for name, fn in (("batched", bstep), ("batched_graph", gstep), ("per_view", pstep)):
             fn()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

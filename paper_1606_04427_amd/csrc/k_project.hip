@@ -5,9 +5,10 @@
 //
 // One thread per particle, grid-stride, coalesced structure-of-arrays loads.
 // Position arithmetic runs in FP64 so the single-precision record keeps the
-// screen position as integer part + fraction.  The colour map lookup runs in
-// FP32.  Output per active particle: a 32-byte record, optionally the 8-byte
-// sorted-mode record, and the 8-byte tile span read by the binning kernels.
+// screen position as integer part + fraction.  The colour map lookup and the
+// peak amplitude 1/(pi sigma^2) (from the stored sigma) run in FP32.  Output
+// per active particle: a 32-byte record, optionally the 8-byte sorted-mode
+// record, and the 8-byte tile span read by the binning kernels.
 #include "bin_device.h"
 
 namespace spl {
@@ -36,11 +37,15 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
                                                     uint32_t *__restrict__ counts) {
   extern __shared__ uint32_t hist[];
   __shared__ unsigned int s_act, s_large;
+  // the species' looks, read per lane (the species select would otherwise
+  // keep every look in scalar registers)
+  __shared__ LookK s_looks[SPL_MAX_SPECIES];
   const int nb = tk.n_tiles + tk.n_ctiles;
   if (threadIdx.x == 0) {
     s_act = 0;
     s_large = 0;
   }
+  if (threadIdx.x < SPL_MAX_SPECIES) s_looks[threadIdx.x] = P.looks[threadIdx.x];
   if (kCount)
     for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
   __syncthreads();
@@ -67,7 +72,10 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
         if (zv > P.z_near) {
           const double xv = vx * P.r[0] + vy * P.r[1] + vz * P.r[2];
           const double yv = vx * P.u[0] + vy * P.u[1] + vz * P.u[2];
-          const double iz = 1.0 / zv;
+          // 1/zv: hardware reciprocal and two Newton steps (zv > z_near > 0)
+          double iz = __builtin_amdgcn_rcp(zv);
+          iz = fma(iz, fma(-zv, iz, 1.0), iz);
+          iz = fma(iz, fma(-zv, iz, 1.0), iz);
           const double X = P.cx + P.F * xv * iz;
           const double Y = P.cy - P.F * yv * iz;
           const double rho = P.F * (double)h * iz;
@@ -75,10 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
           const double sig = sqrt(ks * ks + P.sigma_min * P.sigma_min);
           const double R = P.nu * sig;
           if (fabs(X - P.cx) <= 4194304.0 && fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0) {
-            LookK L = P.looks[0];
-  #pragma unroll
-            for (int j = 1; j < SPL_MAX_SPECIES; ++j)
-              if (sp == j) L = P.looks[j];
+            const LookK L = s_looks[sp];
             float t;
             if (L.log10)
               t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
@@ -104,12 +109,14 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
             const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
             const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
             if (emits || (P.mode == SPL_SORTED && a > 0.0f)) {
-              const double amp = 1.0 / (3.14159265358979323846 * sig * sig);
+              // peak amplitude 1/(pi sigma^2) in single precision from the
+              // stored sigma
+              const float sg = (float)sig;
+              const float amp = __builtin_amdgcn_rcpf(3.14159265f * sg * sg);
               const double fX = floor(X), fY = floor(Y);
               o0 = make_float4((float)fX, (float)(X - fX), (float)fY, (float)(Y - fY));
-              o1 = make_float4((float)sig, (float)((double)E0 * amp), (float)((double)E1 * amp),
-                               (float)((double)E2 * amp));
-              o2 = make_float2((float)((double)a * amp), (float)zv);
+              o1 = make_float4(sg, E0 * amp, E1 * amp, E2 * amp);
+              o2 = make_float2(a * amp, (float)zv);
               spn = record_span(o0, o1.x, tk);
               active = spn.x != kInactive;
             }

@@ -586,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
             em = -x * phi;
           } else {
             em = __builtin_amdgcn_exp2f(-x * kLog2e) - 1.f;
-            phi = -em / x;
+            phi = -em * __builtin_amdgcn_rcpf(x);
           }
           const float tw = tr * e * phi;
           b0 = fmaf(tw, c.y, b0);
