@@ -327,6 +327,59 @@ def test_render_records_matched_input(env, mode, tile, cut):
     assert e <= P1_TOL, f"rel-L2 {e:.3e}"
 
 
+@pytest.mark.parametrize("tile", [16, 32])
+def test_discs_that_just_reach_a_micro_tile(env, tile):
+    """Hand-made records whose truncation disc reaches a neighbouring 4 x 4
+    pixel block only at one pixel centre, a hair inside the radius (plus
+    twins a hair outside): the splat lists an entry on a block only if its
+    disc can reach one of the block's pixel centres, so a test that is too
+    tight would lose exactly these edge pixels.  Every pixel is compared
+    with the FP64 oracle on the same records."""
+    import torch
+
+    B, ctx, R = env
+    W = H = 4 * tile
+    rows = []
+    k = 0
+    cases = [(f, dg) for f in (1 - 1e-5, 1 - 1e-4) for dg in (True, False)] + [(1 + 1e-4, True)]
+    for sig in (0.5, 1.0, 2.3):
+        r = 3.0 * sig
+        for frac, diag in cases:
+                ox, oy = tile * (k % 4), tile * ((k // 4) % 4)
+                k += 1
+                d = r * frac
+                # the target pixel centre, (ox + 4.5, oy + 4.5) diagonally or
+                # (ox + 4.5, oy + 2.5) sideways, is the first of the block to
+                # the right; the sideways particle sits a quarter pixel off
+                # the pixel rows so that no other pixel centre lies at the
+                # radius by accident
+                if diag:
+                    X = Y = 4.5 - d / np.sqrt(2.0)
+                else:
+                    X, Y = 4.5 - np.sqrt(d * d - 0.0625), 2.75
+                X, Y = ox + X, oy + Y
+                xi, yi = np.floor(X), np.floor(Y)
+                rows.append([xi, X - xi, yi, Y - yi, sig, 1.0, 0.5, 0.25])
+    rec_h = np.asarray(rows, np.float32)
+    assert len(rows) <= 16
+    rec = torch.from_numpy(rec_h).to("cuda:0")
+    pose = synth.Pose((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 40.0, 1e-3, W, H)
+    prm = B.make_params(0, B.Palettes([synth.palette(0)]),
+                        [dict(log10=0, brightness=1.0, lo=0.0, hi=1.0)], tile=tile,
+                        large_cut=-1.0)
+    img, _ = ctx.spl_render_records(rec, None, pose, prm)
+    torch.cuda.synchronize()
+    got = img.cpu().numpy().astype(np.float64)
+    ref = R.render_records(rec_h, None, W, H, 0)
+    # the weakest kept contribution (record amplitudes are premultiplied);
+    # the slack covers the fixed-point quantum of a batch (~2^-30 of the
+    # summed amplitudes), far below one lost edge contribution
+    edge = np.exp(-9.0) * 0.25
+    assert np.abs(ref).max() > 0
+    err = np.abs(got - ref)
+    assert np.all(err <= 1e-5 * np.abs(ref) + 1e-2 * edge), float(err.max())
+
+
 def test_paper_bin_rule_render(env):
     """bin_rule 1 drops the corner overlaps the paper calls negligible: the
     image differs from the exact one only by those dropped contributions."""
