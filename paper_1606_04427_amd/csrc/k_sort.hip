@@ -9,7 +9,8 @@
 //                 one chunk is done.
 //  k_merge_pass   longer lists: sorted runs of length L merged pairwise into
 //                 runs of 2L; one workgroup per 2048 outputs stages its inputs
-//                 in LDS, each lane merges 8 keys.
+//                 in LDS, each lane merges 8 keys into LDS, and the outputs
+//                 leave with coalesced stores.
 #include "spl_internal.h"
 
 namespace spl {
@@ -28,11 +29,13 @@ __device__ __forceinline__ void reg_stage(unsigned long long (&v)[E], int t, int
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       if ((e & J) == 0) {
+        // ascending pairs swap when b < a, descending ones when not (equal
+        // keys are only padding, so swapping them changes nothing)
         const bool up = ((t * E + e) & k) == 0;
         const unsigned long long a = v[e], b = v[e + J];
-        const unsigned long long lo = a < b ? a : b, hi = a < b ? b : a;
-        v[e] = up ? lo : hi;
-        v[e + J] = up ? hi : lo;
+        const bool sw = (b < a) == up;
+        v[e] = sw ? b : a;
+        v[e + J] = sw ? a : b;
       }
     }
   }
@@ -67,13 +70,14 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
         }
       } else {
         const int m = j / E;  // partner thread: t ^ m
+        // j >= E and k > j: whether the lane keeps the smaller key does not
+        // depend on e
+        const bool keep_min = ((t * E & j) == 0) == ((t * E & k) == 0);
         if (m < 64) {
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const int i = t * E + e;
             const unsigned long long w = __shfl_xor(v[e], m);
-            const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
-            v[e] = keep_min ? min(v[e], w) : max(v[e], w);
+            v[e] = ((w < v[e]) == keep_min) ? w : v[e];
           }
         } else {
           __syncthreads();
@@ -82,10 +86,8 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
           __syncthreads();
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const int i = t * E + e;
             const unsigned long long w = s[padded((t ^ m) * E + e)];
-            const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
-            v[e] = keep_min ? min(v[e], w) : max(v[e], w);
+            v[e] = ((w < v[e]) == keep_min) ? w : v[e];
           }
         }
       }
@@ -143,8 +145,9 @@ __device__ __forceinline__ int64_t wave_merge_split(const unsigned long long *__
 // A workgroup owns kMergeOut consecutive outputs of one list (they fall in one
 // pair of runs because 2L is a multiple of kMergeOut).  Waves 0 and 1 find
 // where the merge path enters and leaves that output range, the inputs
-// between are staged in LDS with coalesced loads, and each lane merges 8
-// outputs from LDS after a binary search there.
+// between are staged in LDS with coalesced loads, each lane merges 8
+// outputs from LDS after a binary search there, and the merged range is
+// written back with coalesced stores.
 __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long *__restrict__ src,
                                                        unsigned long long *__restrict__ dst,
                                                        const Item *__restrict__ items,
@@ -152,6 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
                                                        const uint32_t *__restrict__ counts,
                                                        int64_t L) {
   __shared__ unsigned long long s_k[kMergeOut];
+  __shared__ unsigned long long s_o[kMergeOut];  // merged outputs, stored coalesced
   __shared__ int64_t s_split[2];
   const Item it = items[blockIdx.x];
   const int64_t s0 = offsets[it.x];
@@ -177,27 +181,30 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
   __syncthreads();
   const int tot = na + nb;
   const int dl = 8 * (int)threadIdx.x;
-  if (dl >= tot) return;
-  const unsigned long long *As = s_k, *Bs = s_k + na;
-  int lo = max(0, dl - nb), hi = min(dl, na);
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (As[mid] < Bs[dl - 1 - mid])
-      lo = mid + 1;
-    else
-      hi = mid;
+  if (dl < tot) {
+    const unsigned long long *As = s_k, *Bs = s_k + na;
+    int lo = max(0, dl - nb), hi = min(dl, na);
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (As[mid] < Bs[dl - 1 - mid])
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    int i = lo, j = dl - lo;
+    const int cnt = min(8, tot - dl);
+    for (int o = 0; o < cnt; ++o) {
+      unsigned long long v;
+      if (j >= nb || (i < na && As[i] < Bs[j]))
+        v = As[i++];
+      else
+        v = Bs[j++];
+      s_o[dl + o] = v;
+    }
   }
-  int i = lo, j = dl - lo;
-  unsigned long long *out = dst + s0 + d0 + dl;
-  const int cnt = min(8, tot - dl);
-  for (int o = 0; o < cnt; ++o) {
-    unsigned long long v;
-    if (j >= nb || (i < na && As[i] < Bs[j]))
-      v = As[i++];
-    else
-      v = Bs[j++];
-    out[o] = v;
-  }
+  __syncthreads();
+  unsigned long long *out = dst + s0 + d0;
+  for (int k = threadIdx.x; k < tot; k += kBlock) out[k] = s_o[k];
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_items(const unsigned long long *__restrict__ src,
