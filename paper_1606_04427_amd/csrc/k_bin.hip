@@ -148,7 +148,10 @@ struct ScanArgs {
 // One workgroup: each thread sums a run of consecutive bins (entries and the
 // item counts of the three chunkings), the runs are scanned with wave
 // shuffles and one pass over the wave totals, and each thread writes its
-// bins' offsets.
+// bins' offsets.  kLds: the counts are first staged in LDS with coalesced
+// loads, so that the threads' runs (consecutive bins per thread) are read
+// from LDS rather than with strided global loads.
+template <bool kLds>
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restrict__ counts,
                                                        int nb, int n_fine,
                                                        uint32_t *__restrict__ offsets,
@@ -156,10 +159,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
                                                        uint32_t *__restrict__ item_off,
                                                        Totals *__restrict__ tot) {
   constexpr int NW = kScanThreads / 64;
+  extern __shared__ uint32_t s_cnt[];
   __shared__ unsigned long long s_w[4][NW];
   __shared__ unsigned int s_max, s_nef, s_nec;
   __shared__ unsigned long long s_l2;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const uint32_t *const cnt = kLds ? s_cnt : counts;
+  if (kLds) {
+    for (int i = t; i < nb; i += kScanThreads) s_cnt[i] = counts[i];
+    __syncthreads();
+  }
   if (t == 0) {
     s_max = 0;
     s_nef = 0;
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   unsigned int mx = 0, nef = 0, nec = 0;
   unsigned long long l2 = 0;
   for (int b = b0; b < b1; ++b) {
-    const uint32_t c = counts[b];
+    const uint32_t c = cnt[b];
     loc[0] += c;
     uint32_t ik[3];
 #pragma unroll
@@ -224,7 +233,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
 #pragma unroll
   for (int q = 0; q < 4; ++q) run[q] = (wv ? s_w[q][wv - 1] : 0ull) + inc[q] - loc[q];
   for (int b = b0; b < b1; ++b) {
-    const uint32_t c = counts[b];
+    const uint32_t c = cnt[b];
     if (b == n_fine && tot) {
       tot->n_fine_pairs = run[0];
       for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = run[1 + k];
@@ -320,8 +329,19 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
     a.cshift[k] = shift_of(cchunk[k]);
     a.minc[k] = min_count[k];
   }
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, counts, n_bins, n_fine, offsets,
-                     cursor, a, item_off, tot);
+  // the counts are staged in LDS when they fit beside the kernel's own 1 KB
+  int dev = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    lds_max = 0;
+    (void)hipGetLastError();
+  }
+  if ((int64_t)n_bins * 4 + 1024 <= (int64_t)lds_max)
+    hipLaunchKernelGGL(k_scan<true>, dim3(1), dim3(kScanThreads), n_bins * sizeof(uint32_t), s,
+                       counts, n_bins, n_fine, offsets, cursor, a, item_off, tot);
+  else
+    hipLaunchKernelGGL(k_scan<false>, dim3(1), dim3(kScanThreads), 0, s, counts, n_bins, n_fine,
+                       offsets, cursor, a, item_off, tot);
   return hipGetLastError();
 }
 
