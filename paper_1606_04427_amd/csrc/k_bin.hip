@@ -150,7 +150,13 @@ struct ScanArgs {
 // shuffles and one pass over the wave totals, and each thread writes its
 // bins' offsets.  kLds: the counts are first staged in LDS with coalesced
 // loads, so that the threads' runs (consecutive bins per thread) are read
-// from LDS rather than with strided global loads.
+// from LDS rather than with strided global loads, and each output array is
+// built in LDS and written with coalesced stores (one workgroup's strided
+// stores would otherwise keep a single CU's memory pipeline busy).  LDS
+// arrays are padded by one word per 32 so that runs of 2^k bins per thread
+// do not fall on one bank.
+__device__ __forceinline__ int scan_pad(int b) { return b + (b >> 5); }
+
 template <bool kLds>
 __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restrict__ counts,
                                                        int nb, int n_fine,
@@ -164,9 +170,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   __shared__ unsigned int s_max, s_nef, s_nec;
   __shared__ unsigned long long s_l2;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const uint32_t *const cnt = kLds ? s_cnt : counts;
+  uint32_t *const s_pre = s_cnt + scan_pad(nb) + 1;
+  auto cnt = [&](int b) { return kLds ? s_cnt[scan_pad(b)] : counts[b]; };
   if (kLds) {
-    for (int i = t; i < nb; i += kScanThreads) s_cnt[i] = counts[i];
+    for (int i = t; i < nb; i += kScanThreads) s_cnt[scan_pad(i)] = counts[i];
     __syncthreads();
   }
   if (t == 0) {
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   unsigned int mx = 0, nef = 0, nec = 0;
   unsigned long long l2 = 0;
   for (int b = b0; b < b1; ++b) {
-    const uint32_t c = cnt[b];
+    const uint32_t c = cnt(b);
     loc[0] += c;
     uint32_t ik[3];
 #pragma unroll
@@ -232,19 +239,50 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   unsigned long long run[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) run[q] = (wv ? s_w[q][wv - 1] : 0ull) + inc[q] - loc[q];
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t c = cnt[b];
-    if (b == n_fine && tot) {
-      tot->n_fine_pairs = run[0];
-      for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = run[1 + k];
+  if (kLds) {
+    // one quantity at a time: the run's exclusive prefixes into LDS, then
+    // coalesced stores of the whole array
+    for (int q = 0; q < 4; ++q) {
+      unsigned long long r = run[q];
+      for (int b = b0; b < b1; ++b) {
+        const uint32_t c = cnt(b);
+        if (b == n_fine && tot) {
+          if (q == 0)
+            tot->n_fine_pairs = r;
+          else
+            tot->n_fine_items[q - 1] = r;
+        }
+        s_pre[scan_pad(b)] = (uint32_t)r;
+        r += q == 0 ? c : items_for(c, b, n_fine, a.shift[q - 1], a.cshift[q - 1], a.minc[q - 1]);
+      }
+      __syncthreads();
+      if (q == 0) {
+        for (int i = t; i < nb; i += kScanThreads) {
+          const uint32_t v = s_pre[scan_pad(i)];
+          offsets[i] = v;
+          cursor[i] = v;
+        }
+      } else {
+        uint32_t *const out = item_off + (q - 1) * (nb + 1);
+        for (int i = t; i < nb; i += kScanThreads) out[i] = s_pre[scan_pad(i)];
+      }
+      __syncthreads();
     }
-    offsets[b] = (uint32_t)run[0];
-    cursor[b] = (uint32_t)run[0];
-    run[0] += c;
+  } else {
+    for (int b = b0; b < b1; ++b) {
+      const uint32_t c = cnt(b);
+      if (b == n_fine && tot) {
+        tot->n_fine_pairs = run[0];
+        for (int k = 0; k < 3; ++k) tot->n_fine_items[k] = run[1 + k];
+      }
+      offsets[b] = (uint32_t)run[0];
+      cursor[b] = (uint32_t)run[0];
+      run[0] += c;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      item_off[k * (nb + 1) + b] = (uint32_t)run[1 + k];
-      run[1 + k] += items_for(c, b, n_fine, a.shift[k], a.cshift[k], a.minc[k]);
+      for (int k = 0; k < 3; ++k) {
+        item_off[k * (nb + 1) + b] = (uint32_t)run[1 + k];
+        run[1 + k] += items_for(c, b, n_fine, a.shift[k], a.cshift[k], a.minc[k]);
+      }
     }
   }
   if (t == kScanThreads - 1) {
@@ -329,16 +367,18 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
     a.cshift[k] = shift_of(cchunk[k]);
     a.minc[k] = min_count[k];
   }
-  // the counts are staged in LDS when they fit beside the kernel's own 1 KB
+  // counts and one output array are staged in LDS when they fit beside the
+  // kernel's own 1 KB
   int dev = 0, lds_max = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
     lds_max = 0;
     (void)hipGetLastError();
   }
-  if ((int64_t)n_bins * 4 + 1024 <= (int64_t)lds_max)
-    hipLaunchKernelGGL(k_scan<true>, dim3(1), dim3(kScanThreads), n_bins * sizeof(uint32_t), s,
-                       counts, n_bins, n_fine, offsets, cursor, a, item_off, tot);
+  const int64_t lds = 2 * ((int64_t)n_bins + n_bins / 32 + 1) * (int64_t)sizeof(uint32_t);
+  if (lds + 1024 <= (int64_t)lds_max)
+    hipLaunchKernelGGL(k_scan<true>, dim3(1), dim3(kScanThreads), (size_t)lds, s, counts, n_bins,
+                       n_fine, offsets, cursor, a, item_off, tot);
   else
     hipLaunchKernelGGL(k_scan<false>, dim3(1), dim3(kScanThreads), 0, s, counts, n_bins, n_fine,
                        offsets, cursor, a, item_off, tot);
