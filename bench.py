@@ -694,7 +694,7 @@ def main():
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 1.0, 1.2])
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build renders on exactly one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the renderer runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

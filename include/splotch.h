@@ -39,7 +39,7 @@ typedef enum {
   SPL_ENOMEM = -2,      /* device allocation failed */
   SPL_EDEVICE = -3,     /* HIP runtime error (no device, launch failure) */
   SPL_EBUSY = -4,       /* request refused by the memory budget */
-  SPL_EUNSUPPORTED = -5 /* valid request this build does not handle */
+  SPL_EUNSUPPORTED = -5 /* valid request the library does not handle */
 } spl_status;
 
 typedef enum { SPL_F32 = 0, SPL_BF16 = 1, SPL_F16 = 2 } spl_dtype;
