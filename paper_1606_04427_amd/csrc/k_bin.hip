@@ -36,9 +36,12 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
   for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
        base += (int64_t)gridDim.x * kChunk) {
     const int64_t end = min(base + (int64_t)kChunk, n);
+    // the next span is loaded while this one is counted
+    uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
     for (int64_t kb = base; kb < end; kb += kBlock) {  // uniform trip count
       const int64_t k = kb + threadIdx.x;
-      const uint2 s = (k < end) ? span[k] : make_uint2(kInactive, kInactive);
+      const uint2 s = nxt;
+      nxt = (k + kBlock < end) ? span[k + kBlock] : make_uint2(kInactive, kInactive);
       count_span(s, k, rec, tk, bins);
     }
   }
@@ -69,9 +72,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
       // local counts of this chunk, then one global reservation per bin
       for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
       __syncthreads();
+      uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
       for (int64_t kb = base; kb < end; kb += kBlock) {
         const int64_t k = kb + threadIdx.x;
-        const uint2 s = (k < end) ? span[k] : make_uint2(kInactive, kInactive);
+        const uint2 s = nxt;
+        nxt = (k + kBlock < end) ? span[k + kBlock] : make_uint2(kInactive, kInactive);
         const bool act = s.x != kInactive;
         const SpanDec d = decode(s);
         const int ntx = d.large ? tk.nctx : tk.ntx;
@@ -92,9 +97,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
       }
       __syncthreads();
     }
+    uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
     for (int64_t kb = base; kb < end; kb += kBlock) {
       const int64_t k = kb + threadIdx.x;
-      const uint2 s = (k < end) ? span[k] : make_uint2(kInactive, kInactive);
+      const uint2 s = nxt;
+      nxt = (k + kBlock < end) ? span[k + kBlock] : make_uint2(kInactive, kInactive);
       const bool act = s.x != kInactive;
       const SpanDec d = decode(s);
       const int ntx = d.large ? tk.nctx : tk.ntx;
