@@ -713,6 +713,11 @@ static int resident_grid(K kernel, int threads, int n_cu) {
   return per_cu * n_cu;
 }
 
+int splat_views_resident(int tile, int n_cu) {
+  return tile == 32 ? resident_grid(k_splat_add_views<32>, kBlock, n_cu)
+                    : resident_grid(k_splat_add_views<16>, kBlock, n_cu);
+}
+
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
                               uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s) {

@@ -28,12 +28,14 @@ namespace {
 
 constexpr int kChunkSplat = 1024;  // list entries per splat item, fine tiles
 constexpr int kChunkLarge = 512;   // list entries per large-particle item
-// List entries per splat item in the batch path.  A batch holds the items of
-// many views, so items four times longer still keep every slot of the device
-// busy, and a dense tile is then merged from a quarter as many partial
-// results (float atomics on the image); one view alone keeps the shorter
-// items, which balance better when a single view's lists are short.
+// List entries per splat item in the batch path when the batch holds enough
+// work: items four times longer still keep every slot of the device busy,
+// and a dense tile is then merged from a quarter as many partial results
+// (float atomics on the image).  A batch with fewer long items than
+// kViewsItemsPerSlot per resident workgroup keeps the shorter items, which
+// balance better.  The scan counts the items of both lengths.
 constexpr int kChunkViews = 4096;
+constexpr int kViewsItemsPerSlot = 8;
 constexpr int kSortChunk = 4096;   // keys per in-LDS sort
 constexpr int kMergeOut = 2048;    // outputs per merge workgroup
 constexpr int kLargeTile = 64;     // px, tiles of the large-particle path
@@ -596,7 +598,8 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   uint32_t *counts = (uint32_t *)c->b_counts.p, *offsets = (uint32_t *)c->b_offsets.p;
   uint32_t *cursor = (uint32_t *)c->b_cursor.p, *itemoff = (uint32_t *)c->b_itemoff.p;
   Totals *tot = (Totals *)c->b_totals.p;
-  const int chunk[3] = {kChunkViews, 0, 0}, cchunk[3] = {kChunkLarge, 0, 0}, minc[3] = {1, 1, 1};
+  const int chunk[3] = {kChunkSplat, kChunkViews, 0}, cchunk[3] = {kChunkLarge, kChunkLarge, 0};
+  const int minc[3] = {1, 1, 1};
   // stage timers cover the whole batch (launches without a captured graph):
   // 0 projection, counts and scans of all views, 3 host gap, 4 items,
   // scatter and image clears, 7 both persistent splat launches, 8 finalise
@@ -620,6 +623,16 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   mark(tf, 3, s);
   HIPTRY(c, hipMemcpyAsync(c->h_btot, tot, sizeof(Totals) * nv, hipMemcpyDeviceToHost, s));
   HIPTRY(c, hipStreamSynchronize(s));
+  // item length: the long items when there are enough of them for every
+  // resident workgroup of the persistent splat
+  int ks = 0;
+  {
+    uint64_t long_items = 0;
+    for (int v = 0; v < nv; ++v) long_items += c->h_btot[v].n_fine_items[1];
+    const uint64_t slots = (uint64_t)splat_views_resident(tk[0].tile, c->n_cu);
+    if (long_items >= (uint64_t)kViewsItemsPerSlot * slots) ks = 1;
+  }
+  const int ichunk = ks ? kChunkViews : kChunkSplat;
   // views are split into groups whose lists fit 32-bit offsets; the groups
   // run one after another on the stream and reuse the list buffers
   std::vector<int> g0s;
@@ -629,7 +642,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     uint64_t p_run = 0, f_run = 0, c_run = 0;
     for (int v = 0; v < nv; ++v) {
       const Totals &T = c->h_btot[v];
-      const uint64_t fi = T.n_fine_items[0], ci = T.n_items[0] - T.n_fine_items[0];
+      const uint64_t fi = T.n_fine_items[ks], ci = T.n_items[ks] - T.n_fine_items[ks];
       if (T.n_pairs >= 0xffffffffull || fi > 0x7fffffffull || ci > 0x7fffffffull)
         return fail(c, SPL_EUNSUPPORTED, "view %d: lists too long (%llu entries)", v,
                     (unsigned long long)T.n_pairs);
@@ -686,11 +699,12 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       for (int v = v0; v < v1; ++v) {
         const Totals &T = c->h_btot[v];
         const int nb = tk[v].n_tiles + tk[v].n_ctiles;
-        if (T.n_items[0])
+        if (T.n_items[ks])
           HIPTRY(c, launch_build_items(counts + v * bstride, offsets + v * bstride, nb,
-                                       tk[v].n_tiles, kChunkViews, kChunkLarge, 1,
-                                       itemoff + v * 3 * bstride, itf + fb[v], q, itc + cb[v],
-                                       (uint32_t)T.n_fine_items[0], (uint32_t)(v - v0)));
+                                       tk[v].n_tiles, ichunk, kChunkLarge, 1,
+                                       itemoff + v * 3 * bstride + ks * (nb + 1), itf + fb[v], q,
+                                       itc + cb[v], (uint32_t)T.n_fine_items[ks],
+                                       (uint32_t)(v - v0)));
         HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n,
                                  tk[v], cursor + v * bstride, pairs + pb[v], nullptr, q));
         HIPTRY(c, launch_fill_f32(outs[v], 0.0f, 3 * (int64_t)tk[v].W * tk[v].H, q));
@@ -706,7 +720,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       mark(tf, 6, q);
       mark(tf, 7, q);
       HIPTRY(c, launch_splat_views(tk[0].tile, dviews, itf, ctr, ctr + 2, itc, ctr + 1, ctr + 3,
-                                   kChunkViews, kChunkLarge, c->n_cu, q));
+                                   ichunk, kChunkLarge, c->n_cu, q));
       mark(tf, 8, q);
       double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
       for (int v = v0; v < v1; ++v) {
@@ -766,7 +780,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       const double nbv = (double)(tk[v].n_tiles + tk[v].n_ctiles);
       B[0] += (double)n * in_pp + act * 32.0 + (double)n * 8.0 +
               (project_counts(tk[v]) ? 0.0 : (double)n * 8.0 + 4.0 * nbv) + 12.0 * nbv;
-      B[4] += 16.0 * (double)T.n_items[0] + (double)n * 8.0 + pairs * 4.0 + 12.0 * npx;
+      B[4] += 16.0 * (double)T.n_items[ks] + (double)n * 8.0 + pairs * 4.0 + 12.0 * npx;
       B[7] += fine * 36.0 + 24.0 * std::min(npx, (double)T.n_fine_nonempty * t2) + large * 36.0 +
               24.0 * std::min(npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);
       B[8] += 24.0 * npx;
@@ -787,7 +801,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       st[v]->n_large = (int64_t)T.n_large;
       st[v]->n_pairs = (int64_t)T.n_fine_pairs;
       st[v]->n_large_pairs = (int64_t)(T.n_pairs - T.n_fine_pairs);
-      st[v]->n_items = (int64_t)T.n_items[0];
+      st[v]->n_items = (int64_t)T.n_items[ks];
       for (int q = 0; q < 3; ++q) {
         st[v]->flux[q] = c->h_bstats[8 * v + q];
         st[v]->max[q] = c->h_bstats[8 * v + 3 + q];

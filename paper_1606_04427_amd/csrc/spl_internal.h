@@ -222,6 +222,8 @@ hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pa
                               const TileK &tk, float *img, hipStream_t s);
 // Persistent splat over the (view, tile chunk) items of many views: large
 // items first, then fine items; n_* and next_* are device counters.
+// Workgroups of the persistent additive splat the device holds at once.
+int splat_views_resident(int tile, int n_cu);
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
                               uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s);

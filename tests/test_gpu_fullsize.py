@@ -70,6 +70,29 @@ def test_additive_10M_1024(env, clustered, cut):
             assert st["n_large"] > 0  # the large-particle path took part
 
 
+def test_batch_8_poses_10M_1024(env, clustered):
+    """The benchmark's batched call (8 poses, one persistent launch, items of
+    4096 list entries since the batch holds enough of them) against the
+    single-view render of each pose, which is checked against the oracle
+    above."""
+    import torch
+
+    B, ctx, R = env
+    ps, (looks, pals) = clustered
+    poses = synth.random_poses(8, seed=2001, width=1024, height=1024)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals), looks, tile=16, large_cut=-1.0)
+    outs, sts = ctx.spl_render_batch(parts, poses, [prm] * len(poses))
+    torch.cuda.synchronize()
+    for pose, o, st in zip(poses, outs, sts):
+        single, st1 = ctx.spl_render(parts, pose, prm)
+        torch.cuda.synchronize()
+        assert st["n_pairs"] == st1["n_pairs"]
+        if st1["n_pairs"] > 4 * 4096:
+            assert st["n_items"] < st1["n_items"]  # the longer items were used
+        assert rel_l2(o.cpu().numpy(), single.cpu().numpy()) < 1e-6
+
+
 def test_sorted_10M_2048(env, clustered):
     import torch
 
