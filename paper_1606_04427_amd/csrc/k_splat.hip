@@ -453,11 +453,12 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   constexpr int MT = NQ / 16;          // lists built per group
   constexpr int NS = NQ + 15;          // piece slots
   constexpr float kLog2e = 1.4426950408889634f;
-  constexpr uint32_t kEmpty = 0x000000ffu | 0x00ff0000u;
   __shared__ float4 s_pos[kBlock];
   __shared__ float4 s_col[kBlock];
   __shared__ float s_ap[kBlock];       // a / (pi sigma^2)
-  __shared__ uint32_t s_box[kBlock];
+  // micro-tiles each staged entry's truncation disc can reach, one bit each
+  using MaskT = typename std::conditional<(NQ > 32), unsigned long long, uint32_t>::type;
+  __shared__ MaskT s_mask[kBlock];
   __shared__ __align__(4) uint8_t s_list[NQ][kBlock];
   __shared__ int s_len[NQ];
   __shared__ int s_start[NQ + 1];
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   }
   for (uint32_t base = it.y; base < it.z; base += kBlock) {
     const uint32_t k = base + tid;
-    uint32_t box = kEmpty;
+    MaskT mask = 0;
     if (k < it.z) {
       const uint32_t pid = (uint32_t)(src[k] & 0xffffffffull);
       const float4 r0 = rec[2 * (size_t)pid];
@@ -497,28 +498,37 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
         const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
         const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
         if (li0 <= li1 && lj0 <= lj1) {
-          box = pack_box(li0, li1, lj0, lj1);
           s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
           s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
           s_ap[tid] = rec2[pid].x;
+          // micro-tiles of the box whose pixel centres the disc can reach
+          // (the same test as the additive splat's)
+          const float ux = (r0.x - (float)x0) + (r0.y - 0.5f);
+          const float uy = (r0.z - (float)y0) + (r0.w - 0.5f);
+          const float rr = tk.nu * r1.x;
+          const float r2m = fmaf(rr * rr, 1.0001f, 1e-3f);
+          for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy) {
+            const float ey = fmaxf(fmaxf((float)(4 * qy) - uy, uy - (float)(4 * qy + 3)), 0.f);
+            const float ey2 = ey * ey;
+            for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
+              const float ex = fmaxf(fmaxf((float)(4 * qx) - ux, ux - (float)(4 * qx + 3)), 0.f);
+              if (fmaf(ex, ex, ey2) <= r2m) mask |= (MaskT)1 << (qy * MX + qx);
+            }
+          }
         }
       }
     }
-    s_box[tid] = box;
+    s_mask[tid] = mask;
     __syncthreads();
     // in-order list of every micro-tile, built by ballots of its group
     const int nb = (int)min((uint32_t)kBlock, it.z - base);
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       const int q = grp + 16 * m;
-      const int mx0 = (q % MX) * 4, my0 = (q / MX) * 4;
       int cnt = 0;
       for (int s0 = 0; s0 < nb; s0 += 16) {
         const int j = s0 + l;
-        const uint32_t b = s_box[j];
-        const int bi0 = (int)(b & 0xffu), bi1 = (int)((b >> 8) & 0xffu);
-        const int bj0 = (int)((b >> 16) & 0xffu), bj1 = (int)(b >> 24);
-        const bool hit = (bi0 <= mx0 + 3) & (bi1 >= mx0) & (bj0 <= my0 + 3) & (bj1 >= my0);
+        const bool hit = (s_mask[j] >> q) & 1;
         const uint32_t bits = (uint32_t)(__ballot(hit) >> (16 * gw)) & 0xffffu;
         if (hit) s_list[q][cnt + __popc(bits & ((1u << l) - 1u))] = (uint8_t)j;
         cnt += __popc(bits);

@@ -327,14 +327,16 @@ def test_render_records_matched_input(env, mode, tile, cut):
     assert e <= P1_TOL, f"rel-L2 {e:.3e}"
 
 
+@pytest.mark.parametrize("mode", [0, 2])
 @pytest.mark.parametrize("tile", [16, 32])
-def test_discs_that_just_reach_a_micro_tile(env, tile):
+def test_discs_that_just_reach_a_micro_tile(env, tile, mode):
     """Hand-made records whose truncation disc reaches a neighbouring 4 x 4
     pixel block only at one pixel centre, a hair inside the radius (plus
     twins a hair outside): the splat lists an entry on a block only if its
     disc can reach one of the block's pixel centres, so a test that is too
-    tight would lose exactly these edge pixels.  Every pixel is compared
-    with the FP64 oracle on the same records."""
+    tight would lose exactly these edge pixels (additive splat and
+    depth-sorted composite).  Every pixel is compared with the FP64 oracle
+    on the same records."""
     import torch
 
     B, ctx, R = env
@@ -363,17 +365,21 @@ def test_discs_that_just_reach_a_micro_tile(env, tile):
     rec_h = np.asarray(rows, np.float32)
     assert len(rows) <= 16
     rec = torch.from_numpy(rec_h).to("cuda:0")
+    # sorted mode: a / (pi sigma^2) and a distinct depth per particle
+    rec2_h = np.asarray([[0.3, 1.0 + 0.1 * i] for i in range(len(rows))], np.float32)
+    rec2 = torch.from_numpy(rec2_h).to("cuda:0") if mode == 2 else None
     pose = synth.Pose((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 40.0, 1e-3, W, H)
-    prm = B.make_params(0, B.Palettes([synth.palette(0)]),
+    prm = B.make_params(mode, B.Palettes([synth.palette(0)]),
                         [dict(log10=0, brightness=1.0, lo=0.0, hi=1.0)], tile=tile,
                         large_cut=-1.0)
-    img, _ = ctx.spl_render_records(rec, None, pose, prm)
+    img, _ = ctx.spl_render_records(rec, rec2, pose, prm)
     torch.cuda.synchronize()
     got = img.cpu().numpy().astype(np.float64)
-    ref = R.render_records(rec_h, None, W, H, 0)
-    # the weakest kept contribution (record amplitudes are premultiplied);
-    # the slack covers the fixed-point quantum of a batch (~2^-30 of the
-    # summed amplitudes), far below one lost edge contribution
+    ref = R.render_records(rec_h, rec2_h if mode == 2 else None, W, H, mode)
+    # the weakest kept contribution (record amplitudes are premultiplied;
+    # the sorted transfer takes them at a transmission close to 1); the
+    # slack covers the fixed-point quantum of a batch (~2^-30 of the summed
+    # amplitudes), far below one lost edge contribution
     edge = np.exp(-9.0) * 0.25
     assert np.abs(ref).max() > 0
     err = np.abs(got - ref)
