@@ -41,6 +41,26 @@ __device__ __forceinline__ void reg_stage(unsigned long long (&v)[E], int t, int
   }
 }
 
+// Partner key of lane ^ m for m < 32: DPP lane permutes inside quads for
+// m = 1, 2, LDS swizzles (no address operand) otherwise.
+template <int M>
+__device__ __forceinline__ unsigned long long xor_lane(unsigned long long v) {
+  const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  int a, b;
+  if constexpr (M == 1) {
+    a = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xf, 0xf, false);
+    b = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xf, 0xf, false);
+  } else if constexpr (M == 2) {
+    a = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xf, 0xf, false);
+    b = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xf, 0xf, false);
+  } else {
+    constexpr int pat = 0x1f | (M << 10);  // bit-mask mode: and 31, xor M
+    a = __builtin_amdgcn_ds_swizzle(lo, pat);
+    b = __builtin_amdgcn_ds_swizzle(hi, pat);
+  }
+  return (unsigned long long)(uint32_t)a | ((unsigned long long)(uint32_t)b << 32);
+}
+
 // Bitonic sort of one chunk of np = 256 E keys (padded with ~0): thread t
 // holds the E consecutive keys t E .. t E + E - 1 in registers.  Compare-
 // exchange partners closer than E sit in the same thread; partners up to
@@ -74,10 +94,20 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
         // depend on e
         const bool keep_min = ((t * E & j) == 0) == ((t * E & k) == 0);
         if (m < 64) {
+          auto cx = [&](auto partner) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const unsigned long long w = __shfl_xor(v[e], m);
-            v[e] = ((w < v[e]) == keep_min) ? w : v[e];
+            for (int e = 0; e < E; ++e) {
+              const unsigned long long w = partner(v[e]);
+              v[e] = ((w < v[e]) == keep_min) ? w : v[e];
+            }
+          };
+          switch (m) {
+            case 1: cx([](unsigned long long x) { return xor_lane<1>(x); }); break;
+            case 2: cx([](unsigned long long x) { return xor_lane<2>(x); }); break;
+            case 4: cx([](unsigned long long x) { return xor_lane<4>(x); }); break;
+            case 8: cx([](unsigned long long x) { return xor_lane<8>(x); }); break;
+            case 16: cx([](unsigned long long x) { return xor_lane<16>(x); }); break;
+            default: cx([](unsigned long long x) { return __shfl_xor(x, 32); }); break;
           }
         } else {
           __syncthreads();
