@@ -18,9 +18,9 @@
 //                  pixels per lane, gather only (a large particle covers most
 //                  of the pixels it is tested against).
 // k_composite<T>   sorted mode: staging as above, in-order micro-tile lists
-//                  built by ballots, one micro-tile per 16-lane group,
-//                  front-to-back slab compositing per pixel in list order;
-//                  transmittance per pixel in registers.
+//                  built by ballots, walked in near-equal ranges by the
+//                  16-lane groups; front-to-back slab compositing of each
+//                  list piece, pieces merged per pixel in list order.
 #include <type_traits>
 
 #include "spl_internal.h"
@@ -428,8 +428,8 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 // 16-lane group, and walked in lockstep as in the additive kernel.  A group
 // composites each piece of a micro-tile list it meets front to back from
 // (C, T) = (0, 1): C += T E tau phi(a tau), T *= exp(-a tau), with
-// phi(x) = (1 - e^-x)/x from its Taylor series below x = 1/2 (no
-// cancellation) and from the exponential above, and leaves the piece's
+// phi(x) = (1 - e^-x)/x from a polynomial below x = 1/2 (no cancellation)
+// and from the exponential above, and leaves the piece's
 // (C, T) in LDS.  After the walk each lane merges, for its pixels, the pieces
 // of the batch in list order into the running (C, T): C += T C_piece,
 // T *= T_piece.  The pieces of one batch fill at most NQ + 15 slots: the
@@ -586,12 +586,13 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
           const float x = s_ap[j] * e;
           float phi, em;  // phi(x), exp(-x) - 1
           if (x < 0.5f) {
-            phi = fmaf(x, -1.f / 40320.f, 1.f / 5040.f);
-            phi = fmaf(x, phi, -1.f / 720.f);
-            phi = fmaf(x, phi, 1.f / 120.f);
-            phi = fmaf(x, phi, -1.f / 24.f);
-            phi = fmaf(x, phi, 1.f / 6.f);
-            phi = fmaf(x, phi, -0.5f);
+            // degree-5 fit to phi on [0, 1/2], least squares in relative
+            // error over Chebyshev nodes: 1.4e-9 relative in exact
+            // arithmetic, 7e-8 in FP32 (as the degree-7 Taylor series)
+            phi = fmaf(x, -1.121324371e-03f, 8.186993189e-03f);
+            phi = fmaf(x, phi, -4.162891582e-02f);
+            phi = fmaf(x, phi, 1.666622162e-01f);
+            phi = fmaf(x, phi, -4.999997914e-01f);
             phi = fmaf(x, phi, 1.f);
             em = -x * phi;
           } else {
