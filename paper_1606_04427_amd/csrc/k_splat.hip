@@ -179,8 +179,11 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
       float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-      auto step = [&]() {
-        if (lp == le) {
+      // steps in blocks of four read the list at b + u (u = 0..3, an
+      // immediate offset); the end of the current list is at b + d
+      int b = lp, d = le - lp;
+      auto step = [&](const int u) {
+        if (d == u) {
           // next micro-tile: flush the running sums
           atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
           atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
@@ -189,13 +192,13 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
           do {
             ++q;
           } while (s_start[q + 1] == s_start[q]);
-          lp = q * kBlock;
-          le = lp + (s_start[q + 1] - s_start[q]);
+          b = q * kBlock - u;
+          d = u + (s_start[q + 1] - s_start[q]);
           pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
           px = (float)((q % MX) * 4 + lx);
           py = (float)((q / MX) * 4 + ly);
         }
-        const int jb = (int)(&s_list[0][0])[lp++] << kShift;  // byte offset
+        const int jb = (int)(&s_list[0][0])[b + u] << kShift;  // byte offset
         const float4 p = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_pos) + jb);
         const float4 c = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_col) + jb);
         const float dx = (px - p.x) + p.y;
@@ -208,9 +211,21 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         a1 += c.z * e;
         a2 += c.w * e;
       };
-#pragma unroll 4
-      for (int t = 0; t < steps; ++t) step();  // uniform across the workgroup
-      if (grp < rem) step();
+      int t = 0;
+      for (; t + 4 <= steps; t += 4) {  // uniform across the workgroup
+        step(0);
+        step(1);
+        step(2);
+        step(3);
+        b += 4;
+        d -= 4;
+      }
+      for (; t < steps; ++t) {
+        step(0);
+        b += 1;
+        d -= 1;
+      }
+      if (grp < rem) step(0);
       if (steps > 0 || grp < rem) {
         atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
         atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
