@@ -130,10 +130,12 @@ def box_pixels(rec, width, height, cut):
     small = sig > 0
     if cut > 0:
         small &= R <= cut
-    i0 = np.clip(np.ceil(X - R - 0.5), 0, width - 1)
-    i1 = np.clip(np.floor(X + R - 0.5), 0, width - 1)
-    j0 = np.clip(np.ceil(Y - R - 0.5), 0, height - 1)
-    j1 = np.clip(np.floor(Y + R - 0.5), 0, height - 1)
+    # clip each end on its own side only, so that a box wholly off the image
+    # stays empty
+    i0 = np.maximum(np.ceil(X - R - 0.5), 0)
+    i1 = np.minimum(np.floor(X + R - 0.5), width - 1)
+    j0 = np.maximum(np.ceil(Y - R - 0.5), 0)
+    j1 = np.minimum(np.floor(Y + R - 0.5), height - 1)
     area = np.maximum(i1 - i0 + 1, 0) * np.maximum(j1 - j0 + 1, 0)
     return float(area[small].sum()), int(small.sum())
 
