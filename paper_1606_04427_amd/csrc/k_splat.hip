@@ -70,8 +70,10 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   constexpr int MX = T / 4;            // micro-tiles per tile row
   constexpr int NQ = MX * MX;          // micro-tiles per tile (16 or 64)
   constexpr float kLog2e = 1.4426950408889634f;
-  __shared__ float4 s_pos[kBlock];     // Xi - x0, 0.5 - Xf, Yi - y0, 0.5 - Yf
-  __shared__ float4 s_col[kBlock];     // log2(e)/sigma^2, premultiplied colour
+  constexpr float kRootLog2e = 1.2011224087864498f;  // sqrt(log2 e)
+  // with g = sqrt(log2 e)/sigma: Xi - x0, (0.5 - Xf) g, Yi - y0, (0.5 - Yf) g
+  __shared__ float4 s_pos[kBlock];
+  __shared__ float4 s_col[kBlock];     // g, premultiplied colour
   // list entries: byte offsets into s_pos / s_col (16-bit, 16 px tiles) or
   // staging slots (8-bit, 32 px tiles, where the lists take 4x the LDS)
   using LT = typename std::conditional<T == 16, uint16_t, uint8_t>::type;
@@ -117,8 +119,10 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
         const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
         if (li0 <= li1 && lj0 <= lj1) {
-          s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
-          s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
+          const float g = kRootLog2e / r1.x;
+          s_pos[tid] = make_float4(r0.x - (float)x0, (0.5f - r0.y) * g, r0.z - (float)y0,
+                                   (0.5f - r0.w) * g);
+          s_col[tid] = make_float4(g, r1.y, r1.z, r1.w);
           amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
           // micro-tiles of the box whose pixel centres the truncation disc
           // can reach (tested against the micro-tile's rectangle of pixel
@@ -179,9 +183,12 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
       float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-      // steps in blocks of four read the list at b + u (u = 0..3, an
-      // immediate offset); the end of the current list is at b + d
-      int b = lp, d = le - lp;
+      // steps in blocks of four read the list at entry b + u (u = 0..3,
+      // an immediate offset from the byte offset bo of entry b); the end
+      // of the current list is at b + d
+      constexpr int kLB = (int)sizeof(LT);
+      const char *const s_lb = reinterpret_cast<const char *>(&s_list[0][0]);
+      int bo = lp * kLB, d = le - lp;
       auto step = [&](const int u) {
         if (d == u) {
           // next micro-tile: flush the running sums
@@ -192,18 +199,22 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
           do {
             ++q;
           } while (s_start[q + 1] == s_start[q]);
-          b = q * kBlock - u;
+          bo = (q * kBlock - u) * kLB;
           d = u + (s_start[q + 1] - s_start[q]);
-          pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
-          px = (float)((q % MX) * 4 + lx);
-          py = (float)((q / MX) * 4 + ly);
+          const int qx = (int)((unsigned)q % MX), qy = (int)((unsigned)q / MX);
+          pix = qy * 4 * T + qx * 4 + ly * T + lx;
+          px = (float)(qx * 4 + lx);
+          py = (float)(qy * 4 + ly);
         }
-        const int jb = (int)(&s_list[0][0])[b + u] << kShift;  // byte offset
+        // byte offset of the entry's staging slot
+        const int jb = (int)*reinterpret_cast<const LT *>(s_lb + bo + u * kLB) << kShift;
         const float4 p = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_pos) + jb);
         const float4 c = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_col) + jb);
-        const float dx = (px - p.x) + p.y;
-        const float dy = (py - p.z) + p.w;
-        const float qq = (dx * dx + dy * dy) * c.x;
+        // distances in units of sigma / sqrt(log2 e): the integer
+        // difference is exact, the FMA rounds once
+        const float dx = fmaf(px - p.x, c.x, p.y);
+        const float dy = fmaf(py - p.z, c.x, p.w);
+        const float qq = fmaf(dx, dx, dy * dy);
         // qq <= qmax keeps the result far above the denormal range, so
         // the hardware exponential needs no range fix-up
         const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
@@ -217,12 +228,12 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         step(1);
         step(2);
         step(3);
-        b += 4;
+        bo += 4 * kLB;
         d -= 4;
       }
       for (; t < steps; ++t) {
         step(0);
-        b += 1;
+        bo += kLB;
         d -= 1;
       }
       if (grp < rem) step(0);
@@ -437,7 +448,8 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
   }
 }
 
-// Sorted mode.  Staging as in splat_add_item; each micro-tile's list is built
+// Sorted mode.  Staging as in splat_add_item (with log2(e)/sigma^2 in place
+// of its pre-scaled distances); each micro-tile's list is built
 // by ballots in the depth order of the tile list.  The lists, laid end to
 // end, are cut into 16 ranges whose lengths differ by at most one, one per
 // 16-lane group, and walked in lockstep as in the additive kernel.  A group
@@ -593,6 +605,8 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
         const int j = (&s_list[0][0])[lp++];
         const float4 p = s_pos[j];
         const float4 c = s_col[j];
+        // the form with pre-scaled distances (as in the additive splat)
+        // takes one register more here, which costs a wave per SIMD
         const float dx = (px - p.x) + p.y;
         const float dy = (py - p.z) + p.w;
         const float qq = (dx * dx + dy * dy) * c.x;
