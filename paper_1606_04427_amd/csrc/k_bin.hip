@@ -10,8 +10,9 @@
 //  k_scan     single-workgroup exclusive scan of the bin counts, plus the
 //             work-item counts of up to three chunkings of the lists.
 //  k_items    expands the item counts into (bin, begin, end, chunk) items.
-//  k_scatter  per-chunk LDS histogram again, one global atomic per non-zero
-//             bin reserves a contiguous range, LDS atomics hand out slots.
+//  k_scatter  LDS histogram of the workgroup's chunks again, one global
+//             atomic per non-zero bin reserves a contiguous range, LDS
+//             atomics hand out slots.
 #include "bin_device.h"
 
 namespace spl {
@@ -65,13 +66,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
   const int nb = tk.n_tiles + tk.n_ctiles;
   const bool paper = tk.bin_rule == 1;
   uint32_t *bins = kLds ? hist : cursor;
-  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
-       base += (int64_t)gridDim.x * kChunk) {
-    const int64_t end = min(base + (int64_t)kChunk, n);
-    if (kLds) {
-      // local counts of this chunk, then one global reservation per bin
-      for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
-      __syncthreads();
+  if (kLds) {
+    // local counts of all the workgroup's chunks, then one global
+    // reservation per bin (the order inside a bin is free: additive lists
+    // are summed, depth-sorted ones are sorted next)
+    for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
+         base += (int64_t)gridDim.x * kChunk) {
+      const int64_t end = min(base + (int64_t)kChunk, n);
       uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
       for (int64_t kb = base; kb < end; kb += kBlock) {
         const int64_t k = kb + threadIdx.x;
@@ -90,13 +93,28 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
         multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, 0u, tk,
                          [&](uint32_t bin, uint32_t, uint32_t) { atomicAdd(&hist[bin], 1u); });
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < nb; i += kBlock) {
-        const uint32_t v = hist[i];
-        if (v) hist[i] = atomicAdd(&cursor[i], v);
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    // eight bins per lane in flight at once: each reservation returns its
+    // base, and one at a time the lane would wait a round trip per bin
+    for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * kBlock) {
+      uint32_t v[8], r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = i0 + u * kBlock;
+        v[u] = i < nb ? hist[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r[u] = v[u] ? atomicAdd(&cursor[i0 + u * kBlock], v[u]) : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (v[u]) hist[i0 + u * kBlock] = r[u];
+    }
+    __syncthreads();
+  }
+  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
+       base += (int64_t)gridDim.x * kChunk) {
+    const int64_t end = min(base + (int64_t)kChunk, n);
     uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
     for (int64_t kb = base; kb < end; kb += kBlock) {
       const int64_t k = kb + threadIdx.x;
@@ -133,7 +151,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
                            pairs[slot] = pk;
                        });
     }
-    if (kLds) __syncthreads();
   }
 }
 
