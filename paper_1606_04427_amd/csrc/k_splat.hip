@@ -9,8 +9,8 @@
 // k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of list
 //                  entries is staged in LDS and appended to the lists of the
 //                  4 x 4 micro-tiles it meets; the lists, laid end to end, are
-//                  cut into 16 near-equal ranges for the 16-lane groups (one
-//                  pixel per lane), with running sums in registers flushed into a
+//                  cut into 32 near-equal ranges for the 8-lane groups (two
+//                  pixels per lane), with running sums in registers flushed into a
 //                  32-bit fixed-point LDS accumulator at micro-tile changes.
 //                  Batch sums fold into per-pixel Neumaier-compensated FP32
 //                  sums.
@@ -46,17 +46,19 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 // premultiplied colour).  The tile is split into 4 x 4 micro-tiles and each
 // staged entry appends itself to the list of every micro-tile its box meets
 // (LDS integer atomics; order inside a list is free for a sum).  The lists,
-// laid end to end, are cut into 16 ranges whose lengths differ by at most
-// one, one per 16-lane group; all groups step through their ranges together,
-// one list entry per step, so the four groups of a wave, which run in
+// laid end to end, are cut into 32 ranges whose lengths differ by at most
+// one, one per 8-lane group; all groups step through their ranges together,
+// one list entry per step, so the eight groups of a wave, which run in
 // lockstep, take the same number of steps however unevenly the entries fall
 // on the micro-tiles.  The per-step work is one compare for the end of the
 // current list, the entry's staging offset and the Gaussian; the step that
-// only the longer ranges take is peeled off the loop.  One pixel per lane;
-// the running sum stays in registers while consecutive entries belong to the
-// same micro-tile and is added into a 32-bit fixed-point LDS accumulator
-// (integer atomics: neighbouring ranges may share a micro-tile) when the
-// group moves on.  The batch scale 2^S keeps the batch's summed peak
+// only the longer ranges take is peeled off the loop.  Two pixels per lane,
+// rows r and r + 2 of one micro-tile column: the entry read from LDS and the
+// horizontal distance serve both (LDS reads, not the vector ALU alone, bound
+// the walk).  The running sums stay in registers while consecutive entries
+// belong to the same micro-tile and are added into a 32-bit fixed-point LDS
+// accumulator (integer atomics: neighbouring ranges may share a micro-tile)
+// when the group moves on.  The batch scale 2^S keeps the batch's summed peak
 // amplitude below 2^30, so no pixel sum overflows.  After each batch the
 // integer sums are folded into per-pixel Neumaier-compensated FP32 sums in
 // registers.
@@ -87,7 +89,9 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   const int tx = (int)it.x % tk.ntx, ty = (int)it.x / tk.ntx;
   const int x0 = tx * T, y0 = ty * T;
   const bool multi = counts[it.x] > (uint32_t)chunk;
-  const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, wave = tid >> 6;
+  // walk: 8-lane groups; lane (lx, ly) of a group takes the micro-tile
+  // pixels (lx, ly) and (lx, ly + 2)
+  const int tid = threadIdx.x, grp = tid >> 3, l = tid & 7, wave = tid >> 6;
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
 
@@ -166,11 +170,11 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
     (void)frexpf(s_amp[0] + s_amp[1] + s_amp[2] + s_amp[3], &ex);  // sum <= 2^ex
     const int S = 30 - ex;
     {
-      // the lists laid end to end are cut into 16 ranges whose lengths differ
+      // the lists laid end to end are cut into 32 ranges whose lengths differ
       // by at most one: every group takes `steps` entries, the first `rem`
       // groups one more
       const int total = s_start[NQ];
-      const int steps = total >> 4, rem = total & 15;
+      const int steps = total >> 5, rem = total & 31;
       const int r0 = grp * steps + min(grp, rem);
       // the group's micro-tile at r0: the last list starting at or before it
       int q = 0;
@@ -182,7 +186,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       int le = q * kBlock + (s_start[q + 1] - s_start[q]);
       int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
       float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
       // steps in blocks of four read the list at entry b + u (u = 0..3,
       // an immediate offset from the byte offset bo of entry b); the end
       // of the current list is at b + d
@@ -195,7 +199,11 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
           atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
           atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
           atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
+          atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(ldexpf(b0, S)));
+          atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(ldexpf(b1, S)));
+          atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(ldexpf(b2, S)));
           a0 = a1 = a2 = 0.f;
+          b0 = b1 = b2 = 0.f;
           do {
             ++q;
           } while (s_start[q + 1] == s_start[q]);
@@ -214,13 +222,20 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         // difference is exact, the FMA rounds once
         const float dx = fmaf(px - p.x, c.x, p.y);
         const float dy = fmaf(py - p.z, c.x, p.w);
-        const float qq = fmaf(dx, dx, dy * dy);
+        const float dz = fmaf((py + 2.f) - p.z, c.x, p.w);
+        const float dx2 = dx * dx;
+        const float qq = fmaf(dy, dy, dx2);
+        const float qz = fmaf(dz, dz, dx2);
         // qq <= qmax keeps the result far above the denormal range, so
         // the hardware exponential needs no range fix-up
         const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
+        const float f = (qz <= qmax) ? __builtin_amdgcn_exp2f(-qz) : 0.f;
         a0 += c.y * e;
         a1 += c.z * e;
         a2 += c.w * e;
+        b0 += c.y * f;
+        b1 += c.z * f;
+        b2 += c.w * f;
       };
       int t = 0;
       for (; t + 4 <= steps; t += 4) {  // uniform across the workgroup
@@ -241,6 +256,9 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
         atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
         atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
+        atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(ldexpf(b0, S)));
+        atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(ldexpf(b1, S)));
+        atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(ldexpf(b2, S)));
       }
     }
     // the other length buffer was last read before the previous batch's
@@ -452,7 +470,8 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 // of its pre-scaled distances); each micro-tile's list is built
 // by ballots in the depth order of the tile list.  The lists, laid end to
 // end, are cut into 16 ranges whose lengths differ by at most one, one per
-// 16-lane group, and walked in lockstep as in the additive kernel.  A group
+// 16-lane group (one pixel per lane), and walked in lockstep as in the
+// additive kernel.  A group
 // composites each piece of a micro-tile list it meets front to back from
 // (C, T) = (0, 1): C += T E tau phi(a tau), T *= exp(-a tau), with
 // phi(x) = (1 - e^-x)/x from a polynomial below x = 1/2 (no cancellation)
