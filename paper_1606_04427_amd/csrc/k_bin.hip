@@ -13,6 +13,8 @@
 //  k_scatter  LDS histogram of the workgroup's chunks again, one global
 //             atomic per non-zero bin reserves a contiguous range, LDS
 //             atomics hand out slots.
+#include <algorithm>
+
 #include "bin_device.h"
 
 namespace spl {
@@ -20,7 +22,20 @@ namespace spl {
 namespace {
 
 constexpr int kLdsBins = 16384;  // 64 KB of u32 bins
-constexpr int kChunk = 4096;     // particles per workgroup pass
+constexpr int kChunk = 4096;     // particles per workgroup when the grid is not sized by occupancy
+
+// The count and scatter grids hold no more workgroups than the device keeps
+// resident at once (no second, partly filled round), and each workgroup takes
+// every gridDim-th unit of kUnit particles: neighbouring indices are often
+// neighbours in space, so contiguous shares would hand whole dense clusters
+// to a few workgroups, while a unit keeps some neighbours together in each
+// tile list (the splat's batches are cheaper when their entries are close).
+// unit_block(t) is the first particle of the workgroup's t-th block of 256.
+constexpr int kUnit = 1024;
+__device__ __forceinline__ int64_t unit_block(int64_t t) {
+  constexpr int U = kUnit / kBlock;
+  return ((int64_t)blockIdx.x + (t / U) * (int64_t)gridDim.x) * kUnit + (t % U) * kBlock;
+}
 
 template <bool kLds>
 __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
@@ -34,16 +49,17 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
     for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
     __syncthreads();
   }
-  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
-       base += (int64_t)gridDim.x * kChunk) {
-    const int64_t end = min(base + (int64_t)kChunk, n);
+  {
+    int64_t t = 0, kb = unit_block(0);
     // the next span is loaded while this one is counted
-    uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
-    for (int64_t kb = base; kb < end; kb += kBlock) {  // uniform trip count
+    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    while (kb < n) {  // uniform trip count
       const int64_t k = kb + threadIdx.x;
+      const int64_t kn = unit_block(++t);
       const uint2 s = nxt;
-      nxt = (k + kBlock < end) ? span[k + kBlock] : make_uint2(kInactive, kInactive);
+      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
       count_span(s, k, rec, tk, bins);
+      kb = kn;
     }
   }
   if (kLds) {
@@ -72,14 +88,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
     // are summed, depth-sorted ones are sorted next)
     for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
     __syncthreads();
-    for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
-         base += (int64_t)gridDim.x * kChunk) {
-      const int64_t end = min(base + (int64_t)kChunk, n);
-      uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
-      for (int64_t kb = base; kb < end; kb += kBlock) {
+    {
+      int64_t t = 0, kb = unit_block(0);
+      uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+      for (; kb < n; kb = unit_block(t)) {
         const int64_t k = kb + threadIdx.x;
+        const int64_t kn = unit_block(++t);
         const uint2 s = nxt;
-        nxt = (k + kBlock < end) ? span[k + kBlock] : make_uint2(kInactive, kInactive);
+        nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
         const bool act = s.x != kInactive;
         const SpanDec d = decode(s);
         const int ntx = d.large ? tk.nctx : tk.ntx;
@@ -112,14 +128,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
     }
     __syncthreads();
   }
-  for (int64_t base = (int64_t)blockIdx.x * kChunk; base < n;
-       base += (int64_t)gridDim.x * kChunk) {
-    const int64_t end = min(base + (int64_t)kChunk, n);
-    uint2 nxt = (base + threadIdx.x < end) ? span[base + threadIdx.x] : make_uint2(kInactive, kInactive);
-    for (int64_t kb = base; kb < end; kb += kBlock) {
+  {
+    int64_t t = 0, kb = unit_block(0);
+    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    for (; kb < n; kb = unit_block(t)) {
       const int64_t k = kb + threadIdx.x;
+      const int64_t kn = unit_block(++t);
       const uint2 s = nxt;
-      nxt = (k + kBlock < end) ? span[k + kBlock] : make_uint2(kInactive, kInactive);
+      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
       const bool act = s.x != kInactive;
       const SpanDec d = decode(s);
       const int ntx = d.large ? tk.nctx : tk.ntx;
@@ -354,23 +370,38 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ c
 
 }  // namespace
 
-// Workgroups of the count and scatter passes: each one zeroes and flushes a
-// histogram of all bins, so fewer, longer-lived ones when there are many bins.
-static int64_t bin_pass_blocks(int nb) { return nb <= 6144 ? 4096 : (nb <= 12288 ? 2048 : 1024); }
+// Workgroups of the count and scatter passes: as many as the device holds at
+// once (each zeroes and flushes a histogram of all bins, and a second, partly
+// filled round would cost as much as a full one), at most one per unit of
+// kUnit particles.  Without an occupancy figure: one per 4096 particles, fewer when
+// there are many bins.
+template <typename K>
+static int64_t bin_pass_grid(K kernel, size_t sh, int64_t n, int nb) {
+  const int64_t units = (n + kUnit - 1) / kUnit;
+  int dev = 0, n_cu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, sh) == hipSuccess &&
+      n_cu > 0 && per_cu > 0)
+    return std::min(units, (int64_t)n_cu * per_cu);
+  (void)hipGetLastError();
+  const int64_t cap = nb <= 6144 ? 4096 : (nb <= 12288 ? 2048 : 1024);
+  return std::min((n + kChunk - 1) / kChunk, cap);
+}
 
 hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
                         uint32_t *counts, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
-  int64_t g = (n + kChunk - 1) / kChunk;
-  const int64_t cap = bin_pass_blocks(nb);
-  if (g > cap) g = cap;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
-  if (nb <= kLdsBins)
-    hipLaunchKernelGGL(k_count<true>, dim3((int)g), dim3(kBlock), nb * sizeof(uint32_t), s,
-                       span, r, n, tk, counts);
-  else
+  if (nb <= kLdsBins) {
+    const size_t sh = nb * sizeof(uint32_t);
+    const int64_t g = bin_pass_grid(k_count<true>, sh, n, nb);
+    hipLaunchKernelGGL(k_count<true>, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
+  } else {
+    const int64_t g = bin_pass_grid(k_count<false>, 0, n, nb);
     hipLaunchKernelGGL(k_count<false>, dim3((int)g), dim3(kBlock), 0, s, span, r, n, tk, counts);
+  }
   return hipGetLastError();
 }
 
@@ -425,27 +456,25 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
                           unsigned long long *keys, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
-  int64_t g = (n + kChunk - 1) / kChunk;
-  const int64_t cap = bin_pass_blocks(nb);
-  if (g > cap) g = cap;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   const bool lds = nb <= kLdsBins;
   const size_t sh = lds ? nb * sizeof(uint32_t) : 0;
+  auto launch = [&](auto kernel) {
+    const int64_t g = bin_pass_grid(kernel, sh, n, nb);
+    hipLaunchKernelGGL(kernel, dim3((int)g), dim3(kBlock), sh, s, span, r, r2, n, tk, cursor,
+                       pairs, keys);
+  };
   if (keys) {
     if (lds)
-      hipLaunchKernelGGL((k_scatter<true, true>), dim3((int)g), dim3(kBlock), sh, s, span, r, r2, n,
-                         tk, cursor, pairs, keys);
+      launch(k_scatter<true, true>);
     else
-      hipLaunchKernelGGL((k_scatter<false, true>), dim3((int)g), dim3(kBlock), 0, s, span, r, r2,
-                         n, tk, cursor, pairs, keys);
+      launch(k_scatter<false, true>);
   } else {
     if (lds)
-      hipLaunchKernelGGL((k_scatter<true, false>), dim3((int)g), dim3(kBlock), sh, s, span, r, r2,
-                         n, tk, cursor, pairs, keys);
+      launch(k_scatter<true, false>);
     else
-      hipLaunchKernelGGL((k_scatter<false, false>), dim3((int)g), dim3(kBlock), 0, s, span, r, r2,
-                         n, tk, cursor, pairs, keys);
+      launch(k_scatter<false, false>);
   }
   return hipGetLastError();
 }
