@@ -2,7 +2,8 @@
 times, against the FP64 oracle on the whole image: the 10M-particle
 clustered set at 1024 x 1024 (additive, tile 16, with and without the
 large-particle path) and at 2048 x 2048 (depth-sorted).  Also the largest
-image sides the ABI accepts and the particle-count limit."""
+image sides the ABI accepts, the particle-count limit, and the tile lists
+of the 10M set bit for bit."""
 import numpy as np
 import pytest
 
@@ -106,6 +107,41 @@ def test_sorted_10M_2048(env, clustered):
     L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
     ref = R.render(R.Particles(ps), pose, R.params(R.SORTED, L))
     _check(img.cpu().numpy().astype(np.float64), ref, 1e-5)
+
+
+@pytest.mark.parametrize("tile", [32, 16, 15])
+def test_binning_10M_bit_exact(env, clustered, tile):
+    """Tile lists of the 10M set at 2048 x 2048, where every count and scatter
+    workgroup takes several strided units of particles: counts and offsets
+    bit-identical to the oracle's binning of the same FP32 records, the
+    unordered lists equal as sets per tile, the depth-ordered ones equal
+    outright.  32 and 16 px tiles keep the histogram in LDS (16384 bins, the
+    most it holds, at 16 px); 15 px tiles (18769 bins) take the global-atomic
+    path."""
+    import torch
+
+    B, ctx, R = env
+    ps, (looks, pals) = clustered
+    pose = synth.random_poses(8, seed=2001, width=2048, height=2048)[0]
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(B.SPL_SORTED, B.Palettes(pals), looks, tile=16)
+    rec, rec2 = ctx.spl_project(parts, pose, prm, with_rec2=True)
+    torch.cuda.synchronize()
+    del parts
+    rec_h, rec2_h = rec.cpu().numpy(), rec2.cpu().numpy()
+    W, H = pose.width, pose.height
+    for by_depth in (False, True):
+        c, o, p = ctx.spl_bin(rec, rec2, W, H, tile, 3.0, 0, by_depth)
+        c, o, p = (c.cpu().numpy().view(np.uint32), o.cpu().numpy().view(np.uint32),
+                   p.cpu().numpy().view(np.uint32))
+        rc, ro, rp = R.bin_records(rec_h, rec2_h, W, H, tile, 3.0, 0, by_depth)
+        assert np.array_equal(c, rc) and np.array_equal(o, ro)
+        if by_depth:
+            assert np.array_equal(p, rp)
+        else:
+            # (tile, particle) keys: equal sorted key arrays mean equal sets per tile
+            t = np.repeat(np.arange(len(rc), dtype=np.uint64), rc.astype(np.int64)) << np.uint64(32)
+            assert np.array_equal(np.sort(t | p.astype(np.uint64)), np.sort(t | rp.astype(np.uint64)))
 
 
 @pytest.mark.parametrize("W,H", [(32768, 8), (8, 32768)])
