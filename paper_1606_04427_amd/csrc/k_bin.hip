@@ -236,7 +236,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
       ik[k] = items_for(c, b, n_fine, a.shift[k], a.cshift[k], a.minc[k]);
       loc[1 + k] += ik[k];
     }
-    if (ik[2]) l2 += c;
+    // item list 2 holds the merge-pass items of the lists longer than one
+    // chunk sort (min_count[2] - 1 keys): the keys each pass moves
+    if (ik[2]) l2 += (unsigned long long)c * (unsigned)merge_passes(c, (uint32_t)(a.minc[2] - 1));
     if (b < n_fine && c > mx) mx = c;
     if (c) {
       if (b < n_fine)
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
       tot->max_count = s_max;
       tot->n_fine_nonempty = s_nef;
       tot->n_coarse_nonempty = s_nec;
-      tot->n_list2_pairs = s_l2;
+      tot->n_merge_keys = s_l2;
     }
   }
 }

@@ -10,7 +10,8 @@
 //  k_merge_pass   longer lists: sorted runs of length L merged pairwise into
 //                 runs of 2L; one workgroup per 2048 outputs stages its inputs
 //                 in LDS, each lane merges 8 keys into LDS, and the outputs
-//                 leave with coalesced stores.
+//                 leave with coalesced stores.  A list that is whole skips
+//                 the remaining passes (merge_passes gives its buffer).
 #include "spl_internal.h"
 
 namespace spl {
@@ -190,6 +191,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
   const Item it = items[blockIdx.x];
   const int64_t s0 = offsets[it.x];
   const int64_t n = counts[it.x];
+  // a list no longer than L is whole already and stays where it is
+  if (n <= L) return;
   const int64_t d0 = (int64_t)it.y - s0, d1 = (int64_t)it.z - s0;
   const int64_t ps = (d0 / (2 * L)) * (2 * L);
   const int64_t la = min(L, n - ps);
@@ -239,8 +242,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
 
 __global__ __launch_bounds__(kBlock) void k_copy_items(const unsigned long long *__restrict__ src,
                                                        unsigned long long *__restrict__ dst,
-                                                       const Item *__restrict__ items) {
+                                                       const Item *__restrict__ items,
+                                                       const uint32_t *__restrict__ counts,
+                                                       uint32_t k0) {
   const Item it = items[blockIdx.x];
+  if ((merge_passes(counts[it.x], k0) & 1) == 0) return;
   for (uint32_t k = it.y + threadIdx.x; k < it.z; k += kBlock) dst[k] = src[k];
 }
 
@@ -279,9 +285,10 @@ hipError_t launch_merge_pass(const unsigned long long *src, unsigned long long *
 }
 
 hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *dst,
-                             const Item *items, int n_items, hipStream_t s) {
+                             const Item *items, int n_items, const uint32_t *counts, uint32_t k0,
+                             hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_items, dim3(n_items), dim3(kBlock), 0, s, src, dst, items);
+  hipLaunchKernelGGL(k_copy_items, dim3(n_items), dim3(kBlock), 0, s, src, dst, items, counts, k0);
   return hipGetLastError();
 }
 

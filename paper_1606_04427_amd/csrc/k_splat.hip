@@ -484,8 +484,8 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ items,
                                                       const unsigned long long *__restrict__ keys,
-                                                      const unsigned long long *__restrict__ keys_long,
-                                                      uint32_t long_min,
+                                                      const unsigned long long *__restrict__ keys_b,
+                                                      uint32_t sort_chunk,
                                                       const float4 *__restrict__ rec,
                                                       const float2 *__restrict__ rec2,
                                                       const uint32_t *__restrict__ counts,
@@ -515,8 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   const int x0 = tx * T, y0 = ty * T;
   const uint32_t cnt_tile = counts[it.x];
   const bool multi = cnt_tile > (uint32_t)chunk;
-  // lists longer than long_min were merged and may live in the other buffer
-  const unsigned long long *const src = cnt_tile > long_min ? keys_long : keys;
+  // the buffer the list's merge passes left it in
+  const unsigned long long *const src = (merge_passes(cnt_tile, sort_chunk) & 1) ? keys_b : keys;
   const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
@@ -797,8 +797,8 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
 }
 
 hipError_t launch_composite(int tile, const Item *items, int n_items,
-                            const unsigned long long *keys, const unsigned long long *keys_long,
-                            uint32_t long_min, const float *rec, const float *rec2,
+                            const unsigned long long *keys, const unsigned long long *keys_b,
+                            uint32_t sort_chunk, const float *rec, const float *rec2,
                             const uint32_t *counts, int chunk, const TileK &tk, float *img,
                             float *partial, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
@@ -806,10 +806,10 @@ hipError_t launch_composite(int tile, const Item *items, int n_items,
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   float4 *pp = reinterpret_cast<float4 *>(partial);
   if (tile == 16)
-    hipLaunchKernelGGL(k_composite<16>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_long, long_min, r, r2,
+    hipLaunchKernelGGL(k_composite<16>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_b, sort_chunk, r, r2,
                        counts, chunk, tk, img, pp);
   else if (tile == 32)
-    hipLaunchKernelGGL(k_composite<32>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_long, long_min, r, r2,
+    hipLaunchKernelGGL(k_composite<32>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_b, sort_chunk, r, r2,
                        counts, chunk, tk, img, pp);
   else
     return hipErrorInvalidValue;

@@ -428,15 +428,12 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
                                   (int)L, s));
       ++passes;
     }
-    // merged lists end in B after an odd number of passes; the composite
-    // reads them there
-    unsigned long long *keys_long = passes % 2 ? keysB : keysA;
     mark(tf, 6, s);
     HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
     mark(tf, 7, s);
     const int ni = (int)T.n_items[0];
     TRY(ensure(c, c->partial, (size_t)ni * tk.tile * tk.tile * 16));
-    HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, keys_long, (uint32_t)kSortChunk, f.rec, f.rec2, counts, kChunkSplat, tk,
+    HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, keysB, (uint32_t)kSortChunk, f.rec, f.rec2, counts, kChunkSplat, tk,
                                f.out, (float *)c->partial.p, s));
     HIPTRY(c, launch_composite_merge(tk.tile, items0, ni, counts, kChunkSplat, tk,
                                      (const float *)c->partial.p, f.out, s));
@@ -460,7 +457,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     B[4] = n * 8.0 + pairs * (sorted ? 8.0 : 4.0);
     // chunk sort: every key read and written once; each merge pass: the
     // keys of the merged lists
-    B[5] = sorted ? pairs * 16.0 + (double)T.n_list2_pairs * 16.0 * passes : 0.0;
+    B[5] = sorted ? pairs * 16.0 + (double)T.n_merge_keys * 16.0 : 0.0;
     if (!sorted) {
       B[6] = 12.0 * npx + large * 36.0 +
              24.0 * std::min((double)npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);
@@ -1070,10 +1067,11 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
                                 (int)L, s));
     ++passes;
   }
-  // lists short enough for one in-LDS sort never leave A; merged lists end in
-  // B after an odd number of passes
-  if (passes % 2)
-    HIPTRY(c, launch_copy_items(B, A, (const Item *)c->items[2].p, (int)T.n_items[2], s));
+  // lists short enough for one in-LDS sort never leave A; a merged list ends
+  // in B after an odd number of its own passes and is copied back
+  if (passes > 0)
+    HIPTRY(c, launch_copy_items(B, A, (const Item *)c->items[2].p, (int)T.n_items[2], counts,
+                                (uint32_t)kSortChunk, s));
   HIPTRY(c, launch_keys_to_pids(A, (int64_t)T.n_pairs, pairs, s));
   HIPTRY(c, hipStreamSynchronize(s));
   return SPL_OK;

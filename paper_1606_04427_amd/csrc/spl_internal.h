@@ -77,7 +77,7 @@ struct Totals {
   unsigned int n_fine_nonempty;     // fine bins with at least one entry
   unsigned int n_coarse_nonempty;   // large-particle bins with at least one entry
   unsigned int pad;
-  unsigned long long n_list2_pairs; // entries of the bins counted by item list 2
+  unsigned long long n_merge_keys;  // keys moved by all merge passes (item list 2)
 };
 
 // ---------------------------------------------------------------------------
@@ -165,6 +165,18 @@ __device__ __forceinline__ uint2 record_span(const float4 r0, float sigma, const
   return sp;
 }
 
+// Merge passes a depth-sorted tile list of c keys takes after the in-LDS
+// chunk sorts of k0 keys: runs of k0, 2 k0, 4 k0, ... are merged while they
+// are shorter than the list.  Pass i reads buffer i % 2 and writes the other
+// one, and a list leaves the passes once it is whole, so it ends in buffer
+// merge_passes(c, k0) % 2 (0 = the buffer the scatter wrote).
+__host__ __device__ __forceinline__ int merge_passes(uint32_t c, uint32_t k0) {
+  int p = 0;
+  if (k0 == 0) return 0;
+  for (uint64_t L = k0; L < c; L *= 2) ++p;
+  return p;
+}
+
 // ---------------------------------------------------------------------------
 // Launch wrappers (each returns hipSuccess or the launch error).
 // ---------------------------------------------------------------------------
@@ -211,8 +223,11 @@ hipError_t launch_merge_pass(const unsigned long long *src, unsigned long long *
                              const uint32_t *counts, int run, hipStream_t s);
 hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32_t *pids,
                                hipStream_t s);
+// Copies the items of the lists whose merge passes end in the second buffer
+// (merge_passes(counts[bin], k0) odd) from src to dst.
 hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *dst,
-                             const Item *items, int n_items, hipStream_t s);
+                             const Item *items, int n_items, const uint32_t *counts, uint32_t k0,
+                             hipStream_t s);
 
 hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint32_t *pairs,
                             const float *rec, const uint32_t *counts, int chunk,
@@ -227,9 +242,11 @@ int splat_views_resident(int tile, int n_cu);
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
                               uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s);
+// keys: the buffer the scatter wrote; keys_b: the merge passes' other buffer
+// (each list is read from the one its merge passes end in, sort_chunk = k0).
 hipError_t launch_composite(int tile, const Item *items, int n_items,
-                            const unsigned long long *keys, const unsigned long long *keys_long,
-                            uint32_t long_min, const float *rec, const float *rec2, const uint32_t *counts, int chunk,
+                            const unsigned long long *keys, const unsigned long long *keys_b,
+                            uint32_t sort_chunk, const float *rec, const float *rec2, const uint32_t *counts, int chunk,
                             const TileK &tk, float *img, float *partial, hipStream_t s);
 hipError_t launch_composite_merge(int tile, const Item *items, int n_items,
                                   const uint32_t *counts, int chunk, const TileK &tk,
