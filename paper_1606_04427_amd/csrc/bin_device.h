@@ -122,6 +122,23 @@ __device__ __forceinline__ void multi_tile_pairs(bool multi, const SpanDec &d, b
 // Adds one particle's (particle, tile) pairs to the bin counts `bins` (LDS or
 // global).  Every lane of the wave must call it; lanes without a particle pass
 // an inactive span.  rec is read only for the paper's tile rule.
+template <class Add>
+__device__ __forceinline__ void count_span_with(uint2 s, int64_t k, const float4 *__restrict__ rec,
+                                                const TileK &tk, Add &&add) {
+  const bool act = s.x != kInactive;
+  const SpanDec d = decode(s);
+  const int ntx = d.large ? tk.nctx : tk.ntx;
+  const int off = d.large ? tk.n_tiles : 0;
+  const bool filt = tk.bin_rule == 1 && !d.large;
+  const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
+  const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
+  int head_of;
+  const int len = wave_runs(single, key, head_of);
+  if (len) add((uint32_t)key, (uint32_t)len);
+  multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, 0u, tk,
+                   [&](uint32_t bin, uint32_t, uint32_t) { add(bin, 1u); });
+}
+
 __device__ __forceinline__ void count_span(uint2 s, int64_t k, const float4 *__restrict__ rec,
                                            const TileK &tk, uint32_t *bins) {
   const bool act = s.x != kInactive;

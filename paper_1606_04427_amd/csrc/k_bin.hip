@@ -71,6 +71,41 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
   }
 }
 
+// The same count with two 16-bit bins per LDS word, so that twice as many
+// bins fit (and a workgroup takes half the LDS).  A bin's count in one
+// workgroup never exceeds the particles it takes (a particle adds at most one
+// to a bin), and the grid gives no workgroup more than kPackedUnits units, so
+// no half carries into the other.
+constexpr int kPackedUnits = 63;  // 63 x 1024 particles < 2^16
+__global__ __launch_bounds__(kBlock) void k_count_packed(const uint2 *__restrict__ span,
+                                                         const float4 *__restrict__ rec, int64_t n,
+                                                         TileK tk, uint32_t *__restrict__ counts) {
+  extern __shared__ uint32_t hist[];
+  const int nb = tk.n_tiles + tk.n_ctiles;
+  const int nw = (nb + 1) / 2;
+  for (int i = threadIdx.x; i < nw; i += kBlock) hist[i] = 0;
+  __syncthreads();
+  auto add = [&](uint32_t bin, uint32_t v) { atomicAdd(&hist[bin >> 1], v << ((bin & 1u) * 16u)); };
+  {
+    int64_t t = 0, kb = unit_block(0);
+    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    while (kb < n) {  // uniform trip count
+      const int64_t k = kb + threadIdx.x;
+      const int64_t kn = unit_block(++t);
+      const uint2 s = nxt;
+      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      count_span_with(s, k, rec, tk, add);
+      kb = kn;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nw; i += kBlock) {
+    const uint32_t v = hist[i];
+    if (v & 0xffffu) atomicAdd(&counts[2 * i], v & 0xffffu);
+    if (v >> 16) atomicAdd(&counts[2 * i + 1], v >> 16);
+  }
+}
+
 template <bool kLds, bool kKeys>
 __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ span,
                                                     const float4 *__restrict__ rec,
@@ -396,10 +431,16 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
-  if (nb <= kLdsBins) {
+  if (nb <= kLdsBins / 2) {
     const size_t sh = nb * sizeof(uint32_t);
     const int64_t g = bin_pass_grid(k_count<true>, sh, n, nb);
     hipLaunchKernelGGL(k_count<true>, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
+  } else if (nb <= 2 * kLdsBins) {
+    const size_t sh = (size_t)((nb + 1) / 2) * sizeof(uint32_t);
+    const int64_t units = (n + kUnit - 1) / kUnit;
+    const int64_t g = std::max(bin_pass_grid(k_count_packed, sh, n, nb),
+                               (units + kPackedUnits - 1) / kPackedUnits);
+    hipLaunchKernelGGL(k_count_packed, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
   } else {
     const int64_t g = bin_pass_grid(k_count<false>, 0, n, nb);
     hipLaunchKernelGGL(k_count<false>, dim3((int)g), dim3(kBlock), 0, s, span, r, n, tk, counts);
