@@ -31,10 +31,12 @@ constexpr int kChunk = 4096;     // particles per workgroup when the grid is not
 // to a few workgroups, while a unit keeps some neighbours together in each
 // tile list (the splat's batches are cheaper when their entries are close).
 // unit_block(t) is the first particle of the workgroup's t-th block of 256.
+// (NT-lane workgroups take blocks of NT particles.)
 constexpr int kUnit = 1024;
+template <int NT = kBlock>
 __device__ __forceinline__ int64_t unit_block(int64_t t) {
-  constexpr int U = kUnit / kBlock;
-  return ((int64_t)blockIdx.x + (t / U) * (int64_t)gridDim.x) * kUnit + (t % U) * kBlock;
+  constexpr int U = kUnit / NT;
+  return ((int64_t)blockIdx.x + (t / U) * (int64_t)gridDim.x) * kUnit + (t % U) * NT;
 }
 
 template <bool kLds>
@@ -77,21 +79,22 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
 // to a bin), and the grid gives no workgroup more than kPackedUnits units, so
 // no half carries into the other.
 constexpr int kPackedUnits = 63;  // 63 x 1024 particles < 2^16
-__global__ __launch_bounds__(kBlock) void k_count_packed(const uint2 *__restrict__ span,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_count_packed(const uint2 *__restrict__ span,
                                                          const float4 *__restrict__ rec, int64_t n,
                                                          TileK tk, uint32_t *__restrict__ counts) {
   extern __shared__ uint32_t hist[];
   const int nb = tk.n_tiles + tk.n_ctiles;
   const int nw = (nb + 1) / 2;
-  for (int i = threadIdx.x; i < nw; i += kBlock) hist[i] = 0;
+  for (int i = threadIdx.x; i < nw; i += NT) hist[i] = 0;
   __syncthreads();
   auto add = [&](uint32_t bin, uint32_t v) { atomicAdd(&hist[bin >> 1], v << ((bin & 1u) * 16u)); };
   {
-    int64_t t = 0, kb = unit_block(0);
+    int64_t t = 0, kb = unit_block<NT>(0);
     uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
     while (kb < n) {  // uniform trip count
       const int64_t k = kb + threadIdx.x;
-      const int64_t kn = unit_block(++t);
+      const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
       nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
       count_span_with(s, k, rec, tk, add);
@@ -99,15 +102,15 @@ __global__ __launch_bounds__(kBlock) void k_count_packed(const uint2 *__restrict
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nw; i += kBlock) {
+  for (int i = threadIdx.x; i < nw; i += NT) {
     const uint32_t v = hist[i];
     if (v & 0xffffu) atomicAdd(&counts[2 * i], v & 0xffffu);
     if (v >> 16) atomicAdd(&counts[2 * i + 1], v >> 16);
   }
 }
 
-template <bool kLds, bool kKeys>
-__global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ span,
+template <bool kLds, bool kKeys, int NT>
+__global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
                                                     const float4 *__restrict__ rec,
                                                     const float2 *__restrict__ rec2, int64_t n,
                                                     TileK tk, uint32_t *__restrict__ cursor,
@@ -121,14 +124,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
     // local counts of all the workgroup's chunks, then one global
     // reservation per bin (the order inside a bin is free: additive lists
     // are summed, depth-sorted ones are sorted next)
-    for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
+    for (int i = threadIdx.x; i < nb; i += NT) hist[i] = 0;
     __syncthreads();
     {
-      int64_t t = 0, kb = unit_block(0);
+      int64_t t = 0, kb = unit_block<NT>(0);
       uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
-      for (; kb < n; kb = unit_block(t)) {
+      for (; kb < n; kb = unit_block<NT>(t)) {
         const int64_t k = kb + threadIdx.x;
-        const int64_t kn = unit_block(++t);
+        const int64_t kn = unit_block<NT>(++t);
         const uint2 s = nxt;
         nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
         const bool act = s.x != kInactive;
@@ -148,27 +151,27 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const uint2 *__restrict__ sp
     __syncthreads();
     // eight bins per lane in flight at once: each reservation returns its
     // base, and one at a time the lane would wait a round trip per bin
-    for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * kBlock) {
+    for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * NT) {
       uint32_t v[8], r[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u * kBlock;
+        const int i = i0 + u * NT;
         v[u] = i < nb ? hist[i] : 0u;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r[u] = v[u] ? atomicAdd(&cursor[i0 + u * kBlock], v[u]) : 0u;
+      for (int u = 0; u < 8; ++u) r[u] = v[u] ? atomicAdd(&cursor[i0 + u * NT], v[u]) : 0u;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (v[u]) hist[i0 + u * kBlock] = r[u];
+        if (v[u]) hist[i0 + u * NT] = r[u];
     }
     __syncthreads();
   }
   {
-    int64_t t = 0, kb = unit_block(0);
+    int64_t t = 0, kb = unit_block<NT>(0);
     uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
-    for (; kb < n; kb = unit_block(t)) {
+    for (; kb < n; kb = unit_block<NT>(t)) {
       const int64_t k = kb + threadIdx.x;
-      const int64_t kn = unit_block(++t);
+      const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
       nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
       const bool act = s.x != kInactive;
@@ -413,12 +416,12 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ c
 // kUnit particles.  Without an occupancy figure: one per 4096 particles, fewer when
 // there are many bins.
 template <typename K>
-static int64_t bin_pass_grid(K kernel, size_t sh, int64_t n, int nb) {
+static int64_t bin_pass_grid(K kernel, size_t sh, int64_t n, int nb, int nt = kBlock) {
   const int64_t units = (n + kUnit - 1) / kUnit;
   int dev = 0, n_cu = 0, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, sh) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, sh) == hipSuccess &&
       n_cu > 0 && per_cu > 0)
     return std::min(units, (int64_t)n_cu * per_cu);
   (void)hipGetLastError();
@@ -438,9 +441,11 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
   } else if (nb <= 2 * kLdsBins) {
     const size_t sh = (size_t)((nb + 1) / 2) * sizeof(uint32_t);
     const int64_t units = (n + kUnit - 1) / kUnit;
-    const int64_t g = std::max(bin_pass_grid(k_count_packed, sh, n, nb),
+    // 512 lanes per workgroup, as in the scatter with a large histogram
+    const int64_t g = std::max(bin_pass_grid(k_count_packed<2 * kBlock>, sh, n, nb, 2 * kBlock),
                                (units + kPackedUnits - 1) / kPackedUnits);
-    hipLaunchKernelGGL(k_count_packed, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
+    hipLaunchKernelGGL(k_count_packed<2 * kBlock>, dim3((int)g), dim3(2 * kBlock), sh, s, span, r,
+                       n, tk, counts);
   } else {
     const int64_t g = bin_pass_grid(k_count<false>, 0, n, nb);
     hipLaunchKernelGGL(k_count<false>, dim3((int)g), dim3(kBlock), 0, s, span, r, n, tk, counts);
@@ -503,21 +508,28 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   const bool lds = nb <= kLdsBins;
   const size_t sh = lds ? nb * sizeof(uint32_t) : 0;
-  auto launch = [&](auto kernel) {
-    const int64_t g = bin_pass_grid(kernel, sh, n, nb);
-    hipLaunchKernelGGL(kernel, dim3((int)g), dim3(kBlock), sh, s, span, r, r2, n, tk, cursor,
-                       pairs, keys);
+  auto launch = [&](auto kernel, int nt) {
+    const int64_t g = bin_pass_grid(kernel, sh, n, nb, nt);
+    hipLaunchKernelGGL(kernel, dim3((int)g), dim3(nt), sh, s, span, r, r2, n, tk, cursor, pairs,
+                       keys);
   };
+  // a histogram above 32 KB leaves few workgroups per CU: 512 lanes each
+  // keep more waves resident
+  const bool wide = lds && nb > kLdsBins / 2;
   if (keys) {
-    if (lds)
-      launch(k_scatter<true, true>);
+    if (wide)
+      launch(k_scatter<true, true, 2 * kBlock>, 2 * kBlock);
+    else if (lds)
+      launch(k_scatter<true, true, kBlock>, kBlock);
     else
-      launch(k_scatter<false, true>);
+      launch(k_scatter<false, true, kBlock>, kBlock);
   } else {
-    if (lds)
-      launch(k_scatter<true, false>);
+    if (wide)
+      launch(k_scatter<true, false, 2 * kBlock>, 2 * kBlock);
+    else if (lds)
+      launch(k_scatter<true, false, kBlock>, kBlock);
     else
-      launch(k_scatter<false, false>);
+      launch(k_scatter<false, false, kBlock>, kBlock);
   }
   return hipGetLastError();
 }
