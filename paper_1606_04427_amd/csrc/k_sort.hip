@@ -5,8 +5,8 @@
 // ascending (depth, index) and every key is unique.
 //
 //  k_sort_chunks  one workgroup per list chunk of <= 4096 keys: bitonic sort
-//                 with up to 16 keys per lane in registers.  A list that fits
-//                 one chunk is done.
+//                 with up to 8 keys per lane of 512 in registers.  A list
+//                 that fits one chunk is done.
 //  k_merge_pass   longer lists: sorted runs of length L merged pairwise into
 //                 runs of 2L; one workgroup per 2048 outputs stages its inputs
 //                 in LDS, each lane merges 8 keys into LDS, and the outputs
@@ -62,18 +62,18 @@ __device__ __forceinline__ unsigned long long xor_lane(unsigned long long v) {
   return (unsigned long long)(uint32_t)a | ((unsigned long long)(uint32_t)b << 32);
 }
 
-// Bitonic sort of one chunk of np = 256 E keys (padded with ~0): thread t
+// Bitonic sort of one chunk of np = NT E keys (padded with ~0): thread t
 // holds the E consecutive keys t E .. t E + E - 1 in registers.  Compare-
 // exchange partners closer than E sit in the same thread; partners up to
 // 64 E away sit in the same wave and are read with a lane shuffle; farther
 // ones go through LDS.  Loads and stores pass through LDS so that global
 // accesses stay coalesced.
-template <int E>
+template <int E, int NT>
 __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys, uint32_t b0,
                                            int n, unsigned long long *s) {
-  constexpr int NP = kBlock * E;
+  constexpr int NP = NT * E;
   const int t = threadIdx.x;
-  for (int p = t; p < NP; p += kBlock) s[padded(p)] = (p < n) ? keys[b0 + p] : ~0ull;
+  for (int p = t; p < NP; p += NT) s[padded(p)] = (p < n) ? keys[b0 + p] : ~0ull;
   __syncthreads();
   unsigned long long v[E];
 #pragma unroll
@@ -128,24 +128,28 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
 #pragma unroll
   for (int e = 0; e < E; ++e) s[padded(t * E + e)] = v[e];
   __syncthreads();
-  for (int p = t; p < n; p += kBlock) keys[b0 + p] = s[padded(p)];
+  for (int p = t; p < n; p += NT) keys[b0 + p] = s[padded(p)];
 }
 
-__global__ __launch_bounds__(kBlock) void k_sort_chunks(unsigned long long *__restrict__ keys,
-                                                        const Item *__restrict__ items) {
+// 512 lanes per workgroup, up to 8 keys each: the 34 KB of LDS allow four
+// workgroups per CU, and 512-lane ones bring twice the waves of 256-lane
+// ones (at the price of one more stage through LDS per merge level).
+constexpr int kSortThreads = 512;
+__global__ __launch_bounds__(kSortThreads) void k_sort_chunks(unsigned long long *__restrict__ keys,
+                                                              const Item *__restrict__ items) {
+  constexpr int NT = kSortThreads;
+  static_assert(NT * 8 == kSortChunk, "a chunk is 8 keys per lane");
   __shared__ unsigned long long s[kSortChunk + kSortChunk / 16];
   const Item it = items[blockIdx.x];
   const int n = (int)(it.z - it.y);
-  if (n <= kBlock)
-    sort_chunk<1>(keys, it.y, n, s);
-  else if (n <= 2 * kBlock)
-    sort_chunk<2>(keys, it.y, n, s);
-  else if (n <= 4 * kBlock)
-    sort_chunk<4>(keys, it.y, n, s);
-  else if (n <= 8 * kBlock)
-    sort_chunk<8>(keys, it.y, n, s);
+  if (n <= NT)
+    sort_chunk<1, NT>(keys, it.y, n, s);
+  else if (n <= 2 * NT)
+    sort_chunk<2, NT>(keys, it.y, n, s);
+  else if (n <= 4 * NT)
+    sort_chunk<4, NT>(keys, it.y, n, s);
   else
-    sort_chunk<16>(keys, it.y, n, s);
+    sort_chunk<8, NT>(keys, it.y, n, s);
 }
 
 // First i in [lo, hi) with A[i] >= B[diag - 1 - i] (hi if none): the start
@@ -271,7 +275,7 @@ hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32
 hipError_t launch_sort_chunks(unsigned long long *keys, const Item *items, int n_items,
                               hipStream_t s) {
   if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort_chunks, dim3(n_items), dim3(kBlock), 0, s, keys, items);
+  hipLaunchKernelGGL(k_sort_chunks, dim3(n_items), dim3(kSortThreads), 0, s, keys, items);
   return hipGetLastError();
 }
 
