@@ -174,3 +174,17 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_record_carries_the_contract_fields():
+    args = types.SimpleNamespace(steps=10, warmup=3)
+    cfg = {"workload": "10M particles, 1024x1024, 8 poses", "n_particles": 10_000_000}
+    r = bench.base_record(args, 1.5e10, 5.4, "f32", cfg)
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config"):
+        assert k in r, k
+    assert r["n_gpus"] == 1 and r["steps"] == 10 and r["warmup"] == 3
+    assert r["higher_is_better"] is True and r["scaling"] == "weak"
+    assert r["vs_baseline"] is None and r["data"] == "synthetic"
+    assert r["config"]["workload"] == cfg["workload"]
+    json.dumps(r)  # one JSON line
