@@ -200,6 +200,52 @@ def random_poses(count: int, seed: int = 2001, width: int = 1024, height: int = 
     return out
 
 
+def _look_at_centre(eye, width, height, fov_y_deg, z_near, up_hint=(0.0, 0.0, 1.0)) -> Pose:
+    c = np.array([0.5, 0.5, 0.5])
+    fwd = c - np.asarray(eye, dtype=np.float64)
+    fwd /= np.linalg.norm(fwd)
+    u = np.asarray(up_hint, dtype=np.float64)
+    u = u - fwd * np.dot(u, fwd)
+    if np.linalg.norm(u) < 1e-9:
+        u = np.array([0.0, 1.0, 0.0]) - fwd * fwd[1]
+    u /= np.linalg.norm(u)
+    return Pose(tuple(map(float, eye)), tuple(map(float, c)), tuple(map(float, u)), fov_y_deg,
+                z_near, width, height)
+
+
+def orbit_poses(count: int = 100, radius: float = 1.6, elevation_deg: float = 20.0,
+                width: int = 1024, height: int = 1024, fov_y_deg: float = 50.0,
+                z_near: float = 0.05) -> list[Pose]:
+    """An animation orbit: count frames evenly spaced in azimuth on a circle
+    of the given radius around the cube centre, raised by elevation_deg,
+    each looking at the centre with z up."""
+    c = np.array([0.5, 0.5, 0.5])
+    el = math.radians(elevation_deg)
+    out = []
+    for k in range(count):
+        az = 2.0 * math.pi * k / count
+        d = np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+        out.append(_look_at_centre(c + radius * d, width, height, fov_y_deg, z_near))
+    return out
+
+
+def sweep_poses(count: int = 6, far: float = 3.0, near: float = 0.6, width: int = 1024,
+                height: int = 1024, fov_y_deg: float = 50.0, z_near: float = 0.05,
+                direction=(0.6, -0.48, 0.64)) -> list[Pose]:
+    """Camera positions from far to near along one direction from the cube
+    centre, distances log-spaced, each looking at the centre: projected radii
+    grow from pose to pose."""
+    c = np.array([0.5, 0.5, 0.5])
+    d = np.asarray(direction, dtype=np.float64)
+    d /= np.linalg.norm(d)
+    out = []
+    for k in range(count):
+        f = k / max(count - 1, 1)
+        dist = math.exp(math.log(far) + f * (math.log(near) - math.log(far)))
+        out.append(_look_at_centre(c + dist * d, width, height, fov_y_deg, z_near))
+    return out
+
+
 def poisson_arrivals(count: int, rate_per_s: float, seed: int = 3001) -> np.ndarray:
     """Arrival times (s) of a Poisson request stream."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -1,0 +1,47 @@
+"""Seeded camera paths of the animation workload: an orbit at constant
+distance with evenly spaced azimuths, and a far-to-near sweep."""
+import math
+
+import numpy as np
+
+from paper_1606_04427_amd import synth
+
+C = np.array([0.5, 0.5, 0.5])
+
+
+def _check_pose(p):
+    eye, look, up = map(np.asarray, (p.eye, p.lookat, p.up))
+    fwd = look - eye
+    assert np.allclose(look, C)
+    assert abs(np.linalg.norm(up) - 1.0) < 1e-12
+    assert abs(np.dot(up, fwd)) < 1e-9 * np.linalg.norm(fwd)
+
+
+def test_orbit_is_a_circle_around_the_centre():
+    poses = synth.orbit_poses(100, radius=1.6, elevation_deg=20.0)
+    assert len(poses) == 100
+    eyes = np.array([p.eye for p in poses]) - C
+    assert np.allclose(np.linalg.norm(eyes, axis=1), 1.6)
+    assert np.allclose(eyes[:, 2], 1.6 * math.sin(math.radians(20.0)))
+    az = np.unwrap(np.arctan2(eyes[:, 1], eyes[:, 0]))
+    assert np.allclose(np.diff(az), 2 * math.pi / 100)
+    for p in poses:
+        _check_pose(p)
+        assert (p.width, p.height) == (1024, 1024)
+
+
+def test_sweep_goes_from_far_to_near():
+    poses = synth.sweep_poses(6, far=3.0, near=0.6)
+    d = np.array([np.linalg.norm(np.asarray(p.eye) - C) for p in poses])
+    assert abs(d[0] - 3.0) < 1e-12 and abs(d[-1] - 0.6) < 1e-12
+    assert np.all(np.diff(d) < 0)
+    assert np.allclose(np.diff(np.log(d)), np.log(0.6 / 3.0) / 5)
+    dirs = (np.array([p.eye for p in poses]) - C) / d[:, None]
+    assert np.allclose(dirs, dirs[0])
+    for p in poses:
+        _check_pose(p)
+
+
+def test_camera_straight_above_the_centre_gets_a_valid_up():
+    p = synth.sweep_poses(2, direction=(0.0, 0.0, 1.0))[0]
+    _check_pose(p)
