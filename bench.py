@@ -467,6 +467,9 @@ def run_orbit(args, torch, B):
         "n_particles": ps.n, "image": [1024, 1024], "frames_per_step": len(orbit)})
     out.update({"ms_per_frame": 1e3 * elapsed / frames, "sweep": rows})
     ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ps, orbit[:1], looks, pals,
+                                           args.cpu_sample or 2_000_000, B.SPL_ADD_AEQE)
     return out
 
 

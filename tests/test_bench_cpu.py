@@ -188,3 +188,14 @@ def test_record_carries_the_contract_fields():
     assert r["vs_baseline"] is None and r["data"] == "synthetic"
     assert r["config"]["workload"] == cfg["workload"]
     json.dumps(r)  # one JSON line
+
+
+def test_cpu_baseline_times_the_oracle_on_a_sample(oracle):
+    from paper_1606_04427_amd import synth
+
+    ps = synth.soneira_peebles(20000, seed=7)
+    poses = synth.orbit_poses(2, width=64, height=64)
+    looks, pals = bench.looks_for(ps)
+    r = bench.cpu_baseline(ps, poses, looks, pals, 5000, 1)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "particles/s"
+    assert r["value"] > 0 and "5000-particle" in r["sample"]
