@@ -199,3 +199,22 @@ def test_cpu_baseline_times_the_oracle_on_a_sample(oracle):
     r = bench.cpu_baseline(ps, poses, looks, pals, 5000, 1)
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "particles/s"
     assert r["value"] > 0 and "5000-particle" in r["sample"]
+
+
+def test_box_pixels_agrees_with_the_oracle_box_rule(oracle):
+    """The update count behind the splat's roofline uses the same pixel box
+    as the binning rule (the oracle's FP32 record box), up to rounding at
+    box edges."""
+    rng = np.random.default_rng(11)
+    W, H = 96, 80
+    rows = [(rng.uniform(-10, 106), rng.uniform(-10, 90), rng.uniform(0.3, 6.0))
+            for _ in range(400)]
+    rec = _records(rows)
+    n_px, _ = bench.box_pixels(rec, W, H, 0.0)
+    want = 0
+    for r in rec.reshape(-1, 8):
+        ok, (i0, i1, j0, j1) = oracle.record_box(r, 3.0, W, H)
+        if ok:
+            want += (i1 - i0 + 1) * (j1 - j0 + 1)
+    assert want > 0
+    assert abs(n_px - want) <= 1e-3 * want
