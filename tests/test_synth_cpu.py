@@ -45,3 +45,29 @@ def test_sweep_goes_from_far_to_near():
 def test_camera_straight_above_the_centre_gets_a_valid_up():
     p = synth.sweep_poses(2, direction=(0.0, 0.0, 1.0))[0]
     _check_pose(p)
+
+
+def test_clustered_set_follows_its_recipe():
+    """The stand-in for the paper's snapshot: seeded and repeatable, about one
+    star per ten particles, positive smoothing lengths and scalars, the
+    clustered part within the nested cluster radii, the uniform field last,
+    absorption in [0.01, 0.5]."""
+    a = synth.soneira_peebles(200_000, seed=5, absorption=True)
+    b = synth.soneira_peebles(200_000, seed=5, absorption=True)
+    assert a.n == 200_000
+    for f in ("x", "y", "z", "h", "intensity", "scalar", "species", "absorption"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    frac = float(np.mean(a.species == 1))
+    assert abs(frac - 0.10) < 0.01
+    assert np.all(a.h > 0) and np.all(a.scalar > 0) and np.all(a.intensity > 0)
+    assert np.all((a.absorption >= 0.01) & (a.absorption <= 0.5))
+    # 95% of the particles sit about the leaves: within the sum of the nested
+    # cluster radii (0.5 (1 + 1/3 + 1/9 + 1/27)) plus five leaf widths of the
+    # cube centre; the uniform field, stored last, fills the cube
+    r = np.sqrt((a.x - 0.5) ** 2 + (a.y - 0.5) ** 2 + (a.z - 0.5) ** 2)
+    bound = 0.5 * (1 + 1 / 3 + 1 / 9 + 1 / 27) + 5 * 0.5 / 81 / 2
+    assert np.mean(r[: int(0.95 * a.n) - 100] <= bound) > 0.999
+    field = a.x[-int(0.05 * a.n) + 100:]
+    assert field.min() < 0.01 and field.max() > 0.99
+    c = synth.soneira_peebles(200_000, seed=6)
+    assert not np.array_equal(a.x, c.x)
