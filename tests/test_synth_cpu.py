@@ -1,5 +1,7 @@
-"""Seeded camera paths of the animation workload: an orbit at constant
-distance with evenly spaced azimuths, and a far-to-near sweep."""
+"""The seeded input generators against their stated recipes: the camera
+paths of the animation workload (an orbit at constant distance with evenly
+spaced azimuths, a far-to-near sweep), the random poses, the clustered set
+and the blobs."""
 import math
 
 import numpy as np
@@ -71,3 +73,29 @@ def test_clustered_set_follows_its_recipe():
     assert field.min() < 0.01 and field.max() > 0.99
     c = synth.soneira_peebles(200_000, seed=6)
     assert not np.array_equal(a.x, c.x)
+
+
+def test_blobs_follow_their_recipe():
+    a = synth.blobs(50_000, seed=3)
+    b = synth.blobs(50_000, seed=3)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.h, b.h)
+    for v in (a.x, a.y, a.z):
+        assert v.min() >= 0.0 and v.max() <= 1.0
+    # smoothing length in pixels at the blob camera's depth: [0.5, 8], median 2
+    world_per_px = 2.0 * math.tan(math.radians(20.0)) / 128.0
+    px = a.h.astype(np.float64) / world_per_px
+    assert px.min() >= 0.5 - 1e-4 and px.max() <= 8.0 + 1e-4
+    assert abs(np.median(px) - 2.0) < 0.05
+    assert np.all(a.species == 0) and np.array_equal(a.intensity, a.scalar)
+
+
+def test_random_poses_follow_their_recipe():
+    poses = synth.random_poses(200, seed=9, dist_range=(0.6, 3.0))
+    d = np.array([np.linalg.norm(np.asarray(p.eye) - C) for p in poses])
+    assert d.min() >= 0.6 - 1e-9 and d.max() <= 3.0 + 1e-9
+    look = np.array([p.lookat for p in poses])
+    assert np.all(np.abs(look - C) < 0.3)
+    for p in poses:
+        fwd = np.asarray(p.lookat) - np.asarray(p.eye)
+        assert abs(np.dot(np.asarray(p.up), fwd)) < 1e-9 * np.linalg.norm(fwd)
+    assert [p.eye for p in poses] == [p.eye for p in synth.random_poses(200, seed=9)]
