@@ -39,10 +39,11 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-# FP32 operations per Gaussian pixel update: two differences, squared
-# distance (mul + fma), scale, exponential, three colour products and three
-# accumulations
-FLOPS_PER_UPDATE = 13.0
+# Operations per Gaussian pixel update (additive modes): about 11 FP32
+# operations (the offsets of the pixel centre from the particle, the squared
+# distance, the truncation test, three colour multiply-adds counted as two
+# operations each) plus one exponential, counted as one operation
+FLOPS_PER_UPDATE = 12.0
 METRIC = "particles/s + HBM GB/s per frame; p50/p99 latency on mixed-view stream"
 KERNEL_OF_STAGE = {"splat": "k_splat_add", "project": "k_project", "large_splat": "k_splat_large",
                    "scatter": "k_scatter", "count": "k_count", "finalise": "k_finalise",
@@ -138,6 +139,26 @@ def box_pixels(rec, width, height, cut):
     j1 = np.minimum(np.floor(Y + R - 0.5), height - 1)
     area = np.maximum(i1 - i0 + 1, 0) * np.maximum(j1 - j0 + 1, 0)
     return float(area[small].sum()), int(small.sum())
+
+
+def radius_range(rec, k_sigma=1.0 / 3.0, sigma_min=0.5):
+    """Realised projected radius rho (px) over the active records of a view:
+    sigma = sqrt((k_sigma rho)^2 + sigma_min^2) inverted for rho."""
+    sig = np.asarray(rec, np.float64).reshape(-1, 8)[:, 4]
+    sig = sig[sig > 0]
+    if sig.size == 0:
+        return None
+    rho = np.sqrt(np.maximum(sig * sig - sigma_min * sigma_min, 0.0)) / k_sigma
+    q = np.percentile(rho, [50, 99])
+    return {"min": float(rho.min()), "p50": float(q[0]), "p99": float(q[1]),
+            "max": float(rho.max())}
+
+
+def footprint(box_px, small):
+    """Box pixels per small particle over several views: both lists hold one
+    entry per view, so the ratio of their sums is the mean over every
+    (particle, view) pair."""
+    return float(sum(box_px)) / max(int(sum(small)), 1)
 
 
 def timed_steps(ctx, step, steps, warmup, torch):
@@ -267,14 +288,16 @@ def run_additive(args, torch, B):
     # outside the timed region: per-pose statistics and the Gaussian updates
     # the splat had to evaluate (from the device's own records)
     stats = [ctx.spl_render(parts, p, prm, out=imgs[k])[1] for k, p in enumerate(poses)]
-    updates, small, pose_updates = 0.0, 0, []
+    pose_updates, pose_small, pose_rho = [], [], []
     for k, p in enumerate(poses):
         rec, _ = ctx.spl_project(parts, p, prm)
-        u, s = box_pixels(rec.cpu().numpy(), p.width, p.height, stats[k]["large_cut"])
-        updates += u
-        small += s
+        rh = rec.cpu().numpy()
+        u, s = box_pixels(rh, p.width, p.height, stats[k]["large_cut"])
         pose_updates.append(u)
-        del rec
+        pose_small.append(s)
+        pose_rho.append(radius_range(rh))
+        del rec, rh
+    updates = float(sum(pose_updates))
     # one persistent splat launch per step covers all poses
     roofline = roofline_for(B, ms, by, args.steps, updates)
     roofline["kernel"] = "k_splat_add_views" if roofline["kernel"] == "k_splat_add" else roofline["kernel"]
@@ -300,6 +323,8 @@ def run_additive(args, torch, B):
         ctx.spl_set_timing(False)
         per_pose.append({"n_active": stats[k]["n_active"], "n_pairs": stats[k]["n_pairs"],
                          "box_px": pose_updates[k],
+                         "n_large": stats[k]["n_large"],
+                         "rho_px": pose_rho[k],
                          "box_px_per_active": pose_updates[k] / max(stats[k]["n_active"], 1),
                          "frame_ms": sum(pm) / max(pf, 1),
                          "splat_ms": pm[B.STAGES.index("splat")] / max(pf, 1)})
@@ -383,7 +408,7 @@ def run_additive(args, torch, B):
         "batched_graph_replay": graphs,
         "per_pose": per_pose,
         "bandwidth_probe": probe,
-        "mean_box_px_per_small_particle": updates * len(poses) / max(small, 1),
+        "mean_box_px_per_small_particle": footprint(pose_updates, pose_small),
         "frames": [{"n_active": s["n_active"], "n_pairs": s["n_pairs"], "n_large": s["n_large"],
                     "n_large_pairs": s["n_large_pairs"]} for s in stats],
     })

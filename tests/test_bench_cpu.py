@@ -38,12 +38,13 @@ def test_stage_names_match_the_library():
 
 
 def test_splat_dominant_is_priced_against_the_fp32_vector_peak():
-    # 8 launches, 4 ms each, 1e9 updates per launch: 13e9 flop / 4e-3 s = 3.25 TFLOP/s
+    # 8 launches, 4 ms each, 1e9 updates per launch at 12 operations each
     ms, by = _times(splat=(32.0, 8 * 2e9), project=(1.0, 8 * 1e9))
     r = bench.roofline_for(B, ms, by, 8, updates_per_launch=1e9)
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
     assert r["peak"] == 157.3
-    assert r["achieved"] == pytest.approx(13.0 * 1e9 / 4e-3 / 1e12)
+    assert bench.FLOPS_PER_UPDATE == 12.0
+    assert r["achieved"] == pytest.approx(12.0 * 1e9 / 4e-3 / 1e12)
     assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
     assert r["kernel"] == "k_splat_add"
     assert r["ms_per_launch"] == pytest.approx(4.0)
@@ -218,3 +219,36 @@ def test_box_pixels_agrees_with_the_oracle_box_rule(oracle):
             want += (i1 - i0 + 1) * (j1 - j0 + 1)
     assert want > 0
     assert abs(n_px - want) <= 1e-3 * want
+
+
+def test_footprint_is_the_mean_over_particle_view_pairs():
+    """Two views: 3 small particles with boxes of 9, 25 and 49 px in the first,
+    one of 100 px in the second; the mean is 183 / 4, whatever the number of
+    views (the sums already cover every view)."""
+    rec = np.zeros((4, 8), np.float32)
+    # X = 50.5, Y = 50.5 (integer part + fraction), sigma chosen so R = 3 sigma
+    # gives odd box widths 3, 5, 7 and 10 px
+    rec[:, 0] = 50.0
+    rec[:, 1] = 0.5
+    rec[:, 2] = 50.0
+    rec[:, 3] = 0.5
+    rec[:, 4] = [0.5, 2.0 / 3.0 + 1e-4, 1.0 + 1e-4, 5.0 / 3.0]
+    u1, s1 = bench.box_pixels(rec[:3], 100, 100, -1.0)
+    assert (u1, s1) == (9 + 25 + 49, 3)
+    rec2 = rec[3:].copy()
+    rec2[:, 1] = 0.0  # X = 50.0: centres within 5 px are 45.5 .. 54.5 -> 10 columns
+    rec2[:, 3] = 0.0
+    u2, s2 = bench.box_pixels(rec2, 100, 100, -1.0)
+    assert (u2, s2) == (100, 1)
+    assert bench.footprint([u1, u2], [s1, s2]) == pytest.approx(183.0 / 4.0)
+
+
+def test_radius_range_inverts_the_kernel_width():
+    rho = np.array([0.0, 3.0, 30.0, 300.0])
+    sig = np.sqrt((rho / 3.0) ** 2 + 0.25)
+    rec = np.zeros((5, 8), np.float32)
+    rec[:4, 4] = sig
+    r = bench.radius_range(rec)  # the inactive record (sigma = 0) is skipped
+    assert r["min"] == pytest.approx(0.0, abs=2e-3)
+    assert r["max"] == pytest.approx(300.0, rel=1e-5)
+    assert bench.radius_range(np.zeros((2, 8), np.float32)) is None
