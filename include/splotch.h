@@ -179,6 +179,27 @@ spl_status spl_render_records(spl_ctx *ctx, int64_t n, const float *rec,
 spl_status spl_render(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
                       const spl_params *prm, float *out, spl_stats *st, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the frame of
+ * spl_render, with every workspace buffer taken from a fixed device array of
+ * spl_noalloc_scratch_bytes() bytes (128 MiB) that the library holds on each
+ * device until the process ends.  The call allocates nothing: no hipMalloc,
+ * hipFree or allocating library routine; the context's own workspace is not
+ * touched.  Inputs, output and stats as spl_render; stage timers are not
+ * recorded.  Limits: a frame whose records, spans, tile lists and sort keys
+ * do not fit returns SPL_ENOMEM with the sizes in spl_last_error.  Per
+ * particle the frame needs 40 bytes (48 in sorted mode), checked before any
+ * work is enqueued (at most about 3.3M and 2.8M particles); the lists, known
+ * after the count, need 4 bytes per (particle, tile) entry (16 in sorted
+ * mode), so at 1.5 entries per particle about 2.9M and 1.8M particles fit.
+ * Every call on one device shares that device's array and finds the previous
+ * call's contents there (the frame clears what must start at zero): calls
+ * that overlap on one device, from any context, thread or stream, race and
+ * must be serialised by the caller. */
+spl_status spl_render_noalloc(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
+                              const spl_params *prm, float *out, spl_stats *st, void *stream);
+int64_t spl_noalloc_scratch_bytes(void);
+
 /* Many views of one resident particle set (the paper's scene-file frame
  * sequence, Sect. 2.1).  cams, prms, outs: host arrays of n_views entries
  * (outs[v] device images).  Projection of all views runs in one launch and

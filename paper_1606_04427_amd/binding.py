@@ -23,7 +23,7 @@ SPL_MAX_SPECIES = 8
 EXPORTS = ["spl_create", "spl_destroy", "spl_last_error", "spl_workspace_bytes",
            "spl_scalar_range", "spl_project", "spl_bin", "spl_render_records", "spl_render",
            "spl_render_batch", "spl_autotune", "spl_set_timing", "spl_get_timing",
-           "spl_set_option"]
+           "spl_set_option", "spl_render_noalloc", "spl_noalloc_scratch_bytes"]
 SPL_OPT_TIMING, SPL_OPT_GRAPHS, SPL_OPT_BATCH_BYTES, SPL_OPT_BATCH_PAIRS = 0, 1, 2, 3
 SPL_N_STAGES = 9
 STAGES = ["project", "count", "scan", "host_gap_items", "scatter", "sort", "large_splat",
@@ -105,8 +105,13 @@ def lib():
         L.spl_set_timing.argtypes = [vp, i32]
         L.spl_get_timing.argtypes = [vp, C.POINTER(d), C.POINTER(d), C.POINTER(i64)]
         L.spl_set_option.argtypes = [vp, i32, i64]
+        L.spl_render_noalloc.argtypes = [vp, C.POINTER(spl_particles), C.POINTER(spl_camera),
+                                         C.POINTER(spl_params), vp, C.POINTER(spl_stats), vp]
+        L.spl_noalloc_scratch_bytes.argtypes = []
+        L.spl_noalloc_scratch_bytes.restype = i64
         for name in EXPORTS:
-            if name not in ("spl_destroy", "spl_last_error", "spl_workspace_bytes"):
+            if name not in ("spl_destroy", "spl_last_error", "spl_workspace_bytes",
+                            "spl_noalloc_scratch_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -306,6 +311,19 @@ class Context:
         cam = make_camera(pose)
         self._check(self.L.spl_render(self.h, C.byref(parts.st), C.byref(cam), C.byref(prm),
                                       _ptr(out), C.byref(st) if stats else None, _stream()))
+        return out, (st.as_dict() if stats else None)
+
+    def spl_render_noalloc(self, parts: DeviceParticles, pose, prm: spl_params, out=None,
+                           stats=True):
+        import torch
+
+        if out is None:
+            out = torch.empty((pose.height, pose.width, 3), dtype=torch.float32, device=parts.device)
+        st = spl_stats()
+        cam = make_camera(pose)
+        self._check(self.L.spl_render_noalloc(self.h, C.byref(parts.st), C.byref(cam),
+                                              C.byref(prm), _ptr(out),
+                                              C.byref(st) if stats else None, _stream()))
         return out, (st.as_dict() if stats else None)
 
     def spl_render_batch(self, parts: DeviceParticles, poses, prms, outs=None, stats=True):

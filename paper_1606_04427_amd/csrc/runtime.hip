@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -23,6 +24,12 @@
 #include "spl_internal.h"
 
 using namespace spl;
+
+// Workspace of spl_render_noalloc: one copy per device, held until the
+// process ends.  Host code never passes this name to a kernel; it uses the
+// device address that spl_create looks up for each device.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -47,6 +54,17 @@ struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
 };
+
+// A fixed region that ensure() carves buffers from instead of allocating.
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};  // device address of `scratch`, per device
 
 // Events of one timed frame: ev[k] .. ev[k+1] brackets stage k.
 struct TimedFrame {
@@ -87,6 +105,8 @@ struct spl_ctx {
   int64_t budget = (int64_t)48 << 30;
   uint64_t group_pairs = 0xfffffffeull;  // list entries per persistent launch
   int n_cu = 256;
+  void *scratch = nullptr;  // this device's copy of `scratch`
+  Arena *arena = nullptr;   // set while spl_render_noalloc runs
 };
 
 namespace {
@@ -114,6 +134,19 @@ spl_status fail(spl_ctx *c, spl_status code, const char *fmt, ...) {
 spl_status ensure(spl_ctx *c, DevBuf &b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.cap >= bytes) return SPL_OK;
+  if (c->arena) {
+    Arena &a = *c->arena;
+    const size_t off = (a.used + 255) & ~(size_t)255;
+    if (off > a.cap || bytes > a.cap - off)
+      return fail(c, SPL_ENOMEM,
+                  "the %zu-byte scratch cannot hold this frame: %zu more bytes needed with %zu "
+                  "in use",
+                  a.cap, bytes, off);
+    b.p = a.base + off;
+    b.cap = bytes;
+    a.used = off + bytes;
+    return SPL_OK;
+  }
   size_t want = b.cap + b.cap / 2;
   if (want < bytes) want = bytes;
   want = (want + 255) & ~(size_t)255;
@@ -899,9 +932,27 @@ spl_status spl_create(int device, spl_ctx **out) {
   }
   if (device < 0 || device >= nd) return SPL_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return SPL_EDEVICE;
+  // the device address of this device's `scratch` (once per device, with
+  // the device current)
+  void *scratch_ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < kMaxDevices && g_scratch[device]) {
+      scratch_ptr = g_scratch[device];
+    } else {
+      const hipError_t e = hipGetSymbolAddress(&scratch_ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !scratch_ptr) {
+        (void)hipGetLastError();
+        return SPL_EDEVICE;
+      }
+      if (device < kMaxDevices) g_scratch[device] = scratch_ptr;
+    }
+  }
   spl_ctx *c = new (std::nothrow) spl_ctx();
   if (!c) return SPL_ENOMEM;
   c->device = device;
+  c->scratch = scratch_ptr;
+  c->err.reserve(512);  // error messages then need no allocation
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->n_cu = ncu;
@@ -1135,6 +1186,51 @@ spl_status spl_render(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
   HIPTRY(c, hipSetDevice(c->device));
   return render_one(c, p, cam, prm, out, st, (hipStream_t)stream);
 }
+
+spl_status spl_render_noalloc(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
+                              const spl_params *prm, float *out, spl_stats *st, void *stream) {
+  if (!c) return SPL_EINVAL;
+  TRY(check_params(c, prm, true));
+  TRY(check_particles(c, p, prm->mode));
+  if (!c->scratch) return fail(c, SPL_EDEVICE, "scratch address unknown on device %d", c->device);
+  HIPTRY(c, hipSetDevice(c->device));
+  // the per-particle buffers bound the particle count up front; the lists,
+  // whose size the frame learns after its count, are checked when carved
+  const bool sorted = prm->mode == SPL_SORTED;
+  const size_t per_particle = 32 + 8 + (sorted ? 8 : 0);
+  const size_t fixed = (size_t)kFinBlocks * 6 * 8 + 64 + sizeof(Totals) + 4096;
+  if (p->n > 0 && (size_t)p->n > (kScratchBytes - fixed) / per_particle)
+    return fail(c, SPL_ENOMEM,
+                "%lld particles need %zu bytes of per-particle workspace; the %zu-byte scratch "
+                "holds at most %zu particles in this mode",
+                (long long)p->n, (size_t)p->n * per_particle, kScratchBytes,
+                (kScratchBytes - fixed) / per_particle);
+  // the frame's buffers come from the scratch: the context's own workspace
+  // is set aside and restored afterwards
+  Arena a;
+  a.base = (char *)c->scratch;
+  a.cap = kScratchBytes;
+  DevBuf *bufs[] = {&c->rec,      &c->rec2,     &c->span,  &c->counts,  &c->offsets,
+                    &c->cursor,   &c->item_off, &c->items[0], &c->items[1], &c->items[2],
+                    &c->pairs,    &c->keysA,    &c->keysB, &c->partial, &c->fin,
+                    &c->stats,    &c->totals};
+  constexpr int kBufs = (int)(sizeof(bufs) / sizeof(bufs[0]));
+  DevBuf saved[kBufs];
+  for (int k = 0; k < kBufs; ++k) {
+    saved[k] = *bufs[k];
+    *bufs[k] = DevBuf();
+  }
+  const bool timing = c->timing;
+  c->timing = false;  // stage timers create events
+  c->arena = &a;
+  const spl_status rc = render_one(c, p, cam, prm, out, st, (hipStream_t)stream);
+  c->arena = nullptr;
+  c->timing = timing;
+  for (int k = 0; k < kBufs; ++k) *bufs[k] = saved[k];
+  return rc;
+}
+
+int64_t spl_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
 
 spl_status spl_render_batch(spl_ctx *c, const spl_particles *p, int32_t n_views,
                             const spl_camera *cams, const spl_params *prms, float *const *outs,
