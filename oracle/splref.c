@@ -33,6 +33,10 @@
  *  external look-up table).  g = log10(s) or s; t = clamp((g-lo)/(hi-lo), 0, 1)
  *  (t = 0 when hi = lo or when s <= 0 under the logarithm); linear
  *  interpolation between M evenly spaced entries; E = brightness * I * c.
+ *  Sect. 2.1 also allows the colour to come directly from a vector field: a
+ *  species with vector_colour takes c = the particle's own rgb vector (no
+ *  ranging), and a particle whose vector has a non-finite component is
+ *  inactive.
  *
  *  Radiative transfer (Sect. 2.1 refers to the transfer equation; Sect. 3.2.2
  *  describes additive drawing).  Per particle slab with optical depth
@@ -116,6 +120,7 @@ int sr_validate(const sr_camera *cam, const sr_params *prm) {
   if (!(prm->nu > 0.0) || !isfinite(prm->nu)) return SR_EINVAL;
   for (k = 0; k < prm->n_species; ++k) {
     const sr_look *l = &prm->looks[k];
+    if (l->vector_colour) continue; /* no palette is read */
     if (!l->rgb || l->n_entries < 1) return SR_EINVAL;
     if (!isfinite(l->lo) || !isfinite(l->hi) || !(l->hi >= l->lo)) return SR_EINVAL;
     if (!isfinite(l->brightness)) return SR_EINVAL;
@@ -193,7 +198,12 @@ static void project_one(const double fr[13], const sr_camera *cam,
         o->R <= SR_RANGE_LIMIT))
     return;
   l = &prm->looks[sp];
-  palette_lookup(l, normalise_scalar(s, l), c);
+  if (l->vector_colour) {
+    for (q = 0; q < 3; ++q) c[q] = p->rgb[3 * k + q];
+    if (!(isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]))) return;
+  } else {
+    palette_lookup(l, normalise_scalar(s, l), c);
+  }
   for (q = 0; q < 3; ++q) o->E[q] = l->brightness * I * c[q];
   o->a = a;
   if (prm->mode != SR_SORTED) {
@@ -228,8 +238,42 @@ int sr_project(const sr_particles *p, const sr_camera *cam,
   if (p->n > 0 && (!p->x || !p->y || !p->z || !p->h || !p->intensity || !p->scalar))
     return SR_EINVAL;
   if (prm->mode == SR_SORTED && p->n > 0 && !p->absorption) return SR_EINVAL;
+  for (k = 0; k < prm->n_species; ++k)
+    if (prm->looks[k].vector_colour && p->n > 0 && !p->rgb) return SR_EINVAL;
   sr_frame(cam, fr);
   for (k = 0; k < p->n; ++k) project_one(fr, cam, prm, p, k, &out[k], &valid);
+  return SR_OK;
+}
+
+int sr_expected_flux(const sr_particles *p, const sr_camera *cam,
+                     const sr_params *prm, double expected[3]) {
+  sr_proj *pr;
+  int64_t k;
+  int rc, q;
+  if (!p || p->n < 0 || !expected) return SR_EINVAL;
+  if (sr_validate(cam, prm) != SR_OK || prm->mode == SR_SORTED) return SR_EINVAL;
+  pr = (sr_proj *)malloc(sizeof(sr_proj) * (p->n > 0 ? p->n : 1));
+  if (!pr) return SR_ENOMEM;
+  rc = sr_project(p, cam, prm, pr);
+  if (rc != SR_OK) {
+    free(pr);
+    return rc;
+  }
+  for (q = 0; q < 3; ++q) expected[q] = 0.0;
+  for (k = 0; k < p->n; ++k) {
+    const sr_proj *o = &pr[k];
+    double kappa = 0.0, R2 = o->R * o->R, amp;
+    int i, j;
+    if (!o->active) continue;
+    amp = 1.0 / (SR_PI * o->sigma * o->sigma);
+    for (j = o->j0; j <= o->j1; ++j)
+      for (i = o->i0; i <= o->i1; ++i) {
+        double dx = i + 0.5 - o->X, dy = j + 0.5 - o->Y, d2 = dx * dx + dy * dy;
+        if (d2 <= R2) kappa += amp * exp(-d2 / (o->sigma * o->sigma));
+      }
+    for (q = 0; q < 3; ++q) expected[q] += o->E[q] * kappa;
+  }
+  free(pr);
   return SR_OK;
 }
 
@@ -397,6 +441,8 @@ int sr_render_brute(const sr_particles *p, const sr_camera *cam,
   if (sr_validate(cam, prm) != SR_OK || prm->mode == SR_SORTED) return SR_EINVAL;
   if (p->n > 0 && (!p->x || !p->y || !p->z || !p->h || !p->intensity || !p->scalar))
     return SR_EINVAL;
+  for (k = 0; k < prm->n_species; ++k)
+    if (prm->looks[k].vector_colour && p->n > 0 && !p->rgb) return SR_EINVAL;
   sr_frame(cam, fr);
   npx = (int64_t)cam->width * cam->height;
   memset(out, 0, sizeof(double) * 3 * npx);

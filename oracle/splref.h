@@ -47,6 +47,7 @@ typedef struct {
   int32_t log10_scalar; /* 1: normalise log10(scalar) instead of scalar */
   double brightness;    /* multiplies every emission of the species */
   double lo, hi;        /* normalisation range of the (log) scalar, hi >= lo */
+  int32_t vector_colour; /* 1: colour = the particle's rgb vector, no palette */
 } sr_look;
 
 typedef struct {
@@ -67,6 +68,7 @@ typedef struct {
   const double *scalar;      /* scalar field mapped through the palette */
   const double *absorption;  /* per-particle absorption; SR_SORTED only */
   const uint8_t *species;    /* may be NULL: every particle is species 0 */
+  const double *rgb;         /* n x 3 colour vectors; needed by vector_colour */
 } sr_particles;
 
 /* Per-particle result of transform, projection, clipping and colour. */
@@ -143,6 +145,13 @@ int sr_bin_records(int64_t n, const float *rec, const float *rec2,
 int sr_render_records(int64_t n, const float *rec, const float *rec2,
                       int32_t width, int32_t height, int32_t mode, double nu,
                       double *out);
+
+/* Expected flux of the additive transfer sum: sum over active particles of
+ * E_p kappa_p, kappa_p = sum over the pixels of the particle's clipped box
+ * whose centres lie within R of tau_p (the sampled, truncated, clipped
+ * kernel).  expected[3] per channel. */
+int sr_expected_flux(const sr_particles *p, const sr_camera *cam,
+                     const sr_params *prm, double expected[3]);
 
 /* Image statistics: per-channel sum and maximum. */
 void sr_image_stats(const double *img, int32_t width, int32_t height,

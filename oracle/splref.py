@@ -38,7 +38,7 @@ class _Camera(C.Structure):
 class _Look(C.Structure):
     _fields_ = [("rgb", C.POINTER(C.c_float)), ("n_entries", C.c_int32),
                 ("log10_scalar", C.c_int32), ("brightness", C.c_double),
-                ("lo", C.c_double), ("hi", C.c_double)]
+                ("lo", C.c_double), ("hi", C.c_double), ("vector_colour", C.c_int32)]
 
 
 class _Params(C.Structure):
@@ -52,7 +52,8 @@ class _Particles(C.Structure):
                 ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
                 ("z", C.POINTER(C.c_double)), ("h", C.POINTER(C.c_double)),
                 ("intensity", C.POINTER(C.c_double)), ("scalar", C.POINTER(C.c_double)),
-                ("absorption", C.POINTER(C.c_double)), ("species", C.POINTER(C.c_uint8))]
+                ("absorption", C.POINTER(C.c_double)), ("species", C.POINTER(C.c_uint8)),
+                ("rgb", C.POINTER(C.c_double))]
 
 
 class Proj(C.Structure):
@@ -89,6 +90,8 @@ def lib():
                                      C.c_int64, C.POINTER(C.c_int64)]
         L.sr_render_records.argtypes = [C.c_int64, fp, fp, C.c_int32, C.c_int32, C.c_int32,
                                         C.c_double, dp]
+        L.sr_expected_flux.argtypes = [C.POINTER(_Particles), C.POINTER(_Camera),
+                                       C.POINTER(_Params), dp]
         L.sr_image_stats.argtypes = [dp, C.c_int32, C.c_int32, dp, dp]
         L.sr_image_stats.restype = None
         _lib = L
@@ -117,7 +120,9 @@ class Looks:
     """Keeps the palettes alive while the C structs point at them."""
 
     def __init__(self, looks):
-        self.pals = [np.ascontiguousarray(l["rgb"], dtype=np.float32) for l in looks]
+        # a species coloured from the vector field needs no palette
+        self.pals = [np.ascontiguousarray(l.get("rgb", np.zeros((1, 3))), dtype=np.float32)
+                     for l in looks]
         self.arr = (_Look * len(looks))()
         for k, l in enumerate(looks):
             self.arr[k].rgb = _ptr(self.pals[k], C.c_float)
@@ -126,6 +131,7 @@ class Looks:
             self.arr[k].brightness = float(l.get("brightness", 1.0))
             self.arr[k].lo = float(l.get("lo", 0.0))
             self.arr[k].hi = float(l.get("hi", 1.0))
+            self.arr[k].vector_colour = int(l.get("vector", 0))
 
 
 def params(mode, looks: Looks, k_sigma=1.0 / 3.0, sigma_min=0.5, nu=3.0, normalise=0) -> _Params:
@@ -143,13 +149,15 @@ def params(mode, looks: Looks, k_sigma=1.0 / 3.0, sigma_min=0.5, nu=3.0, normali
 class Particles:
     """FP64 copies of a particle set (inputs widened exactly from float32)."""
 
-    def __init__(self, ps, absorption=None):
+    def __init__(self, ps, absorption=None, rgb=None):
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         self.x, self.y, self.z = f64(ps.x), f64(ps.y), f64(ps.z)
         self.h, self.i, self.s = f64(ps.h), f64(ps.intensity), f64(ps.scalar)
         a = absorption if absorption is not None else ps.absorption
         self.a = None if a is None else f64(a)
         self.sp = np.ascontiguousarray(ps.species, dtype=np.uint8)
+        c = rgb if rgb is not None else getattr(ps, "rgb", None)
+        self.rgb = None if c is None else f64(np.asarray(c).reshape(-1, 3))
         self.st = _Particles()
         self.st.n = self.x.shape[0]
         self.st.x, self.st.y, self.st.z = (_ptr(self.x, C.c_double), _ptr(self.y, C.c_double),
@@ -159,6 +167,7 @@ class Particles:
         self.st.scalar = _ptr(self.s, C.c_double)
         self.st.absorption = _ptr(self.a, C.c_double)
         self.st.species = _ptr(self.sp, C.c_uint8)
+        self.st.rgb = _ptr(self.rgb, C.c_double)
 
 
 def check(rc, what):
@@ -244,6 +253,13 @@ def render_records(rec, rec2, width, height, mode, nu=3.0) -> np.ndarray:
     check(lib().sr_render_records(rec.shape[0], _ptr(rec, C.c_float), _ptr(rec2, C.c_float),
                                   width, height, mode, nu, _ptr(out, C.c_double)),
           "sr_render_records")
+    return out
+
+
+def expected_flux(ps: Particles, pose, prm: _Params) -> np.ndarray:
+    out = np.zeros(3, np.float64)
+    check(lib().sr_expected_flux(C.byref(ps.st), C.byref(camera(pose)), C.byref(prm),
+                                 _ptr(out, C.c_double)), "sr_expected_flux")
     return out
 
 

@@ -28,6 +28,7 @@ class ParticleSet:
     species: np.ndarray  # uint8
     absorption: np.ndarray | None = None  # float32, sorted mode
     meta: dict = field(default_factory=dict)
+    rgb: np.ndarray | None = None  # float32 (n, 3) colour vector field
 
     @property
     def n(self) -> int:
@@ -35,9 +36,10 @@ class ParticleSet:
 
     def subset(self, idx) -> "ParticleSet":
         a = None if self.absorption is None else self.absorption[idx]
+        c = None if self.rgb is None else self.rgb[idx]
         return ParticleSet(self.x[idx], self.y[idx], self.z[idx], self.h[idx],
                            self.intensity[idx], self.scalar[idx], self.species[idx],
-                           a, dict(self.meta))
+                           a, dict(self.meta), c)
 
 
 @dataclass
@@ -172,6 +174,19 @@ def soneira_peebles(n: int, seed: int = 1001, levels: int = 4, branch: int = 8,
     return ParticleSet(x, y, z, h, inten, dens.astype(np.float32), species, absorb,
                        meta={"kind": "soneira_peebles", "seed": seed, "levels": levels,
                              "branch": branch, "lam": lam, "n_leaves": n_leaves})
+
+
+def colour_field(ps: ParticleSet, seed: int = 4001, dim: float = 0.04) -> np.ndarray:
+    """A colour vector field for the set, shape (n, 3) float32: a smooth
+    function of position (each channel a sinusoid of a random direction, as a
+    velocity or magnetic-field direction mapped to RGB would be) in
+    [dim, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = np.stack([ps.x, ps.y, ps.z], axis=1).astype(np.float64)
+    k = rng.normal(0.0, 6.0, size=(3, 3))
+    ph = rng.uniform(0.0, 2.0 * math.pi, size=3)
+    c = 0.5 + 0.5 * np.sin(pos @ k.T + ph)
+    return np.ascontiguousarray(dim + (1.0 - dim) * c, dtype=np.float32)
 
 
 def random_poses(count: int, seed: int = 2001, width: int = 1024, height: int = 1024,

@@ -6,7 +6,8 @@ import numpy as np
 from paper_1606_04427_amd.synth import ParticleSet, Pose
 
 
-def particles(xyz, h, intensity=None, scalar=None, species=None, absorption=None) -> ParticleSet:
+def particles(xyz, h, intensity=None, scalar=None, species=None, absorption=None,
+              rgb=None) -> ParticleSet:
     xyz = np.asarray(xyz, dtype=np.float32).reshape(-1, 3)
     n = xyz.shape[0]
     h = np.broadcast_to(np.asarray(h, dtype=np.float32), (n,)).copy()
@@ -17,7 +18,10 @@ def particles(xyz, h, intensity=None, scalar=None, species=None, absorption=None
     sp = np.zeros(n, np.uint8) if species is None else np.asarray(species, np.uint8).copy()
     ab = None if absorption is None else np.broadcast_to(
         np.asarray(absorption, np.float32), (n,)).copy()
-    return ParticleSet(xyz[:, 0].copy(), xyz[:, 1].copy(), xyz[:, 2].copy(), h, inten, sc, sp, ab)
+    c = None if rgb is None else np.ascontiguousarray(
+        np.broadcast_to(np.asarray(rgb, np.float32).reshape(-1, 3), (n, 3)))
+    return ParticleSet(xyz[:, 0].copy(), xyz[:, 1].copy(), xyz[:, 2].copy(), h, inten, sc, sp, ab,
+                       rgb=c)
 
 
 def axis_camera(width=64, height=64, dist=10.0, fov=90.0, z_near=1e-3) -> Pose:
