@@ -70,6 +70,11 @@ typedef struct {
                                 FP32 and BF16) */
   const uint8_t *species;    /* n bytes, or NULL (all species 0) */
   const float *absorption;   /* n floats, SPL_SORTED only, else ignored */
+  const void *rgb;           /* colour vector field (Sect. 2.1: colour taken
+                                directly from a vector input field), n x 3
+                                attr_dtype, row per particle; NULL unless a
+                                species colours from it */
+  float c_scale;             /* colour vector = c_scale * rgb */
 } spl_particles;
 
 /* Camera and look-at positions (Sect. 2.1).  Forward = lookat - eye, right =
@@ -81,16 +86,22 @@ typedef struct {
   int32_t width, height;
 } spl_camera;
 
-/* One colour map per species (Sect. 2.1 "color map loaded at runtime"; the
- * scene file varies brightness and palette thresholds).  rgb: device memory,
- * n_entries x 3 floats, entries evenly spaced over the normalised scalar.
- * The (log10 if log10_scalar) scalar is normalised by [lo, hi], hi >= lo. */
+/* One look per species (Sect. 2.1: colour generated either as a function of
+ * a scalar through a colour map loaded at run time, or directly from a
+ * vector input field; the scene file varies brightness and palette
+ * thresholds).  Palette colouring (vector_colour = 0): rgb is device memory,
+ * n_entries x 3 floats, entries evenly spaced over the normalised scalar; the
+ * (log10 if log10_scalar) scalar is normalised by [lo, hi], hi >= lo.
+ * Vector colouring (vector_colour = 1): the colour is the particle's own
+ * rgb vector (spl_particles.rgb, required); palette fields are ignored.
+ * Either way the emission is brightness x intensity x colour. */
 typedef struct {
   const float *rgb;
   int32_t n_entries;    /* 1 .. 4096 */
   int32_t log10_scalar;
   double brightness;
   double lo, hi;
+  int32_t vector_colour;
 } spl_look;
 
 typedef struct {
@@ -107,6 +118,9 @@ typedef struct {
                          particle path (additive modes); 0 = library choice,
                          < 0 = never */
   int32_t normalise;  /* 1: divide the image by its maximum value */
+  int32_t flux_check; /* additive modes, 1: also compute the expected flux
+                         (spl_stats.expected_flux), one more pass over the
+                         particles' pixel boxes */
 } spl_params;
 
 /* Per-render statistics; flux and max are FP64 reductions over the final
@@ -121,17 +135,34 @@ typedef struct {
   double max[3];         /* maximum pixel value, per channel */
   int32_t tile;          /* tile size used */
   double large_cut;      /* large-particle cut used, px */
+  double raw_flux[3];    /* additive modes: sum over pixels of J = sum_p E_p
+                            tau_p before the absorption = emission map (FP64) */
+  double expected_flux[3]; /* flux_check: sum over particles of E_p kappa_p,
+                            kappa_p = the particle's sampled, truncated and
+                            clipped kernel summed over its pixels (FP64
+                            accumulation); equals raw_flux up to rounding when
+                            every contribution reaches the image; NaN
+                            otherwise */
 } spl_stats;
 
 typedef struct spl_ctx spl_ctx;
 
-/* Creates a context bound to `device`.  The workspace grows on demand. */
+typedef struct spl_dataset spl_dataset;
+
+/* Creates a context bound to `device`: one stream-ordered worker with a
+ * device workspace that grows on demand and is reused by every later frame
+ * (Sect. 3.2.1: allocation on the hot path is a large cost, so buffers are
+ * pooled and reused rather than allocated per frame). */
 spl_status spl_create(int device, spl_ctx **out);
 void spl_destroy(spl_ctx *ctx);
 /* Message for the last failed call on this context (never NULL). */
 const char *spl_last_error(const spl_ctx *ctx);
 /* Device memory currently held by the context workspace, bytes. */
 int64_t spl_workspace_bytes(const spl_ctx *ctx);
+/* Releases the context workspace (after the device finishes its work); the
+ * next frame allocates what it needs again.  For callers that share a device
+ * memory budget between several contexts. */
+spl_status spl_trim(spl_ctx *ctx);
 
 /* Ranging (Sect. 2.1 preprocessing): per-species min / max of the scalar
  * field, or of log10 of it (values <= 0 skipped), over finite values.  lo, hi:
@@ -163,9 +194,11 @@ spl_status spl_bin(spl_ctx *ctx, int64_t n, const float *rec, const float *rec2,
                    uint32_t *offsets, uint32_t *pairs, int64_t pairs_cap,
                    int64_t *n_pairs, void *stream);
 
-/* Renders records made by spl_project (same camera size): the tiled splat,
- * large-particle path, depth sort and finalisation of spl_render, starting
- * after the projection.  cam supplies width and height; prm supplies mode,
+/* Renders records made by spl_project (same camera size): the rendering
+ * stage of Sect. 3.1 (tile lists, then each tile's list drawn by the worker
+ * that owns the tile's pixels, the image accumulated on the device), i.e. the
+ * tiled splat, large-particle path, depth sort and finalisation of
+ * spl_render, starting after the projection.  cam supplies width and height; prm supplies mode,
  * nu, tile, bin_rule, large_cut and normalise.  out: device image.  st may be
  * NULL (then the call does not synchronise at the end). */
 spl_status spl_render_records(spl_ctx *ctx, int64_t n, const float *rec,
@@ -173,11 +206,41 @@ spl_status spl_render_records(spl_ctx *ctx, int64_t n, const float *rec,
                               const spl_params *prm, float *out, spl_stats *st,
                               void *stream);
 
-/* Full frame: projection + colour, tile binning, splat (small and large
- * particle paths, or depth-sorted compositing), finalisation.  out: device
- * image.  st may be NULL. */
+/* Full frame (Sect. 2.1: particles, camera and colour maps in, an RGB image
+ * out; Sect. 3.1: rasterisation loops, then the tiled render): projection +
+ * colour, tile binning, splat (small and large particle paths, or
+ * depth-sorted compositing), finalisation.  p: device arrays the caller owns.
+ * out: device image.  st may be NULL. */
 spl_status spl_render(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
                       const spl_params *prm, float *out, spl_stats *st, void *stream);
+
+/* Resident data sets (Sect. 2.1: particle data are converted to the code's
+ * internal format as they are read).  Copies src (host arrays when
+ * src_on_device = 0, device arrays on the context's device when 1) into
+ * device memory the data set owns, converting h, intensity, scalar and rgb to
+ * store_dtype on the device: FP32 as is, BF16 rounded to nearest even, FP16
+ * divided by a power of two per array (the one that puts the largest finite
+ * magnitude in [2^10, 2^11)) and rounded to nearest even.  Positions,
+ * species and absorption are copied as they are.  The data set lives on the
+ * context's device until spl_dataset_free and may be used by every context
+ * on that device (concurrent renders only read it).  Synchronises. */
+spl_status spl_dataset_upload(spl_ctx *ctx, const spl_particles *src, int32_t src_on_device,
+                              int32_t store_dtype, spl_dataset **out, void *stream);
+void spl_dataset_free(spl_dataset *ds);
+/* The resident arrays (device pointers, stored dtype and scales) for the
+ * calls that take spl_particles.  The pointers stay valid until
+ * spl_dataset_free. */
+spl_status spl_dataset_particles(const spl_dataset *ds, spl_particles *out);
+/* Device bytes the data set holds. */
+int64_t spl_dataset_bytes(const spl_dataset *ds);
+
+/* spl_render on a resident data set.  out_on_device = 1: out is a device
+ * image; 0: out is host memory (height x width x 3 floats), filled from a
+ * device image in the context workspace (Sect. 3.1: the image is copied back
+ * to the host at the end), and the call synchronises. */
+spl_status spl_render_dataset(spl_ctx *ctx, const spl_dataset *ds, const spl_camera *cam,
+                              const spl_params *prm, float *out, int32_t out_on_device,
+                              spl_stats *st, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the frame of
@@ -208,10 +271,39 @@ int64_t spl_noalloc_scratch_bytes(void);
 spl_status spl_render_batch(spl_ctx *ctx, const spl_particles *p, int32_t n_views,
                             const spl_camera *cams, const spl_params *prms,
                             float *const *outs, spl_stats *st, void *stream);
+/* spl_render_batch on a resident data set; outs[v] are device images when
+ * out_on_device = 1, host memory when 0 (then the call synchronises). */
+spl_status spl_render_batch_dataset(spl_ctx *ctx, const spl_dataset *ds, int32_t n_views,
+                                    const spl_camera *cams, const spl_params *prms,
+                                    float *const *outs, int32_t out_on_device, spl_stats *st,
+                                    void *stream);
 
-/* Picks the tile size and large-particle cut that render this view fastest
- * (timed on the device) and caches the choice for (n, width x height, mode).
- * tile and large_cut: host outputs.  Synchronises. */
+/* Out-of-core rendering (Sect. 3.1: data larger than the device memory are
+ * copied in chunks into two device buffers, the next chunk copied while the
+ * current one renders, and the image accumulates over the chunks before it
+ * is copied back).  p: host arrays (attr_dtype any; memory from
+ * spl_host_alloc lets the copies overlap the rendering, pageable memory
+ * works without the overlap).  chunk: particles per chunk, >= 1; the two
+ * buffers hold 2 x chunk particles.  The copies run on a second stream of
+ * the context (default priority) ordered against `stream` by events.
+ * Additive modes only: SPL_EUNSUPPORTED for SPL_SORTED (depth order spans
+ * chunks).  The absorption = emission map and the normalisation apply once,
+ * to the summed image.  out/out_on_device as spl_render_dataset; st sums the
+ * particle and list counts over the chunks.  Synchronises. */
+spl_status spl_render_stream(spl_ctx *ctx, const spl_particles *p, int64_t chunk,
+                             const spl_camera *cam, const spl_params *prm, float *out,
+                             int32_t out_on_device, spl_stats *st, void *stream);
+/* Page-locked host memory for spl_render_stream's inputs. */
+spl_status spl_host_alloc(size_t bytes, void **out);
+void spl_host_free(void *p);
+
+/* Tuning (Sect. 3.2.3: a script runs the code over candidate values of the
+ * tile size and keeps the fastest).  Renders this view with tile sizes 16
+ * and 32 and large-particle cuts 16, 32, 64, 128 px and none, timed on the
+ * device, and caches the fastest choice for (n, width x height, mode, camera
+ * pose): later frames of the same view with tile = 0 or large_cut = 0 take
+ * it; other poses of the same size take the choice of the most recently
+ * tuned pose.  tile and large_cut: host outputs.  Synchronises. */
 spl_status spl_autotune(spl_ctx *ctx, const spl_particles *p, const spl_camera *cam,
                         const spl_params *prm, int32_t *tile, double *large_cut,
                         void *stream);

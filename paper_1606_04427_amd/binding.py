@@ -23,7 +23,10 @@ SPL_MAX_SPECIES = 8
 EXPORTS = ["spl_create", "spl_destroy", "spl_last_error", "spl_workspace_bytes",
            "spl_scalar_range", "spl_project", "spl_bin", "spl_render_records", "spl_render",
            "spl_render_batch", "spl_autotune", "spl_set_timing", "spl_get_timing",
-           "spl_set_option", "spl_render_noalloc", "spl_noalloc_scratch_bytes"]
+           "spl_set_option", "spl_render_noalloc", "spl_noalloc_scratch_bytes",
+           "spl_dataset_upload", "spl_dataset_free", "spl_dataset_particles", "spl_dataset_bytes",
+           "spl_render_dataset", "spl_render_batch_dataset", "spl_render_stream",
+           "spl_host_alloc", "spl_host_free", "spl_trim"]
 SPL_OPT_TIMING, SPL_OPT_GRAPHS, SPL_OPT_BATCH_BYTES, SPL_OPT_BATCH_PAIRS = 0, 1, 2, 3
 SPL_N_STAGES = 9
 STAGES = ["project", "count", "scan", "host_gap_items", "scatter", "sort", "large_splat",
@@ -35,7 +38,7 @@ class spl_particles(C.Structure):
                 ("h", C.c_void_p), ("intensity", C.c_void_p), ("scalar", C.c_void_p),
                 ("attr_dtype", C.c_int32), ("h_scale", C.c_float), ("i_scale", C.c_float),
                 ("s_scale", C.c_float), ("species", C.c_void_p),
-                ("absorption", C.c_void_p)]
+                ("absorption", C.c_void_p), ("rgb", C.c_void_p), ("c_scale", C.c_float)]
 
 
 class spl_camera(C.Structure):
@@ -46,27 +49,31 @@ class spl_camera(C.Structure):
 
 class spl_look(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("n_entries", C.c_int32), ("log10_scalar", C.c_int32),
-                ("brightness", C.c_double), ("lo", C.c_double), ("hi", C.c_double)]
+                ("brightness", C.c_double), ("lo", C.c_double), ("hi", C.c_double),
+                ("vector_colour", C.c_int32)]
 
 
 class spl_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_species", C.c_int32),
                 ("looks", spl_look * SPL_MAX_SPECIES), ("k_sigma", C.c_double),
                 ("sigma_min", C.c_double), ("nu", C.c_double), ("tile", C.c_int32),
-                ("bin_rule", C.c_int32), ("large_cut", C.c_double), ("normalise", C.c_int32)]
+                ("bin_rule", C.c_int32), ("large_cut", C.c_double), ("normalise", C.c_int32),
+                ("flux_check", C.c_int32)]
 
 
 class spl_stats(C.Structure):
     _fields_ = [("n_active", C.c_int64), ("n_large", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_large_pairs", C.c_int64), ("n_items", C.c_int64),
                 ("flux", C.c_double * 3), ("max", C.c_double * 3), ("tile", C.c_int32),
-                ("large_cut", C.c_double)]
+                ("large_cut", C.c_double), ("raw_flux", C.c_double * 3),
+                ("expected_flux", C.c_double * 3)]
 
     def as_dict(self):
         return {"n_active": self.n_active, "n_large": self.n_large, "n_pairs": self.n_pairs,
                 "n_large_pairs": self.n_large_pairs, "n_items": self.n_items,
                 "flux": list(self.flux), "max": list(self.max), "tile": self.tile,
-                "large_cut": self.large_cut}
+                "large_cut": self.large_cut, "raw_flux": list(self.raw_flux),
+                "expected_flux": list(self.expected_flux)}
 
 
 _lib = None
@@ -109,9 +116,29 @@ def lib():
                                          C.POINTER(spl_params), vp, C.POINTER(spl_stats), vp]
         L.spl_noalloc_scratch_bytes.argtypes = []
         L.spl_noalloc_scratch_bytes.restype = i64
+        L.spl_dataset_upload.argtypes = [vp, C.POINTER(spl_particles), i32, i32, C.POINTER(vp),
+                                         vp]
+        L.spl_dataset_free.argtypes = [vp]
+        L.spl_dataset_free.restype = None
+        L.spl_dataset_particles.argtypes = [vp, C.POINTER(spl_particles)]
+        L.spl_dataset_bytes.argtypes = [vp]
+        L.spl_dataset_bytes.restype = i64
+        L.spl_render_dataset.argtypes = [vp, vp, C.POINTER(spl_camera), C.POINTER(spl_params),
+                                         vp, i32, C.POINTER(spl_stats), vp]
+        L.spl_render_batch_dataset.argtypes = [vp, vp, i32, C.POINTER(spl_camera),
+                                               C.POINTER(spl_params), C.POINTER(vp), i32,
+                                               C.POINTER(spl_stats), vp]
+        L.spl_render_stream.argtypes = [vp, C.POINTER(spl_particles), i64, C.POINTER(spl_camera),
+                                        C.POINTER(spl_params), vp, i32, C.POINTER(spl_stats),
+                                        vp]
+        L.spl_host_alloc.argtypes = [C.c_size_t, C.POINTER(vp)]
+        L.spl_host_free.argtypes = [vp]
+        L.spl_host_free.restype = None
+        L.spl_trim.argtypes = [vp]
         for name in EXPORTS:
             if name not in ("spl_destroy", "spl_last_error", "spl_workspace_bytes",
-                            "spl_noalloc_scratch_bytes"):
+                            "spl_noalloc_scratch_bytes", "spl_dataset_free",
+                            "spl_dataset_bytes", "spl_host_free"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -144,49 +171,135 @@ def make_camera(pose) -> spl_camera:
     return c
 
 
-class DeviceParticles:
-    """A particle set resident in device memory (torch tensors), in the
-    structure-of-arrays layout the library reads."""
+def host_particles(ps):
+    """spl_particles over the host arrays of a particle set (FP32 attributes,
+    unit scales); returns the struct and the arrays that keep it valid."""
+    keep = []
 
-    def __init__(self, ps, device="cuda:0", attr_dtype="f32", h_scale=None):
-        import torch
+    def arr(a, dt):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a.ctypes.data
 
-        self.device = device
-        f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
-        self.x, self.y, self.z = f32(ps.x), f32(ps.y), f32(ps.z)
-        def pow2_scale(a):
-            # FP16 storage: a power of two that maps the largest magnitude
-            # near 2^10, well inside the FP16 range
-            if attr_dtype != "f16":
-                return 1.0
-            a = np.asarray(a, np.float64)
-            fin = np.abs(a[np.isfinite(a)])
-            m = float(fin.max()) if fin.size else 0.0
-            return 2.0 ** math.floor(math.log2(m / 1024.0)) if m > 0 else 1.0
+    st = spl_particles()
+    st.n = int(ps.x.shape[0])
+    st.x, st.y, st.z = arr(ps.x, np.float32), arr(ps.y, np.float32), arr(ps.z, np.float32)
+    st.h = arr(ps.h, np.float32)
+    st.intensity = arr(ps.intensity, np.float32)
+    st.scalar = arr(ps.scalar, np.float32)
+    st.attr_dtype = SPL_F32
+    st.h_scale = st.i_scale = st.s_scale = st.c_scale = 1.0
+    st.species = arr(ps.species, np.uint8)
+    st.absorption = arr(ps.absorption, np.float32)
+    st.rgb = arr(getattr(ps, "rgb", None), np.float32)
+    return st, keep
 
-        self.h_scale = float(h_scale) if h_scale is not None else pow2_scale(ps.h)
-        self.i_scale = pow2_scale(ps.intensity)
-        self.s_scale = pow2_scale(ps.scalar)
-        tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[attr_dtype]
-        self.code = {"f32": SPL_F32, "bf16": SPL_BF16, "f16": SPL_F16}[attr_dtype]
-        cast = lambda a, sc: torch.from_numpy(
-            np.ascontiguousarray(np.asarray(a, np.float64) / sc, np.float32)).to(device).to(tdt)
-        self.h = cast(ps.h, self.h_scale)
-        self.intensity = cast(ps.intensity, self.i_scale)
-        self.scalar = cast(ps.scalar, self.s_scale)
-        self.species = torch.from_numpy(np.ascontiguousarray(ps.species, np.uint8)).to(device)
-        self.absorption = None if ps.absorption is None else f32(ps.absorption)
-        self.n = int(ps.x.shape[0])
+
+DTYPE_CODES = {"f32": SPL_F32, "bf16": SPL_BF16, "f16": SPL_F16}
+
+
+class Dataset:
+    """A particle set resident in device memory that the library owns
+    (spl_dataset_upload): the host arrays are copied in and h, intensity,
+    scalar and the colour vectors are converted to the stored dtype on the
+    device.  `st` is the resident view (spl_dataset_particles)."""
+
+    def __init__(self, ctx, ps, store="f32"):
+        self.L = lib()
+        self.code = DTYPE_CODES[store]
+        src, keep = host_particles(ps)
+        h = C.c_void_p()
+        ctx._check(self.L.spl_dataset_upload(ctx.h, C.byref(src), 0, self.code, C.byref(h),
+                                             _stream()))
+        del keep
+        self.h = h
         self.st = spl_particles()
-        self.st.n = self.n
-        self.st.x, self.st.y, self.st.z = _ptr(self.x), _ptr(self.y), _ptr(self.z)
-        self.st.h, self.st.intensity, self.st.scalar = _ptr(self.h), _ptr(self.intensity), _ptr(self.scalar)
-        self.st.attr_dtype = self.code
-        self.st.h_scale = self.h_scale
-        self.st.i_scale = self.i_scale
-        self.st.s_scale = self.s_scale
-        self.st.species = _ptr(self.species)
-        self.st.absorption = _ptr(self.absorption)
+        self.L.spl_dataset_particles(h, C.byref(self.st))
+        self.n = int(src.n)
+        self.device = f"cuda:{ctx.device}"
+
+    def nbytes(self) -> int:
+        return int(self.L.spl_dataset_bytes(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.spl_dataset_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_uploaders = {}
+
+
+def _uploader(device):
+    """One library context per device for uploads that have no context of
+    their own."""
+    import torch
+
+    idx = torch.device(device).index or 0
+    if idx not in _uploaders:
+        _uploaders[idx] = Context(idx)
+    return _uploaders[idx]
+
+
+class DeviceParticles(Dataset):
+    """A resident data set uploaded through a shared per-device context
+    (the same conversion as Dataset)."""
+
+    def __init__(self, ps, device="cuda:0", attr_dtype="f32"):
+        super().__init__(_uploader(device), ps, attr_dtype)
+
+
+class PinnedParticles:
+    """Host copies of a particle set in page-locked memory (spl_host_alloc),
+    the input of out-of-core rendering (spl_render_stream)."""
+
+    def __init__(self, ps):
+        self.L = lib()
+        self.blocks = []
+
+        def pin(a, dt):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dt)
+            p = C.c_void_p()
+            if self.L.spl_host_alloc(a.nbytes, C.byref(p)) != SPL_OK:
+                raise SplotchError(SPL_ENOMEM, "spl_host_alloc failed")
+            self.blocks.append(p)
+            C.memmove(p, a.ctypes.data, a.nbytes)
+            return p.value
+
+        st = spl_particles()
+        st.n = int(ps.x.shape[0])
+        st.x, st.y, st.z = pin(ps.x, np.float32), pin(ps.y, np.float32), pin(ps.z, np.float32)
+        st.h = pin(ps.h, np.float32)
+        st.intensity = pin(ps.intensity, np.float32)
+        st.scalar = pin(ps.scalar, np.float32)
+        st.attr_dtype = SPL_F32
+        st.h_scale = st.i_scale = st.s_scale = st.c_scale = 1.0
+        st.species = pin(ps.species, np.uint8)
+        st.absorption = None
+        st.rgb = pin(getattr(ps, "rgb", None), np.float32)
+        self.st = st
+        self.n = st.n
+
+    def close(self):
+        for p in self.blocks:
+            self.L.spl_host_free(p)
+        self.blocks = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Palettes:
@@ -200,10 +313,11 @@ class Palettes:
 
 
 def make_params(mode, palettes: Palettes, looks, k_sigma=1.0 / 3.0, sigma_min=0.5, nu=3.0,
-                tile=0, bin_rule=0, large_cut=0.0, normalise=0) -> spl_params:
-    """looks: list of dicts with brightness, lo, hi, log10 (one per species).
-    The returned parameters keep `palettes` alive: they hold its device
-    pointers."""
+                tile=0, bin_rule=0, large_cut=0.0, normalise=0, flux_check=0) -> spl_params:
+    """looks: list of dicts with brightness, lo, hi, log10 and vector (1: the
+    species takes its colour from the particles' rgb vectors), one per
+    species.  The returned parameters keep `palettes` alive: they hold its
+    device pointers."""
     p = spl_params()
     p._palettes = palettes
     p.mode = mode
@@ -215,6 +329,7 @@ def make_params(mode, palettes: Palettes, looks, k_sigma=1.0 / 3.0, sigma_min=0.
         p.looks[k].brightness = float(l.get("brightness", 1.0))
         p.looks[k].lo = float(l.get("lo", 0.0))
         p.looks[k].hi = float(l.get("hi", 1.0))
+        p.looks[k].vector_colour = int(l.get("vector", 0))
     p.k_sigma = k_sigma
     p.sigma_min = sigma_min
     p.nu = nu
@@ -222,6 +337,7 @@ def make_params(mode, palettes: Palettes, looks, k_sigma=1.0 / 3.0, sigma_min=0.
     p.bin_rule = bin_rule
     p.large_cut = large_cut
     p.normalise = normalise
+    p.flux_check = flux_check
     return p
 
 
@@ -235,6 +351,7 @@ class Context:
         if rc != SPL_OK:
             raise SplotchError(rc, f"spl_create({device}) failed")
         self.h = h
+        self.device = device
 
     def close(self):
         if self.h:
@@ -253,6 +370,9 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(self.L.spl_workspace_bytes(self.h))
+
+    def spl_trim(self):
+        self._check(self.L.spl_trim(self.h))
 
     def spl_scalar_range(self, parts: DeviceParticles, n_species: int, log10: bool):
         lo = (C.c_double * n_species)()
@@ -340,6 +460,57 @@ class Context:
         self._check(self.L.spl_render_batch(self.h, C.byref(parts.st), nv, cams, prm_arr, out_arr,
                                             sts if stats else None, _stream()))
         return outs, ([s.as_dict() for s in sts] if stats else None)
+
+    def spl_render_dataset(self, ds: Dataset, pose, prm: spl_params, out=None, host_out=False,
+                           stats=True):
+        """host_out: the image comes back as a numpy array filled by the
+        library (device image copied to host memory)."""
+        import torch
+
+        if out is None:
+            out = (np.empty((pose.height, pose.width, 3), np.float32) if host_out else
+                   torch.empty((pose.height, pose.width, 3), dtype=torch.float32,
+                               device=ds.device))
+        ptr = out.ctypes.data if host_out else out.data_ptr()
+        st = spl_stats()
+        cam = make_camera(pose)
+        self._check(self.L.spl_render_dataset(self.h, ds.h, C.byref(cam), C.byref(prm),
+                                              C.c_void_p(ptr), 0 if host_out else 1,
+                                              C.byref(st) if stats else None, _stream()))
+        return out, (st.as_dict() if stats else None)
+
+    def spl_render_batch_dataset(self, ds: Dataset, poses, prms, outs=None, host_out=False,
+                                 stats=True):
+        import torch
+
+        nv = len(poses)
+        if outs is None:
+            outs = [np.empty((p.height, p.width, 3), np.float32) if host_out else
+                    torch.empty((p.height, p.width, 3), dtype=torch.float32, device=ds.device)
+                    for p in poses]
+        cams = (spl_camera * nv)(*[make_camera(p) for p in poses])
+        prm_arr = (spl_params * nv)(*prms)
+        out_arr = (C.c_void_p * nv)(*[o.ctypes.data if host_out else o.data_ptr() for o in outs])
+        sts = (spl_stats * nv)()
+        self._check(self.L.spl_render_batch_dataset(self.h, ds.h, nv, cams, prm_arr, out_arr,
+                                                    0 if host_out else 1,
+                                                    sts if stats else None, _stream()))
+        return outs, ([s.as_dict() for s in sts] if stats else None)
+
+    def spl_render_stream(self, host: PinnedParticles, chunk: int, pose, prm: spl_params,
+                          out=None, host_out=False, stats=True, device="cuda:0"):
+        import torch
+
+        if out is None:
+            out = (np.empty((pose.height, pose.width, 3), np.float32) if host_out else
+                   torch.empty((pose.height, pose.width, 3), dtype=torch.float32, device=device))
+        ptr = out.ctypes.data if host_out else out.data_ptr()
+        st = spl_stats()
+        cam = make_camera(pose)
+        self._check(self.L.spl_render_stream(self.h, C.byref(host.st), int(chunk), C.byref(cam),
+                                             C.byref(prm), C.c_void_p(ptr), 0 if host_out else 1,
+                                             C.byref(st) if stats else None, _stream()))
+        return out, (st.as_dict() if stats else None)
 
     def spl_set_option(self, option: int, value: int):
         self._check(self.L.spl_set_option(self.h, option, int(value)))

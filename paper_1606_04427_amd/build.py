@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libsplotch_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["k_project.hip", "k_bin.hip", "k_sort.hip", "k_splat.hip", "k_finalise.hip",
-           "runtime.hip"]
+           "k_dataset.hip", "runtime.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -18,21 +18,29 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, in
     p[i] = v;
 }
 
+__global__ void k_fill_f64(double *p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_fill_f32(float *p, float v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock)
     p[i] = v;
 }
 
+// Per block: FP64 sums of the final image (3), maxima (3) and sums of the
+// values before the map (3: the additive J), in that order.
 __global__ __launch_bounds__(kBlock) void k_finalise(float *__restrict__ img, int64_t n_px,
                                                      int aeqe, double *__restrict__ partials) {
-  __shared__ double s_red[6][kBlock];
-  double sm[3] = {0.0, 0.0, 0.0};
+  __shared__ double s_red[kStatPartials][kBlock];
+  double sm[3] = {0.0, 0.0, 0.0}, raw[3] = {0.0, 0.0, 0.0};
   double mx[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
   for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n_px;
        p += (int64_t)gridDim.x * kBlock) {
     float *o = img + 3 * p;
     float v[3] = {o[0], o[1], o[2]};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) raw[c] += (double)v[c];
     if (aeqe) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -50,6 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_finalise(float *__restrict__ img, in
   for (int c = 0; c < 3; ++c) {
     s_red[c][threadIdx.x] = sm[c];
     s_red[3 + c][threadIdx.x] = mx[c];
+    s_red[6 + c][threadIdx.x] = raw[c];
   }
   __syncthreads();
   for (int d = kBlock / 2; d > 0; d >>= 1) {
@@ -58,30 +67,35 @@ __global__ __launch_bounds__(kBlock) void k_finalise(float *__restrict__ img, in
       for (int c = 0; c < 3; ++c) {
         s_red[c][threadIdx.x] += s_red[c][threadIdx.x + d];
         s_red[3 + c][threadIdx.x] = fmax(s_red[3 + c][threadIdx.x], s_red[3 + c][threadIdx.x + d]);
+        s_red[6 + c][threadIdx.x] += s_red[6 + c][threadIdx.x + d];
       }
     }
     __syncthreads();
   }
-  if (threadIdx.x < 6) partials[6 * blockIdx.x + threadIdx.x] = s_red[threadIdx.x][0];
+  if (threadIdx.x < kStatPartials)
+    partials[kStatPartials * blockIdx.x + threadIdx.x] = s_red[threadIdx.x][0];
 }
 
-// stats[0..2] = flux, [3..5] = max per channel, [6] = max over channels.
+// stats[0..2] = flux, [3..5] = max per channel, [6] = max over channels,
+// [7..9] = flux before the map; block partials summed in block order.
 __global__ __launch_bounds__(kBlock) void k_reduce_stats(const double *__restrict__ partials,
                                                          int n_blocks, double *__restrict__ stats) {
-  __shared__ double s_red[6][kBlock];
-  double sm[3] = {0.0, 0.0, 0.0};
+  __shared__ double s_red[kStatPartials][kBlock];
+  double sm[3] = {0.0, 0.0, 0.0}, raw[3] = {0.0, 0.0, 0.0};
   double mx[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
   for (int b = threadIdx.x; b < n_blocks; b += kBlock) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      sm[c] += partials[6 * b + c];
-      mx[c] = fmax(mx[c], partials[6 * b + 3 + c]);
+      sm[c] += partials[kStatPartials * b + c];
+      mx[c] = fmax(mx[c], partials[kStatPartials * b + 3 + c]);
+      raw[c] += partials[kStatPartials * b + 6 + c];
     }
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     s_red[c][threadIdx.x] = sm[c];
     s_red[3 + c][threadIdx.x] = mx[c];
+    s_red[6 + c][threadIdx.x] = raw[c];
   }
   __syncthreads();
   for (int d = kBlock / 2; d > 0; d >>= 1) {
@@ -90,12 +104,76 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stats(const double *__restric
       for (int c = 0; c < 3; ++c) {
         s_red[c][threadIdx.x] += s_red[c][threadIdx.x + d];
         s_red[3 + c][threadIdx.x] = fmax(s_red[3 + c][threadIdx.x], s_red[3 + c][threadIdx.x + d]);
+        s_red[6 + c][threadIdx.x] += s_red[6 + c][threadIdx.x + d];
       }
     }
     __syncthreads();
   }
   if (threadIdx.x < 6) stats[threadIdx.x] = s_red[threadIdx.x][0];
   if (threadIdx.x == 0) stats[6] = fmax(fmax(s_red[3][0], s_red[4][0]), s_red[5][0]);
+  if (threadIdx.x >= 6 && threadIdx.x < 9) stats[threadIdx.x + 1] = s_red[threadIdx.x][0];
+}
+
+// Expected flux (a conservation check independent of the tile lists and the
+// splat): for every active record, kappa = the sum of exp(-d^2/sigma^2) over
+// the pixels of its box whose centres lie within the truncation radius, in
+// FP64 from the record's screen position and width; the particle adds A x
+// kappa per channel, A = E/(pi sigma^2) being the record's premultiplied
+// colour, so the total is sum_p E_p kappa_p.  Only particles whose span
+// marks them active count (the projection leaves the records of inactive
+// particles unwritten).  One wave per particle at a time, its lanes striding
+// over the box; FP64 partial sums per block.
+__global__ __launch_bounds__(kBlock) void k_expected_flux(const float4 *__restrict__ rec,
+                                                          const uint2 *__restrict__ span,
+                                                          int64_t n, int W, int H, float nu,
+                                                          double *__restrict__ partials) {
+  __shared__ double s_red[3][kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t wstride = (int64_t)gridDim.x * (kBlock / 64);
+  double acc[3] = {0.0, 0.0, 0.0};  // lane 0's running sums
+  for (int64_t k = (int64_t)blockIdx.x * (kBlock / 64) + wave; k < n; k += wstride) {
+    if (span[k].x == kInactive) continue;
+    const float4 r0 = rec[2 * k], r1 = rec[2 * k + 1];
+    int i0, i1, j0, j1;
+    if (!record_box(r0.x, r0.y, r0.z, r0.w, r1.x, nu, W, H, i0, i1, j0, j1)) continue;
+    const double X = (double)r0.x + (double)r0.y, Y = (double)r0.z + (double)r0.w;
+    const double sg = (double)r1.x, R = (double)nu * sg;
+    const double R2 = R * R, inv_s2 = 1.0 / (sg * sg);
+    const int64_t bw = i1 - i0 + 1, total = bw * (int64_t)(j1 - j0 + 1);
+    double kappa = 0.0;
+    for (int64_t t = lane; t < total; t += 64) {
+      const int i = i0 + (int)(t % bw), j = j0 + (int)(t / bw);
+      const double dx = (double)i + 0.5 - X, dy = (double)j + 0.5 - Y;
+      const double d2 = dx * dx + dy * dy;
+      if (d2 <= R2) kappa += exp(-d2 * inv_s2);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) kappa += __shfl_xor(kappa, o);
+    if (lane == 0) {
+      acc[0] += (double)r1.y * kappa;
+      acc[1] += (double)r1.z * kappa;
+      acc[2] += (double)r1.w * kappa;
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s_red[c][wave] = acc[c];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) v += s_red[threadIdx.x][w];
+    partials[3 * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+// out[0..2] = sum of the blocks' expected-flux partials, in block order.
+__global__ void k_reduce_expected(const double *__restrict__ partials, int n_blocks,
+                                  double *__restrict__ out) {
+  if (threadIdx.x < 3) {
+    double v = 0.0;
+    for (int b = 0; b < n_blocks; ++b) v += partials[3 * b + threadIdx.x];
+    out[threadIdx.x] = v;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_normalise(float *__restrict__ img, int64_t n,
@@ -137,6 +215,18 @@ hipError_t launch_finalise(float *img, int64_t n_px, int aeqe, double *partials,
 hipError_t launch_reduce_stats(const double *partials, int n_blocks, double *stats,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(kBlock), 0, s, partials, n_blocks, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_expected_flux(const float *rec, const uint2 *span, int64_t n, int W, int H,
+                                float nu, double *partials, int n_blocks, double *out,
+                                hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_expected_flux, dim3(n_blocks), dim3(kBlock), 0, s,
+                       reinterpret_cast<const float4 *>(rec), span, n, W, H, nu, partials);
+  else
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, partials, 3 * n_blocks);
+  hipLaunchKernelGGL(k_reduce_expected, dim3(1), dim3(64), 0, s, partials, n_blocks, out);
   return hipGetLastError();
 }
 

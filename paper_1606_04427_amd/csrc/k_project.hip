@@ -6,7 +6,9 @@
 // One thread per particle, grid-stride, coalesced structure-of-arrays loads.
 // Position arithmetic runs in FP64 so the single-precision record keeps the
 // screen position as integer part + fraction.  The colour map lookup and the
-// peak amplitude 1/(pi sigma^2) (from the stored sigma) run in FP32.  Output
+// peak amplitude 1/(pi sigma^2) (from the stored sigma) run in FP32.  A
+// species coloured from the vector field takes the particle's own RGB instead
+// of the colour map (Sect. 2.1 allows either).  Output
 // per active particle: a 32-byte record, optionally the 8-byte sorted-mode
 // record, and the 8-byte tile span read by the binning kernels.
 #include "bin_device.h"
@@ -84,18 +86,25 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
           const double R = P.nu * sig;
           if (fabs(X - P.cx) <= 4194304.0 && fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0) {
             const LookK L = s_looks[sp];
-            float t;
-            if (L.log10)
-              t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
-            else
-              t = (s - L.lo) * L.inv_range;
-            t = fminf(fmaxf(t, 0.0f), 1.0f);
             float c0, c1, c2;
-            if (L.M == 1) {
+            bool colour_ok = true;
+            if (L.vec) {
+              // colour taken directly from the vector field
+              c0 = load_attr(P.rgb, P.dtype, 3 * k) * P.c_scale;
+              c1 = load_attr(P.rgb, P.dtype, 3 * k + 1) * P.c_scale;
+              c2 = load_attr(P.rgb, P.dtype, 3 * k + 2) * P.c_scale;
+              colour_ok = finitef(c0) && finitef(c1) && finitef(c2);
+            } else if (L.M == 1) {
               c0 = L.rgb[0];
               c1 = L.rgb[1];
               c2 = L.rgb[2];
             } else {
+              float t;
+              if (L.log10)
+                t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
+              else
+                t = (s - L.lo) * L.inv_range;
+              t = fminf(fmaxf(t, 0.0f), 1.0f);
               const float u = t * (float)(L.M - 1);
               int j = (int)floorf(u);
               j = min(max(j, 0), L.M - 2);
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
             const float bi = L.beta * I;
             const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
             const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
-            if (emits || (P.mode == SPL_SORTED && a > 0.0f)) {
+            if (colour_ok && (emits || (P.mode == SPL_SORTED && a > 0.0f))) {
               // peak amplitude 1/(pi sigma^2) in single precision from the
               // stored sigma
               const float sg = (float)sig;

@@ -49,6 +49,9 @@ constexpr int kLargeTile = 64;     // px, tiles of the large-particle path
 constexpr int kDefaultTile = 16;
 constexpr double kDefaultCut = 32.0;  // px
 constexpr int kFinBlocks = 1024;
+// FP64 statistics per view: [0..2] flux, [3..5] max, [6] overall max,
+// [7..9] flux before the map, [10..12] expected flux
+constexpr int kStatWords = 16;
 
 struct DevBuf {
   void *p = nullptr;
@@ -75,15 +78,28 @@ struct TimedFrame {
 
 }  // namespace
 
+// A resident particle set: one device allocation holding every array.
+struct spl_dataset {
+  int device = 0;
+  spl_particles view{};  // device pointers into mem, stored dtype and scales
+  void *mem = nullptr;
+  size_t bytes = 0;
+};
+
 struct spl_ctx {
   int device = 0;
   std::string err;
   DevBuf rec, rec2, span, counts, offsets, cursor, item_off, items[3], pairs, keysA, keysB,
-      partial, fin, stats, totals, minmax;
+      partial, fin, stats, totals, minmax, himg, chunk[2];
+  hipStream_t copy_stream = nullptr;  // host-to-device copies of spl_render_stream
+  hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   Totals *h_tot = nullptr;
   double *h_stats = nullptr;
   int64_t bytes = 0;
-  std::map<std::tuple<int64_t, int, int, int>, std::pair<int, double>> tune;
+  // autotuner choices: per (n, W, H, mode, camera pose), and the most
+  // recent choice per (n, W, H, mode) for poses that were not tuned
+  std::map<std::tuple<int64_t, int, int, int, uint64_t>, std::pair<int, double>> tune;
+  std::map<std::tuple<int64_t, int, int, int>, std::pair<int, double>> tune_any;
   // stage timers
   bool timing = false;
   std::vector<hipEvent_t> event_pool;
@@ -237,12 +253,15 @@ spl_status check_params(spl_ctx *c, const spl_params *p, bool need_looks) {
     return fail(c, SPL_EINVAL, "n_species %d outside 1..%d", p->n_species, SPL_MAX_SPECIES);
   for (int k = 0; k < p->n_species; ++k) {
     const spl_look &l = p->looks[k];
+    if (l.vector_colour != 0 && l.vector_colour != 1)
+      return fail(c, SPL_EINVAL, "species %d: vector_colour must be 0 or 1", k);
+    if (!std::isfinite(l.brightness)) return fail(c, SPL_EINVAL, "species %d: brightness", k);
+    if (l.vector_colour) continue;  // the palette fields are not read
     if (!l.rgb) return fail(c, SPL_EINVAL, "palette of species %d is NULL", k);
     if (l.n_entries < 1 || l.n_entries > 4096)
       return fail(c, SPL_EINVAL, "palette of species %d has %d entries", k, l.n_entries);
     if (!std::isfinite(l.lo) || !std::isfinite(l.hi) || !(l.hi >= l.lo))
       return fail(c, SPL_EINVAL, "species %d: need finite lo <= hi", k);
-    if (!std::isfinite(l.brightness)) return fail(c, SPL_EINVAL, "species %d: brightness", k);
   }
   return SPL_OK;
 }
@@ -261,6 +280,17 @@ spl_status check_particles(spl_ctx *c, const spl_particles *p, int mode) {
     return fail(c, SPL_EINVAL, "h_scale, i_scale and s_scale must be finite and > 0");
   if (mode == SPL_SORTED && !p->absorption)
     return fail(c, SPL_EINVAL, "sorted mode needs absorption");
+  if (p->rgb && (!(p->c_scale > 0.0f) || !std::isfinite(p->c_scale)))
+    return fail(c, SPL_EINVAL, "c_scale must be finite and > 0");
+  return SPL_OK;
+}
+
+// A species coloured from the vector field needs the particles' rgb array.
+spl_status check_colour(spl_ctx *c, const spl_particles *p, const spl_params *prm) {
+  if (p->n == 0) return SPL_OK;
+  for (int k = 0; k < prm->n_species; ++k)
+    if (prm->looks[k].vector_colour && !p->rgb)
+      return fail(c, SPL_EINVAL, "species %d colours from the vector field but rgb is NULL", k);
   return SPL_OK;
 }
 
@@ -277,6 +307,7 @@ void fill_proj(ProjK &pk, const spl_particles *p, const spl_params *prm) {
       L.rgb = l.rgb;
       L.M = l.n_entries;
       L.log10 = l.log10_scalar ? 1 : 0;
+      L.vec = l.vector_colour ? 1 : 0;
       L.beta = (float)l.brightness;
       L.lo = (float)l.lo;
       L.inv_range = (l.hi > l.lo) ? (float)(1.0 / (l.hi - l.lo)) : 0.0f;
@@ -296,6 +327,8 @@ void fill_proj(ProjK &pk, const spl_particles *p, const spl_params *prm) {
   pk.s_scale = p->s_scale;
   pk.species = p->species;
   pk.absorb = p->absorption;
+  pk.rgb = p->rgb;
+  pk.c_scale = p->rgb ? p->c_scale : 1.0f;
   pk.n = p->n;
 }
 
@@ -318,15 +351,46 @@ void fill_tiles(TileK &tk, int W, int H, int tile, double nu, double cut, int bi
 
 // Tile size and large cut for a view: explicit parameters win, then the
 // autotuner's cached choice, then the defaults.
-void choose(spl_ctx *c, int64_t n, int W, int H, const spl_params *prm, int &tile, double &cut) {
+// FNV-1a digest of a camera pose (position, look-at, up, field of view,
+// near plane): the autotuner's choice depends on the radii the pose projects.
+uint64_t pose_digest(const spl_camera *cam) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void *p, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(cam->eye, sizeof(cam->eye));
+  mix(cam->lookat, sizeof(cam->lookat));
+  mix(cam->up, sizeof(cam->up));
+  mix(&cam->fov_y_deg, sizeof(double));
+  mix(&cam->z_near, sizeof(double));
+  return h;
+}
+
+// Tile size and large cut for a view: explicit parameters win, then the
+// autotuner's choice for this pose, then its latest choice for the image
+// size, then the defaults.
+void choose(spl_ctx *c, int64_t n, const spl_camera *cam, const spl_params *prm, int &tile,
+            double &cut) {
   tile = prm->tile;
   cut = prm->large_cut;
-  auto it = c->tune.find(std::make_tuple(n, W, H, prm->mode));
-  if (tile == 0) tile = (it != c->tune.end()) ? it->second.first : kDefaultTile;
+  const int W = cam->width, H = cam->height;
+  const std::pair<int, double> *t = nullptr;
+  auto it = c->tune.find(std::make_tuple(n, W, H, prm->mode, pose_digest(cam)));
+  if (it != c->tune.end()) {
+    t = &it->second;
+  } else {
+    auto ia = c->tune_any.find(std::make_tuple(n, W, H, prm->mode));
+    if (ia != c->tune_any.end()) t = &ia->second;
+  }
+  if (tile == 0) tile = t ? t->first : kDefaultTile;
   if (prm->mode == SPL_SORTED || cut < 0.0)
     cut = INFINITY;
   else if (cut == 0.0)
-    cut = (it != c->tune.end()) ? it->second.second : kDefaultCut;
+    cut = t ? t->second : kDefaultCut;
 }
 
 struct Frame {
@@ -339,6 +403,9 @@ struct Frame {
   double out_bytes_per_active;   // bytes it writes per active particle
   bool counted;                  // the first stage already produced the tile counts
   TimedFrame *tf;                // NULL unless timing
+  bool flux_check = false;       // expected flux of the records (additive modes)
+  bool clear = true;             // zero the image first (else add into it)
+  bool finish = true;            // final map, FP64 reductions, normalisation
 };
 
 // ---- stage timers ---------------------------------------------------------
@@ -389,6 +456,17 @@ void resolve_timing(spl_ctx *c, bool wait) {
     for (hipEvent_t e : tf.ev) c->event_pool.push_back(e);
   }
   c->pending.swap(keep);
+}
+
+// The end of a frame: the absorption = emission map (additive J before it),
+// FP64 flux and maximum per channel, optional division by the maximum.
+spl_status finish_image(spl_ctx *c, float *img, int64_t npx, int mode, int normalise,
+                        hipStream_t s) {
+  const int fb = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
+  HIPTRY(c, launch_finalise(img, npx, mode == SPL_ADD_AEQE, (double *)c->fin.p, fb, s));
+  HIPTRY(c, launch_reduce_stats((const double *)c->fin.p, fb, (double *)c->stats.p, s));
+  if (normalise) HIPTRY(c, launch_normalise(img, npx, (const double *)c->stats.p, s));
+  return SPL_OK;
 }
 
 // Everything after the per-particle spans exist (ws span, totals n_active /
@@ -444,7 +522,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   int passes = 0;
   if (!sorted) {
     mark(tf, 6, s);
-    HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
+    if (f.clear) HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
     const int nfi = (int)T.n_fine_items[0];
     const int nci = (int)(T.n_items[0] - T.n_fine_items[0]);
     HIPTRY(c, launch_splat_large(items0 + nfi, nci, (const uint32_t *)c->pairs.p, f.rec, counts,
@@ -472,10 +550,10 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
                                      (const float *)c->partial.p, f.out, s));
     mark(tf, 8, s);
   }
-  const int fb = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
-  HIPTRY(c, launch_finalise(f.out, npx, f.mode == SPL_ADD_AEQE, (double *)c->fin.p, fb, s));
-  HIPTRY(c, launch_reduce_stats((const double *)c->fin.p, fb, (double *)c->stats.p, s));
-  if (f.normalise) HIPTRY(c, launch_normalise(f.out, npx, (const double *)c->stats.p, s));
+  if (f.finish) TRY(finish_image(c, f.out, npx, f.mode, f.normalise, s));
+  if (f.flux_check)
+    HIPTRY(c, launch_expected_flux(f.rec, span, f.n, tk.W, tk.H, tk.nu, (double *)c->fin.p,
+                                   kFinBlocks, (double *)c->stats.p + 10, s));
   mark(tf, 9, s);
   if (tf) {
     // algorithmic bytes: every array a stage must touch, once
@@ -503,8 +581,11 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     c->pending.push_back(*tf);
   }
   if (st) {
-    HIPTRY(c, hipMemcpyAsync(c->h_stats, c->stats.p, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPTRY(c, hipStreamSynchronize(s));
+    if (f.finish || f.flux_check) {
+      HIPTRY(c, hipMemcpyAsync(c->h_stats, c->stats.p, kStatWords * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+      HIPTRY(c, hipStreamSynchronize(s));
+    }
     st->n_active = (int64_t)T.n_active;
     st->n_large = (int64_t)T.n_large;
     st->n_pairs = (int64_t)T.n_fine_pairs;
@@ -513,6 +594,8 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     for (int q = 0; q < 3; ++q) {
       st->flux[q] = c->h_stats[q];
       st->max[q] = c->h_stats[3 + q];
+      st->raw_flux[q] = sorted ? NAN : c->h_stats[7 + q];
+      st->expected_flux[q] = f.flux_check ? c->h_stats[10 + q] : NAN;
     }
     st->tile = tk.tile;
     st->large_cut = std::isfinite(tk.large_cut) ? (double)tk.large_cut : -1.0;
@@ -538,24 +621,26 @@ spl_status prepare_common(spl_ctx *c, int64_t n, const TileK &tk, hipStream_t s)
   TRY(ensure(c, c->cursor, (size_t)nb * 4));
   TRY(ensure(c, c->item_off, (size_t)3 * (nb + 1) * 4));
   TRY(ensure(c, c->totals, sizeof(Totals)));
-  TRY(ensure(c, c->fin, (size_t)kFinBlocks * 6 * 8));
-  TRY(ensure(c, c->stats, 8 * 8));
+  TRY(ensure(c, c->fin, (size_t)kFinBlocks * kStatPartials * 8));
+  TRY(ensure(c, c->stats, kStatWords * 8));
   HIPTRY(c, launch_fill_u32((uint32_t *)c->counts.p, 0u, nb, s));
   HIPTRY(c, launch_fill_u32((uint32_t *)c->totals.p, 0u, sizeof(Totals) / 4, s));
   return SPL_OK;
 }
 
 spl_status render_one(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
-                      const spl_params *prm, float *out, spl_stats *st, hipStream_t s) {
+                      const spl_params *prm, float *out, spl_stats *st, hipStream_t s,
+                      bool clear = true, bool finish = true) {
   ProjK pk;
   TRY(check_params(c, prm, true));
   TRY(check_particles(c, p, prm->mode));
+  TRY(check_colour(c, p, prm));
   TRY(camera_frame(c, cam, pk));
   if (!out) return fail(c, SPL_EINVAL, "output image is NULL");
   fill_proj(pk, p, prm);
   int tile;
   double cut;
-  choose(c, p->n, cam->width, cam->height, prm, tile, cut);
+  choose(c, p->n, cam, prm, tile, cut);
   TileK tk;
   fill_tiles(tk, cam->width, cam->height, tile, prm->nu, cut, prm->bin_rule);
   const bool sorted = prm->mode == SPL_SORTED;
@@ -574,6 +659,9 @@ spl_status render_one(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
           prm->mode, prm->normalise, out,
           12.0 + 3.0 * attr + (p->species ? 1.0 : 0.0) + (sorted ? 4.0 : 0.0),
           32.0 + (sorted ? 8.0 : 0.0), project_counts(tk), nullptr};
+  f.clear = clear;
+  f.finish = finish;
+  f.flux_check = prm->flux_check != 0 && !sorted;
   return render_timed(c, f, tf, st, s);
 }
 
@@ -594,7 +682,8 @@ spl_status ensure_host(spl_ctx *c, int views) {
   if (hipHostMalloc((void **)&c->h_btot, sizeof(Totals) * views, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_views, sizeof(ViewK) * views, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctr, 2 * sizeof(uint32_t) * views, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_bstats, 8 * sizeof(double) * views, hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc((void **)&c->h_bstats, kStatWords * sizeof(double) * views,
+                    hipHostMallocDefault) != hipSuccess)
     return fail(c, SPL_ENOMEM, "pinned host allocation failed");
   c->h_cap = views;
   return SPL_OK;
@@ -621,8 +710,8 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   TRY(ensure(c, c->b_totals, (size_t)nv * sizeof(Totals)));
   TRY(ensure(c, c->b_views, (size_t)nv * sizeof(ViewK)));
   TRY(ensure(c, c->b_ctr, 4 * sizeof(uint32_t)));
-  TRY(ensure(c, c->b_fin, (size_t)nv * kFinBlocks * 6 * 8));
-  TRY(ensure(c, c->b_stats, (size_t)nv * 8 * 8));
+  TRY(ensure(c, c->b_fin, (size_t)nv * kFinBlocks * kStatPartials * 8));
+  TRY(ensure(c, c->b_stats, (size_t)nv * kStatWords * 8));
   float *rec = (float *)c->b_rec.p;
   uint2 *span = (uint2 *)c->b_span.p;
   uint32_t *counts = (uint32_t *)c->b_counts.p, *offsets = (uint32_t *)c->b_offsets.p;
@@ -757,9 +846,16 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
         const int64_t npx = (int64_t)tk[v].W * tk[v].H;
         const int fbk = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
         HIPTRY(c, launch_finalise(outs[v], npx, prm[v]->mode == SPL_ADD_AEQE,
-                                  fin + (size_t)v * kFinBlocks * 6, fbk, q));
-        HIPTRY(c, launch_reduce_stats(fin + (size_t)v * kFinBlocks * 6, fbk, stats + 8 * v, q));
-        if (prm[v]->normalise) HIPTRY(c, launch_normalise(outs[v], npx, stats + 8 * v, q));
+                                  fin + (size_t)v * kFinBlocks * kStatPartials, fbk, q));
+        HIPTRY(c, launch_reduce_stats(fin + (size_t)v * kFinBlocks * kStatPartials, fbk,
+                                      stats + kStatWords * v, q));
+        if (prm[v]->normalise)
+          HIPTRY(c, launch_normalise(outs[v], npx, stats + kStatWords * v, q));
+        if (prm[v]->flux_check)
+          HIPTRY(c, launch_expected_flux(rec + (size_t)v * n * 8, span + (size_t)v * n, n,
+                                         tk[v].W, tk[v].H, tk[v].nu,
+                                         fin + (size_t)v * kFinBlocks * kStatPartials, kFinBlocks,
+                                         stats + kStatWords * v + 10, q));
       }
     }
     mark(tf, 9, q);
@@ -822,7 +918,8 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   bool any_stats = false;
   for (int v = 0; v < nv; ++v) any_stats = any_stats || st[v];
   if (any_stats) {
-    HIPTRY(c, hipMemcpyAsync(c->h_bstats, stats, 8 * sizeof(double) * nv, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipMemcpyAsync(c->h_bstats, stats, kStatWords * sizeof(double) * nv,
+                             hipMemcpyDeviceToHost, s));
     HIPTRY(c, hipStreamSynchronize(s));
     for (int v = 0; v < nv; ++v) {
       if (!st[v]) continue;
@@ -833,8 +930,11 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       st[v]->n_large_pairs = (int64_t)(T.n_pairs - T.n_fine_pairs);
       st[v]->n_items = (int64_t)T.n_items[ks];
       for (int q = 0; q < 3; ++q) {
-        st[v]->flux[q] = c->h_bstats[8 * v + q];
-        st[v]->max[q] = c->h_bstats[8 * v + 3 + q];
+        const double *hs = c->h_bstats + kStatWords * v;
+        st[v]->flux[q] = hs[q];
+        st[v]->max[q] = hs[3 + q];
+        st[v]->raw_flux[q] = hs[7 + q];
+        st[v]->expected_flux[q] = prm[v]->flux_check ? hs[10 + q] : NAN;
       }
       st[v]->tile = tk[v].tile;
       st[v]->large_cut = std::isfinite(tk[v].large_cut) ? (double)tk[v].large_cut : -1.0;
@@ -857,6 +957,7 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
   for (int v = 0; v < nv; ++v) {
     ProjK k;
     TRY(check_params(c, &prms[v], true));
+    TRY(check_colour(c, p, &prms[v]));
     TRY(camera_frame(c, &cams[v], k));
     if (!outs[v]) return fail(c, SPL_EINVAL, "output image %d is NULL", v);
     any_sorted = any_sorted || prms[v].mode == SPL_SORTED;
@@ -873,7 +974,7 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
     fill_proj(k, p, &prms[v]);
     int tile;
     double cut;
-    choose(c, p->n, cams[v].width, cams[v].height, &prms[v], tile, cut);
+    choose(c, p->n, &cams[v], &prms[v], tile, cut);
     TileK t;
     fill_tiles(t, cams[v].width, cams[v].height, tile, prms[v].nu, cut, prms[v].bin_rule);
     pk.push_back(k);
@@ -918,6 +1019,344 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
   return SPL_OK;
 }
 
+// ---- resident data sets ----------------------------------------------------
+
+size_t attr_bytes(int dtype) { return dtype == SPL_F32 ? 4 : 2; }
+size_t round256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+hipError_t copy_in(void *dst, const void *src, size_t bytes, int on_device, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  return hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        s);
+}
+
+// One attribute array (count values) into the stored type; returns the scale
+// of the stored values in *scale_out.
+spl_status convert_attr(spl_ctx *c, const void *src, int sdtype, float sscale, int64_t count,
+                        int on_device, void *stage, void *dst, int store, float *scale_out,
+                        hipStream_t s) {
+  const void *from = src;
+  if (!on_device) {
+    HIPTRY(c, copy_in(stage, src, (size_t)count * attr_bytes(sdtype), 0, s));
+    from = stage;
+  }
+  double scale = 1.0;
+  if (store == SPL_F16) {
+    // the power of two that puts the largest finite magnitude in [2^10, 2^11)
+    uint32_t *bits = (uint32_t *)c->minmax.p;
+    HIPTRY(c, launch_fill_u32(bits, 0u, 1, s));
+    HIPTRY(c, launch_absmax(from, sdtype, sscale, count, bits, s));
+    uint32_t hb = 0;
+    HIPTRY(c, hipMemcpyAsync(&hb, bits, 4, hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    float m;
+    std::memcpy(&m, &hb, 4);
+    if (m > 0.0f) scale = std::ldexp(1.0, (int)std::floor(std::log2((double)m / 1024.0)));
+  }
+  HIPTRY(c, launch_convert(from, sdtype, sscale, dst, store, (float)(1.0 / scale), count, s));
+  *scale_out = (float)scale;
+  return SPL_OK;
+}
+
+spl_status dataset_upload(spl_ctx *c, const spl_particles *src, int on_device, int store,
+                          spl_dataset **out, hipStream_t s) {
+  if (!out) return fail(c, SPL_EINVAL, "out is NULL");
+  TRY(check_particles(c, src, SPL_ADD_RAW));
+  if (store < SPL_F32 || store > SPL_F16)
+    return fail(c, SPL_EINVAL, "unknown store_dtype %d", store);
+  const int64_t n = src->n;
+  const size_t sa = attr_bytes(store), ssrc = attr_bytes(src->attr_dtype);
+  // layout of the one allocation
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += round256(bytes);
+    return o;
+  };
+  const size_t ox = take(4 * n), oy = take(4 * n), oz = take(4 * n);
+  const size_t oh = take(sa * n), oi = take(sa * n), os = take(sa * n);
+  const size_t osp = src->species ? take(n) : 0;
+  const size_t oab = src->absorption ? take(4 * n) : 0;
+  const size_t orgb = src->rgb ? take(3 * sa * n) : 0;
+  spl_dataset *ds = new (std::nothrow) spl_dataset();
+  if (!ds) return fail(c, SPL_ENOMEM, "host allocation failed");
+  if (hipMalloc(&ds->mem, off ? off : 256) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ds;
+    return fail(c, SPL_ENOMEM, "device allocation of %zu bytes for the data set failed", off);
+  }
+  ds->bytes = off;
+  ds->device = c->device;
+  char *m = (char *)ds->mem;
+  void *stage = nullptr;
+  spl_status rc = SPL_OK;
+  auto cleanup = [&](spl_status r) {
+    if (stage) (void)hipFree(stage);
+    if (r != SPL_OK) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(ds->mem);
+      delete ds;
+    }
+    return r;
+  };
+  if (n > 0) {
+    if (!on_device &&
+        hipMalloc(&stage, (size_t)n * ssrc * (src->rgb ? 3 : 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      stage = nullptr;
+      return cleanup(fail(c, SPL_ENOMEM, "device staging allocation failed"));
+    }
+    if ((rc = ensure(c, c->minmax, 4 * SPL_MAX_SPECIES * 8)) != SPL_OK) return cleanup(rc);
+    const hipError_t e0 = copy_in(m + ox, src->x, 4 * n, on_device, s);
+    const hipError_t e1 = e0 == hipSuccess ? copy_in(m + oy, src->y, 4 * n, on_device, s) : e0;
+    const hipError_t e2 = e1 == hipSuccess ? copy_in(m + oz, src->z, 4 * n, on_device, s) : e1;
+    const hipError_t e3 = (e2 == hipSuccess && src->species) ? copy_in(m + osp, src->species, n, on_device, s) : e2;
+    const hipError_t e4 = (e3 == hipSuccess && src->absorption)
+                              ? copy_in(m + oab, src->absorption, 4 * n, on_device, s)
+                              : e3;
+    if (e4 != hipSuccess)
+      return cleanup(fail(c, SPL_EDEVICE, "data set copy failed: %s", hipGetErrorString(e4)));
+    float sc = 1.0f;
+    if ((rc = convert_attr(c, src->h, src->attr_dtype, src->h_scale, n, on_device, stage, m + oh,
+                           store, &sc, s)) != SPL_OK)
+      return cleanup(rc);
+    ds->view.h_scale = sc;
+    if ((rc = convert_attr(c, src->intensity, src->attr_dtype, src->i_scale, n, on_device, stage,
+                           m + oi, store, &sc, s)) != SPL_OK)
+      return cleanup(rc);
+    ds->view.i_scale = sc;
+    if ((rc = convert_attr(c, src->scalar, src->attr_dtype, src->s_scale, n, on_device, stage,
+                           m + os, store, &sc, s)) != SPL_OK)
+      return cleanup(rc);
+    ds->view.s_scale = sc;
+    ds->view.c_scale = 1.0f;
+    if (src->rgb) {
+      if ((rc = convert_attr(c, src->rgb, src->attr_dtype, src->c_scale, 3 * n, on_device, stage,
+                             m + orgb, store, &sc, s)) != SPL_OK)
+        return cleanup(rc);
+      ds->view.c_scale = sc;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return cleanup(fail(c, SPL_EDEVICE, "data set upload failed"));
+  } else {
+    ds->view.h_scale = ds->view.i_scale = ds->view.s_scale = ds->view.c_scale = 1.0f;
+  }
+  spl_particles &v = ds->view;
+  v.n = n;
+  v.x = (const float *)(m + ox);
+  v.y = (const float *)(m + oy);
+  v.z = (const float *)(m + oz);
+  v.h = m + oh;
+  v.intensity = m + oi;
+  v.scalar = m + os;
+  v.attr_dtype = store;
+  v.species = src->species ? (const uint8_t *)(m + osp) : nullptr;
+  v.absorption = src->absorption ? (const float *)(m + oab) : nullptr;
+  v.rgb = src->rgb ? (const void *)(m + orgb) : nullptr;
+  *out = ds;
+  return cleanup(SPL_OK);
+}
+
+spl_status check_dataset(spl_ctx *c, const spl_dataset *ds) {
+  if (!ds) return fail(c, SPL_EINVAL, "data set is NULL");
+  if (ds->device != c->device)
+    return fail(c, SPL_EINVAL, "data set lives on device %d, the context on %d", ds->device,
+                c->device);
+  return SPL_OK;
+}
+
+// A frame into a host image: rendered into the context's device image, then
+// copied back (Sect. 3.1: the image goes back to the host at the end).
+spl_status render_out(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
+                      const spl_params *prm, float *out, int out_on_device, spl_stats *st,
+                      hipStream_t s) {
+  if (out_on_device) return render_one(c, p, cam, prm, out, st, s);
+  if (!out) return fail(c, SPL_EINVAL, "output image is NULL");
+  if (!cam || cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
+    return fail(c, SPL_EINVAL, "bad camera or image size");
+  const size_t bytes = (size_t)cam->width * cam->height * 12;
+  TRY(ensure(c, c->himg, bytes));
+  TRY(render_one(c, p, cam, prm, (float *)c->himg.p, st, s));
+  HIPTRY(c, hipMemcpyAsync(out, c->himg.p, bytes, hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  return SPL_OK;
+}
+
+spl_status render_batch_out(spl_ctx *c, const spl_particles *p, int nv, const spl_camera *cams,
+                            const spl_params *prms, float *const *outs, int out_on_device,
+                            spl_stats *st, hipStream_t s) {
+  if (out_on_device) return render_batch(c, p, nv, cams, prms, outs, st, s);
+  size_t total = 0;
+  for (int v = 0; v < nv; ++v) {
+    if (!outs[v]) return fail(c, SPL_EINVAL, "output image %d is NULL", v);
+    if (cams[v].width < 1 || cams[v].height < 1 || cams[v].width > 32768 ||
+        cams[v].height > 32768)
+      return fail(c, SPL_EINVAL, "view %d: image size %dx%d outside 1..32768", v, cams[v].width,
+                  cams[v].height);
+    total += round256((size_t)cams[v].width * cams[v].height * 12);
+  }
+  TRY(ensure(c, c->himg, total));
+  std::vector<float *> dev(nv);
+  size_t off = 0;
+  for (int v = 0; v < nv; ++v) {
+    dev[v] = (float *)((char *)c->himg.p + off);
+    off += round256((size_t)cams[v].width * cams[v].height * 12);
+  }
+  TRY(render_batch(c, p, nv, cams, prms, dev.data(), st, s));
+  for (int v = 0; v < nv; ++v)
+    HIPTRY(c, hipMemcpyAsync(outs[v], dev[v], (size_t)cams[v].width * cams[v].height * 12,
+                             hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  return SPL_OK;
+}
+
+// ---- out-of-core rendering --------------------------------------------------
+
+// Chunk k of the host arrays into device buffer b (one allocation per buffer:
+// positions, attributes, species, colour vectors), on the copy stream, after
+// the render that last read the buffer.
+spl_status stream_copy(spl_ctx *c, const spl_particles *hp, int64_t chunk, int64_t k,
+                       spl_particles *views) {
+  const int b = (int)(k & 1);
+  const int64_t first = k * chunk, m = std::min<int64_t>(chunk, hp->n - first);
+  const size_t sa = attr_bytes(hp->attr_dtype);
+  char *base = (char *)c->chunk[b].p;
+  size_t off = 0;
+  auto take = [&](size_t per) {
+    char *p = base + off;
+    off += round256(per * (size_t)chunk);
+    return p;
+  };
+  spl_particles &v = views[b];
+  v = *hp;
+  v.n = m;
+  float *x = (float *)take(4), *y = (float *)take(4), *z = (float *)take(4);
+  void *h = take(sa), *in = take(sa), *sc = take(sa);
+  uint8_t *sp = hp->species ? (uint8_t *)take(1) : nullptr;
+  void *rgb = hp->rgb ? take(3 * sa) : nullptr;
+  hipStream_t q = c->copy_stream;
+  if (k >= 2) HIPTRY(c, hipStreamWaitEvent(q, c->ev_done[b], 0));
+  HIPTRY(c, copy_in(x, hp->x + first, 4 * m, 0, q));
+  HIPTRY(c, copy_in(y, hp->y + first, 4 * m, 0, q));
+  HIPTRY(c, copy_in(z, hp->z + first, 4 * m, 0, q));
+  HIPTRY(c, copy_in(h, (const char *)hp->h + sa * first, sa * m, 0, q));
+  HIPTRY(c, copy_in(in, (const char *)hp->intensity + sa * first, sa * m, 0, q));
+  HIPTRY(c, copy_in(sc, (const char *)hp->scalar + sa * first, sa * m, 0, q));
+  if (sp) HIPTRY(c, copy_in(sp, hp->species + first, m, 0, q));
+  if (rgb) HIPTRY(c, copy_in(rgb, (const char *)hp->rgb + 3 * sa * first, 3 * sa * m, 0, q));
+  HIPTRY(c, hipEventRecord(c->ev_copied[b], q));
+  v.x = x;
+  v.y = y;
+  v.z = z;
+  v.h = h;
+  v.intensity = in;
+  v.scalar = sc;
+  v.species = sp;
+  v.rgb = rgb;
+  v.absorption = nullptr;
+  return SPL_OK;
+}
+
+spl_status render_stream(spl_ctx *c, const spl_particles *hp, int64_t chunk,
+                         const spl_camera *cam, const spl_params *prm, float *img,
+                         spl_stats *st, hipStream_t s) {
+  TRY(check_params(c, prm, true));
+  if (prm->mode == SPL_SORTED)
+    return fail(c, SPL_EUNSUPPORTED, "out-of-core rendering is additive only (depth order "
+                                     "spans chunks)");
+  TRY(check_particles(c, hp, prm->mode));
+  TRY(check_colour(c, hp, prm));
+  ProjK pk;
+  TRY(camera_frame(c, cam, pk));
+  if (!img) return fail(c, SPL_EINVAL, "output image is NULL");
+  if (chunk < 1) return fail(c, SPL_EINVAL, "chunk must be >= 1");
+  chunk = std::min<int64_t>(chunk, std::max<int64_t>(hp->n, 1));
+  if (!c->copy_stream) HIPTRY(c, hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+  for (int b = 0; b < 2; ++b) {
+    if (!c->ev_copied[b])
+      HIPTRY(c, hipEventCreateWithFlags(&c->ev_copied[b], hipEventDisableTiming));
+    if (!c->ev_done[b]) HIPTRY(c, hipEventCreateWithFlags(&c->ev_done[b], hipEventDisableTiming));
+  }
+  const size_t sa = attr_bytes(hp->attr_dtype);
+  const size_t per = round256(4 * chunk) * 3 + round256(sa * chunk) * 3 +
+                     (hp->species ? round256(chunk) : 0) + (hp->rgb ? round256(3 * sa * chunk) : 0);
+  TRY(ensure(c, c->chunk[0], per));
+  TRY(ensure(c, c->chunk[1], per));
+  TRY(ensure(c, c->fin, (size_t)kFinBlocks * kStatPartials * 8));  // an empty set renders no
+  TRY(ensure(c, c->stats, kStatWords * 8));                          // chunk but is finished
+  // the chunk frames: the transfer sum J added into the image, no map
+  spl_params q = *prm;
+  q.mode = SPL_ADD_RAW;
+  q.normalise = 0;
+  // the tile size and cut the whole set would get
+  int tile;
+  double cut;
+  choose(c, hp->n, cam, prm, tile, cut);
+  q.tile = tile;
+  q.large_cut = std::isfinite(cut) ? cut : -1.0;
+  const int64_t npx = (int64_t)cam->width * cam->height;
+  const int64_t nchunks = (hp->n + chunk - 1) / chunk;
+  HIPTRY(c, launch_fill_f32(img, 0.0f, 3 * npx, s));
+  const bool timing = c->timing;
+  c->timing = false;  // per-chunk stage timers would count chunks as frames
+  spl_particles views[2];
+  spl_stats acc{};
+  spl_status rc = SPL_OK;
+  double expected[3] = {0.0, 0.0, 0.0};
+  // the copy stream may start once the image clear and earlier work on the
+  // caller's stream are ordered before it
+  hipEvent_t start = c->ev_done[1];
+  HIPTRY(c, hipEventRecord(start, s));
+  HIPTRY(c, hipStreamWaitEvent(c->copy_stream, start, 0));
+  if (nchunks > 0) rc = stream_copy(c, hp, chunk, 0, views);
+  for (int64_t k = 0; k < nchunks && rc == SPL_OK; ++k) {
+    const int b = (int)(k & 1);
+    if (k + 1 < nchunks && (rc = stream_copy(c, hp, chunk, k + 1, views)) != SPL_OK) break;
+    if (hipStreamWaitEvent(s, c->ev_copied[b], 0) != hipSuccess) {
+      rc = fail(c, SPL_EDEVICE, "stream wait failed");
+      break;
+    }
+    spl_stats cs{};
+    rc = render_one(c, &views[b], cam, &q, img, &cs, s, false, false);
+    if (rc != SPL_OK) break;
+    if (hipEventRecord(c->ev_done[b], s) != hipSuccess) {
+      rc = fail(c, SPL_EDEVICE, "event record failed");
+      break;
+    }
+    acc.n_active += cs.n_active;
+    acc.n_large += cs.n_large;
+    acc.n_pairs += cs.n_pairs;
+    acc.n_large_pairs += cs.n_large_pairs;
+    acc.n_items += cs.n_items;
+    for (int ch = 0; ch < 3; ++ch) expected[ch] += cs.expected_flux[ch];
+  }
+  c->timing = timing;
+  if (rc != SPL_OK) {
+    (void)hipStreamSynchronize(c->copy_stream);
+    return rc;
+  }
+  HIPTRY(c, hipStreamSynchronize(c->copy_stream));
+  // the map, the FP64 reductions and the normalisation, once, on the sum
+  TRY(finish_image(c, img, npx, prm->mode, prm->normalise, s));
+  if (st) {
+    HIPTRY(c, hipMemcpyAsync(c->h_stats, c->stats.p, kStatWords * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    *st = acc;
+    for (int ch = 0; ch < 3; ++ch) {
+      st->flux[ch] = c->h_stats[ch];
+      st->max[ch] = c->h_stats[3 + ch];
+      st->raw_flux[ch] = c->h_stats[7 + ch];
+      st->expected_flux[ch] = prm->flux_check ? expected[ch] : NAN;
+    }
+    st->tile = tile;
+    st->large_cut = std::isfinite(cut) ? cut : -1.0;
+  } else {
+    HIPTRY(c, hipStreamSynchronize(s));
+  }
+  return SPL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -957,7 +1396,8 @@ spl_status spl_create(int device, spl_ctx **out) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->n_cu = ncu;
   if (hipHostMalloc((void **)&c->h_tot, sizeof(Totals), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void **)&c->h_stats, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      hipHostMalloc((void **)&c->h_stats, kStatWords * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess) {
     if (c->h_tot) (void)hipHostFree(c->h_tot);
     delete c;
     return SPL_ENOMEM;
@@ -966,16 +1406,38 @@ spl_status spl_create(int device, spl_ctx **out) {
   return SPL_OK;
 }
 
+// Every workspace buffer of the context, for release.
+#define SPL_WORKSPACE_BUFFERS(c)                                                            \
+  {&c->rec, &c->rec2, &c->span, &c->counts, &c->offsets, &c->cursor, &c->item_off,          \
+   &c->items[0], &c->items[1], &c->items[2], &c->pairs, &c->keysA, &c->keysB, &c->partial,  \
+   &c->fin, &c->stats, &c->totals, &c->minmax, &c->b_rec, &c->b_span, &c->b_counts,          \
+   &c->b_offsets, &c->b_cursor, &c->b_itemoff, &c->b_totals, &c->b_pairs, &c->b_itf,        \
+   &c->b_itc, &c->b_views, &c->b_ctr, &c->b_fin, &c->b_stats, &c->himg, &c->chunk[0],        \
+   &c->chunk[1]}
+
+spl_status spl_trim(spl_ctx *c) {
+  if (!c) return SPL_EINVAL;
+  HIPTRY(c, hipSetDevice(c->device));
+  HIPTRY(c, hipDeviceSynchronize());  // no frame may still use the buffers
+  DevBuf *bufs[] = SPL_WORKSPACE_BUFFERS(c);
+  for (DevBuf *b : bufs) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->cap = 0;
+  }
+  c->bytes = 0;
+  if (c->gexec) {  // the replayable graph points into the freed buffers
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  return SPL_OK;
+}
+
 void spl_destroy(spl_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  DevBuf *bufs[] = {&c->rec, &c->rec2, &c->span, &c->counts, &c->offsets, &c->cursor,
-                    &c->item_off, &c->items[0], &c->items[1], &c->items[2], &c->pairs,
-                    &c->keysA, &c->keysB, &c->partial, &c->fin, &c->stats, &c->totals,
-                    &c->minmax, &c->b_rec, &c->b_span, &c->b_counts, &c->b_offsets,
-                    &c->b_cursor, &c->b_itemoff, &c->b_totals, &c->b_pairs, &c->b_itf,
-                    &c->b_itc, &c->b_views, &c->b_ctr, &c->b_fin, &c->b_stats};
+  DevBuf *bufs[] = SPL_WORKSPACE_BUFFERS(c);
   for (DevBuf *b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (TimedFrame &tf : c->pending)
@@ -989,6 +1451,11 @@ void spl_destroy(spl_ctx *c) {
   if (c->h_bstats) (void)hipHostFree(c->h_bstats);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
+  for (int b = 0; b < 2; ++b) {
+    if (c->ev_copied[b]) (void)hipEventDestroy(c->ev_copied[b]);
+    if (c->ev_done[b]) (void)hipEventDestroy(c->ev_done[b]);
+  }
   delete c;
 }
 
@@ -1037,6 +1504,7 @@ spl_status spl_project(spl_ctx *c, const spl_particles *p, const spl_camera *cam
   ProjK pk;
   TRY(check_params(c, prm, true));
   TRY(check_particles(c, p, prm->mode));
+  TRY(check_colour(c, p, prm));
   TRY(camera_frame(c, cam, pk));
   if (p->n > 0 && !rec) return fail(c, SPL_EINVAL, "rec is NULL");
   HIPTRY(c, hipSetDevice(c->device));
@@ -1144,7 +1612,7 @@ spl_status spl_render_records(spl_ctx *c, int64_t n, const float *rec, const flo
   hipStream_t s = (hipStream_t)stream;
   int tile;
   double cut;
-  choose(c, n, cam->width, cam->height, prm, tile, cut);
+  choose(c, n, cam, prm, tile, cut);
   TileK tk;
   fill_tiles(tk, cam->width, cam->height, tile, prm->nu, cut, prm->bin_rule);
   TRY(prepare_common(c, n, tk, s));
@@ -1192,13 +1660,15 @@ spl_status spl_render_noalloc(spl_ctx *c, const spl_particles *p, const spl_came
   if (!c) return SPL_EINVAL;
   TRY(check_params(c, prm, true));
   TRY(check_particles(c, p, prm->mode));
+  TRY(check_colour(c, p, prm));
   if (!c->scratch) return fail(c, SPL_EDEVICE, "scratch address unknown on device %d", c->device);
   HIPTRY(c, hipSetDevice(c->device));
   // the per-particle buffers bound the particle count up front; the lists,
   // whose size the frame learns after its count, are checked when carved
   const bool sorted = prm->mode == SPL_SORTED;
   const size_t per_particle = 32 + 8 + (sorted ? 8 : 0);
-  const size_t fixed = (size_t)kFinBlocks * 6 * 8 + 64 + sizeof(Totals) + 4096;
+  const size_t fixed = (size_t)kFinBlocks * kStatPartials * 8 + kStatWords * 8 +
+                       sizeof(Totals) + 4096;
   if (p->n > 0 && (size_t)p->n > (kScratchBytes - fixed) / per_particle)
     return fail(c, SPL_ENOMEM,
                 "%lld particles need %zu bytes of per-particle workspace; the %zu-byte scratch "
@@ -1243,6 +1713,88 @@ spl_status spl_render_batch(spl_ctx *c, const spl_particles *p, int32_t n_views,
   return render_batch(c, p, n_views, cams, prms, outs, st, (hipStream_t)stream);
 }
 
+spl_status spl_dataset_upload(spl_ctx *c, const spl_particles *src, int32_t src_on_device,
+                              int32_t store_dtype, spl_dataset **out, void *stream) {
+  if (!c) return SPL_EINVAL;
+  HIPTRY(c, hipSetDevice(c->device));
+  return dataset_upload(c, src, src_on_device ? 1 : 0, store_dtype, out, (hipStream_t)stream);
+}
+
+void spl_dataset_free(spl_dataset *ds) {
+  if (!ds) return;
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  (void)hipSetDevice(ds->device);
+  (void)hipDeviceSynchronize();  // no render may still read it
+  if (ds->mem) (void)hipFree(ds->mem);
+  if (have) (void)hipSetDevice(cur);
+  delete ds;
+}
+
+spl_status spl_dataset_particles(const spl_dataset *ds, spl_particles *out) {
+  if (!ds || !out) return SPL_EINVAL;
+  *out = ds->view;
+  return SPL_OK;
+}
+
+int64_t spl_dataset_bytes(const spl_dataset *ds) { return ds ? (int64_t)ds->bytes : 0; }
+
+spl_status spl_render_dataset(spl_ctx *c, const spl_dataset *ds, const spl_camera *cam,
+                              const spl_params *prm, float *out, int32_t out_on_device,
+                              spl_stats *st, void *stream) {
+  if (!c) return SPL_EINVAL;
+  TRY(check_dataset(c, ds));
+  HIPTRY(c, hipSetDevice(c->device));
+  return render_out(c, &ds->view, cam, prm, out, out_on_device, st, (hipStream_t)stream);
+}
+
+spl_status spl_render_batch_dataset(spl_ctx *c, const spl_dataset *ds, int32_t n_views,
+                                    const spl_camera *cams, const spl_params *prms,
+                                    float *const *outs, int32_t out_on_device, spl_stats *st,
+                                    void *stream) {
+  if (!c) return SPL_EINVAL;
+  TRY(check_dataset(c, ds));
+  if (n_views < 0 || (n_views > 0 && (!cams || !prms || !outs)))
+    return fail(c, SPL_EINVAL, "bad view arrays");
+  HIPTRY(c, hipSetDevice(c->device));
+  if (n_views == 0) return SPL_OK;
+  return render_batch_out(c, &ds->view, n_views, cams, prms, outs, out_on_device, st,
+                          (hipStream_t)stream);
+}
+
+spl_status spl_render_stream(spl_ctx *c, const spl_particles *p, int64_t chunk,
+                             const spl_camera *cam, const spl_params *prm, float *out,
+                             int32_t out_on_device, spl_stats *st, void *stream) {
+  if (!c) return SPL_EINVAL;
+  HIPTRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (out_on_device) return render_stream(c, p, chunk, cam, prm, out, st, s);
+  if (!out) return fail(c, SPL_EINVAL, "output image is NULL");
+  if (!cam || cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768)
+    return fail(c, SPL_EINVAL, "bad camera or image size");
+  const size_t bytes = (size_t)cam->width * cam->height * 12;
+  TRY(ensure(c, c->himg, bytes));
+  TRY(render_stream(c, p, chunk, cam, prm, (float *)c->himg.p, st, s));
+  HIPTRY(c, hipMemcpyAsync(out, c->himg.p, bytes, hipMemcpyDeviceToHost, s));
+  HIPTRY(c, hipStreamSynchronize(s));
+  return SPL_OK;
+}
+
+spl_status spl_host_alloc(size_t bytes, void **out) {
+  if (!out) return SPL_EINVAL;
+  *out = nullptr;
+  if (hipHostMalloc(out, bytes ? bytes : 1, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return SPL_ENOMEM;
+  }
+  return SPL_OK;
+}
+
+void spl_host_free(void *p) {
+  if (p) (void)hipHostFree(p);
+}
+
 spl_status spl_set_option(spl_ctx *c, int32_t option, int64_t value) {
   if (!c) return SPL_EINVAL;
   switch (option) {
@@ -1272,6 +1824,7 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
   if (!tile_out || !cut_out) return fail(c, SPL_EINVAL, "outputs are NULL");
   TRY(check_params(c, prm, true));
   TRY(check_particles(c, p, prm->mode));
+  TRY(check_colour(c, p, prm));
   ProjK pk;
   TRY(camera_frame(c, cam, pk));
   HIPTRY(c, hipSetDevice(c->device));
@@ -1321,8 +1874,9 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
   (void)hipEventDestroy(e1);
   (void)hipFree(img);
   if (rc != SPL_OK) return rc;
-  c->tune[std::make_tuple(p->n, cam->width, cam->height, prm->mode)] =
-      std::make_pair(best_tile, best_cut < 0 ? INFINITY : best_cut);
+  const std::pair<int, double> choice(best_tile, best_cut < 0 ? INFINITY : best_cut);
+  c->tune[std::make_tuple(p->n, cam->width, cam->height, prm->mode, pose_digest(cam))] = choice;
+  c->tune_any[std::make_tuple(p->n, cam->width, cam->height, prm->mode)] = choice;
   *tile_out = best_tile;
   *cut_out = best_cut;
   return SPL_OK;

@@ -22,6 +22,7 @@ struct LookK {
   const float *rgb;
   int M;
   int log10;
+  int vec;          // 1: colour from the particle's rgb vector
   float beta;
   float lo;
   float inv_range;  // 1/(hi - lo); 0 when hi == lo
@@ -53,6 +54,8 @@ struct ProjK {
   float h_scale, i_scale, s_scale;
   const uint8_t *species;
   const float *absorb;
+  const void *rgb;  // colour vectors, 3 per particle (attribute dtype)
+  float c_scale;
   int64_t n;
 };
 
@@ -252,8 +255,25 @@ hipError_t launch_composite_merge(int tile, const Item *items, int n_items,
                                   const uint32_t *counts, int chunk, const TileK &tk,
                                   const float *partial, float *img, hipStream_t s);
 
+// Resident data sets: largest finite |value x scale| (bits of a
+// non-negative float, atomic max into *out_bits), and conversion to the
+// stored type (value x sscale x inv_dscale, rounded to nearest even).
+hipError_t launch_absmax(const void *src, int dtype, float scale, int64_t n, uint32_t *out_bits,
+                         hipStream_t s);
+hipError_t launch_convert(const void *src, int sdtype, float sscale, void *dst, int ddtype,
+                          float inv_dscale, int64_t n, hipStream_t s);
+
+// Finalisation: kStatPartials FP64 values per block (sums, maxima and sums
+// before the map, per channel); the reduction writes stats[0..9] (flux,
+// maxima, overall maximum, flux before the map).
+constexpr int kStatPartials = 9;
 hipError_t launch_finalise(float *img, int64_t n_px, int aeqe, double *partials, int n_blocks,
                            hipStream_t s);
+// Expected flux sum_p E_p kappa_p of the active records rec[0, n) (span
+// not kInactive) into out[0..2]; partials: 3 x n_blocks doubles.
+hipError_t launch_expected_flux(const float *rec, const uint2 *span, int64_t n, int W, int H,
+                                float nu, double *partials, int n_blocks, double *out,
+                                hipStream_t s);
 hipError_t launch_reduce_stats(const double *partials, int n_blocks, double *stats,
                                hipStream_t s);
 hipError_t launch_normalise(float *img, int64_t n_px, const double *stats, hipStream_t s);
