@@ -1,0 +1,143 @@
+"""The batched reduced-precision shape and the animation camera paths, against
+the FP64 oracle.
+
+Batched shape: views of 4096 x 4096 and 1024 x 1024 in one spl_render_batch
+call (tile 32 without the large-particle path at 4096^2, tile 16 with the
+default cut at 1024^2, the benchmark's tuned choices), attributes stored in
+FP32, BF16 and FP16.  The particles are a 1M-particle clustered set drawn
+with the recipe of the 200M-particle benchmark set and smoothing lengths
+scaled by (1M / 200M)^(1/3), which gives them the 200M set's local densities
+and so its projected radii.  Each view is compared with the oracle on the
+FP32 originals: rel-L2 <= 1e-5 and the per-pixel bound for FP32, <= 2e-3 for
+BF16 and <= 5e-4 for FP16.
+
+Camera paths (the paper's benchmark shape, Sect. 4.1: a camera orbit at
+1024^2; Sect. 4.3: camera positions from far to near): frames of the
+100-frame orbit in one batched call and the six far-to-near sweep poses one
+per call, on a 1M-particle sample of the 55M-particle recipe with smoothing
+lengths scaled by (1M / 55M)^(1/3)."""
+import numpy as np
+import pytest
+
+from paper_1606_04427_amd import synth
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 2e-3, "f16": 5e-4}
+
+
+@pytest.fixture(scope="module")
+def env(oracle):
+    import torch
+
+    from paper_1606_04427_amd import binding as B
+
+    assert torch.cuda.is_available()
+    ctx = B.Context(0)
+    yield B, ctx, oracle
+    ctx.close()
+
+
+def _scaled_set(n, seed, n_full):
+    ps = synth.soneira_peebles(n, seed=seed)
+    ps.h = (ps.h * (n / n_full) ** (1.0 / 3.0)).astype(np.float32)
+    looks, pals = [], []
+    for k in range(2):
+        s = ps.scalar[ps.species == k]
+        looks.append(dict(log10=1, brightness=0.02 * (1 + k), lo=float(np.log10(s.min())),
+                          hi=float(np.log10(s.max()))))
+        pals.append(synth.palette(k))
+    return ps, looks, pals
+
+
+@pytest.fixture(scope="module")
+def c3(env):
+    B, ctx, R = env
+    ps, looks, pals = _scaled_set(1_000_000, 1003, 200_000_000)
+    big = synth.random_poses(2, seed=2003, width=4096, height=4096)
+    small = synth.random_poses(2, seed=2004, width=1024, height=1024)
+    poses = [big[0], small[0], big[1], small[1]]
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    RP = R.Particles(ps)
+    refs = [R.render(RP, p, R.params(R.ADD_AEQE, L)) for p in poses]
+    return ps, looks, pals, poses, refs
+
+
+@pytest.mark.parametrize("store", ["f32", "bf16", "f16"])
+def test_batched_4096_and_1024_views_match_oracle(env, c3, store):
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals, poses, refs = c3
+    print(f"c3 shape store={store} views={[p.width for p in poses]}", flush=True)
+    ds = B.Dataset(ctx, ps, store)
+    P = B.Palettes(pals)
+    prms = [B.make_params(B.SPL_ADD_AEQE, P, looks, tile=32, large_cut=-1.0) if p.width == 4096
+            else B.make_params(B.SPL_ADD_AEQE, P, looks, tile=16, large_cut=32.0) for p in poses]
+    outs, sts = ctx.spl_render_batch_dataset(ds, poses, prms)
+    torch.cuda.synchronize()
+    for p, o, st, ref in zip(poses, outs, sts, refs):
+        got = o.cpu().numpy().astype(np.float64)
+        err = rel_l2(got, ref)
+        print(f"  {p.width}x{p.height} tile={st['tile']} n_active={st['n_active']} rel_l2={err:.3e}",
+              flush=True)
+        assert st["n_active"] > 10_000
+        assert st["tile"] == (32 if p.width == 4096 else 16)
+        assert err < TOL[store]
+        if store == "f32":
+            bound = 1e-3 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+            assert np.all(np.abs(got - ref) <= bound)
+        del got
+    ds.close()
+
+
+@pytest.fixture(scope="module")
+def paths(env):
+    ps, looks, pals = _scaled_set(1_000_000, 1005, 55_000_000)
+    orbit = synth.orbit_poses(100)[::25]  # 4 frames spread over the orbit
+    sweep = synth.sweep_poses(6)
+    return ps, looks, pals, orbit, sweep
+
+
+def test_orbit_frames_in_one_batch_match_oracle(env, paths):
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals, orbit, _ = paths
+    ds = B.Dataset(ctx, ps, "f32")
+    P = B.Palettes(pals)
+    prms = [B.make_params(B.SPL_ADD_AEQE, P, looks, tile=16)] * len(orbit)
+    outs, sts = ctx.spl_render_batch_dataset(ds, orbit, prms)
+    torch.cuda.synchronize()
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    RP = R.Particles(ps)
+    for k, (pose, o, st) in enumerate(zip(orbit, outs, sts)):
+        ref = R.render(RP, pose, R.params(R.ADD_AEQE, L))
+        got = o.cpu().numpy().astype(np.float64)
+        err = rel_l2(got, ref)
+        print(f"orbit frame {25 * k}: n_active={st['n_active']} rel_l2={err:.3e}", flush=True)
+        assert err < 1e-5
+    ds.close()
+
+
+@pytest.mark.parametrize("cut", [-1.0, 32.0])
+def test_far_to_near_sweep_matches_oracle(env, paths, cut):
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals, _, sweep = paths
+    ds = B.Dataset(ctx, ps, "f32")
+    P = B.Palettes(pals)
+    prm = B.make_params(B.SPL_ADD_AEQE, P, looks, tile=16, large_cut=cut)
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    RP = R.Particles(ps)
+    for k, pose in enumerate(sweep):
+        img, st = ctx.spl_render_dataset(ds, pose, prm)
+        torch.cuda.synchronize()
+        ref = R.render(RP, pose, R.params(R.ADD_AEQE, L))
+        err = rel_l2(img.cpu().numpy().astype(np.float64), ref)
+        print(f"sweep {k} cut={cut}: n_active={st['n_active']} n_large={st['n_large']} "
+              f"rel_l2={err:.3e}", flush=True)
+        assert err < 1e-5
+    ds.close()
