@@ -36,7 +36,9 @@ class Request:
     done: float = math.nan
     batch: int = -1       # sequence number of the batch that rendered it
     worker: int = -1
-    cost: int = 0         # bytes reserved while in flight
+    cost: int = 0         # image + workspace bytes
+    img_bytes: int = 0    # image bytes, held until the request completes
+    ws_bytes: int = 0     # workspace bytes it adds to its worker's context
     image: object = None
     stats: dict | None = None
     error: str | None = None
@@ -46,14 +48,32 @@ class Request:
         return self.done - self.arrival
 
 
-def request_bytes(n_particles: int, width: int, height: int, sorted_mode: bool) -> int:
-    """Device bytes one view holds while in flight: its image plus the
-    per-view workspace (32 B record and 8 B span per particle, list entries;
-    sorted views also hold depth records and two key buffers)."""
+def request_cost(n_particles: int, width: int, height: int, sorted_mode: bool,
+                 entries_per_particle: float = 2.0, tile: int = 16) -> tuple[int, int]:
+    """Device bytes of one view: (image, workspace).
+
+    The image (12 B per pixel) is held from admission until the request
+    completes.  The workspace is what the view adds to its worker's library
+    context while it renders, and the context keeps it for later batches:
+    a 32 B record and an 8 B span per particle, 4 B per tile-list entry
+    (about entries_per_particle entries per particle), a 16 B work item per
+    1024 entries and per tile, counts, offsets and cursors (16 B per tile) and
+    fixed buffers (4 MiB).  Sorted views add an 8 B depth record per particle,
+    two 8 B sort keys per entry, and the composite's partial tiles (16 B per
+    pixel of each work item's tile)."""
     img = 12 * width * height
-    ws = n_particles * (32 + 8 + 8) + 4 * MiB
+    tiles = -(-width // tile) * -(-height // tile)
+    entries = int(entries_per_particle * n_particles)
+    items = entries // 1024 + tiles
+    ws = n_particles * (32 + 8) + 4 * entries + 16 * items + 16 * tiles + 4 * MiB
     if sorted_mode:
-        ws += n_particles * (8 + 2 * 16)
+        ws += n_particles * 8 + 16 * entries + items * tile * tile * 16
+    return img, ws
+
+
+def request_bytes(n_particles: int, width: int, height: int, sorted_mode: bool, **kw) -> int:
+    """Image plus workspace of one view (request_cost summed)."""
+    img, ws = request_cost(n_particles, width, height, sorted_mode, **kw)
     return img + ws
 
 
@@ -61,10 +81,17 @@ class Server:
     """Continuous-batching request loop (see the module docstring).
 
     make_executor(worker_index) is called once in each worker thread.
-    cost(request) gives the bytes a request reserves; budget_bytes bounds
-    their sum over requests in flight.  keep(request) decides whether the
-    image is kept on the request after completion (dropping it frees device
-    memory at once)."""
+    cost(request) gives either the bytes a request holds until it completes,
+    or a pair (image bytes, workspace bytes).  Device memory is accounted as
+    the images of requests in flight plus the workspace every worker's
+    context holds (an executor with workspace_bytes() reports it after each
+    batch; otherwise the largest workspace estimate of its batches is used),
+    and budget_bytes bounds that sum.  A worker that is idle and cannot admit
+    the head of the queue because of held workspace releases its own (the
+    executor's trim(), if it has one) and tells the other workers, which then
+    do the same, so the head always runs eventually.  keep(request) decides
+    whether the image is kept on the request after completion (dropping it
+    frees device memory at once)."""
 
     def __init__(self, make_executor, n_workers: int = 2, budget_bytes: int = 64 << 30,
                  max_views: int = 16, cost=None, keep=None, clock=time.perf_counter):
@@ -74,15 +101,18 @@ class Server:
         self.n_workers = n_workers
         self.budget = int(budget_bytes)
         self.max_views = max_views
-        self.cost = cost or (lambda r: request_bytes(0, r.pose.width, r.pose.height, False))
+        self.cost = cost or (lambda r: request_cost(0, r.pose.width, r.pose.height, False))
         self.keep = keep or (lambda r: True)
         self.clock = clock
         self.queue: collections.deque[Request] = collections.deque()
         self.cv = threading.Condition()
-        self.reserved = 0
-        self.peak_reserved = 0
+        self.reserved = 0          # images of requests in flight
+        self.held = [0] * n_workers  # workspace each worker's context holds
+        self.planned = [0] * n_workers  # workspace a running batch may grow to
+        self.peak_reserved = 0     # largest images + workspace accounted at once
         self.in_flight = 0
         self.n_batches = 0
+        self.n_trims = 0
         self.completed: list[Request] = []
         self.stopping = False
         self.threads: list[threading.Thread] = []
@@ -101,7 +131,9 @@ class Server:
         return self
 
     def submit(self, r: Request):
-        r.cost = int(self.cost(r))
+        c = self.cost(r)
+        r.img_bytes, r.ws_bytes = (int(c[0]), int(c[1])) if isinstance(c, tuple) else (int(c), 0)
+        r.cost = r.img_bytes + r.ws_bytes
         if math.isnan(r.arrival):
             r.arrival = self.clock()
         with self.cv:
@@ -139,17 +171,29 @@ class Server:
             raise RuntimeError(f"worker failed: {self.errors[0]!r}")
 
     # -- scheduling -------------------------------------------------------------
-    def _take(self) -> list[Request]:
-        """Admits queued requests in arrival order; caller holds the lock."""
-        batch = []
+    def _accounted(self, w: int, extra_img: int, ws_w: int) -> int:
+        """Bytes in use if worker w's workspace were ws_w and extra_img more
+        image bytes were in flight; caller holds the lock."""
+        others = sum(max(self.held[v], self.planned[v]) for v in range(self.n_workers) if v != w)
+        return self.reserved + extra_img + others + ws_w
+
+    def _take(self, w: int) -> list[Request]:
+        """Admits queued requests in arrival order for worker w; caller holds
+        the lock."""
+        batch, img, ws = [], 0, 0
         while self.queue and len(batch) < self.max_views:
             r = self.queue[0]
-            if self.reserved + r.cost > self.budget:
+            ws_w = max(self.held[w], ws + r.ws_bytes)
+            if self._accounted(w, img + r.img_bytes, ws_w) > self.budget:
                 break
             self.queue.popleft()
-            self.reserved += r.cost
             batch.append(r)
-        self.peak_reserved = max(self.peak_reserved, self.reserved)
+            img += r.img_bytes
+            ws += r.ws_bytes
+        if batch:
+            self.reserved += img
+            self.planned[w] = max(self.held[w], ws)
+            self.peak_reserved = max(self.peak_reserved, self._accounted(w, 0, self.planned[w]))
         return batch
 
     def _worker(self, w: int):
@@ -166,9 +210,21 @@ class Server:
                     while True:
                         if self.errors:
                             return
-                        batch = self._take()
+                        batch = self._take(w)
                         if batch or (self.stopping and not self.queue):
                             break
+                        if self.queue and self.held[w] > 0:
+                            # the head does not fit beside the workspace the
+                            # workers hold: release this worker's and let the
+                            # others reconsider
+                            trim = getattr(ex, "trim", None)
+                            if trim:
+                                trim()
+                            self.held[w] = 0
+                            self.planned[w] = 0
+                            self.n_trims += 1
+                            self.cv.notify_all()
+                            continue
                         self.cv.wait()
                     if not batch:
                         return
@@ -183,6 +239,7 @@ class Server:
                     err = None
                 except Exception as e:  # a failed batch fails its requests only
                     images, stats, err = [None] * len(batch), [None] * len(batch), repr(e)
+                held = getattr(ex, "workspace_bytes", None)
                 t = self.clock()
                 for r, im, st in zip(batch, images, stats):
                     r.stats = st
@@ -191,7 +248,9 @@ class Server:
                 with self.cv:
                     for r in batch:
                         r.done = t
-                    self.reserved -= sum(r.cost for r in batch)
+                    self.reserved -= sum(r.img_bytes for r in batch)
+                    self.held[w] = int(held()) if held else self.planned[w]
+                    self.planned[w] = 0
                     self.in_flight -= len(batch)
                     self.completed.extend(batch)
                     self.cv.notify_all()
@@ -251,18 +310,20 @@ def summary(requests) -> dict:
 
 
 class GpuExecutor:
-    """Renders batches through the HIP library on its own context and stream.
+    """Renders batches through the HIP library on its own context and stream,
+    from a data set resident in device memory (binding.Dataset, shared by every
+    worker).  A batch of one view takes the single-view call.
 
     bank: list of (Palettes, looks) pairs, indexed by Request.look."""
 
-    def __init__(self, parts, bank, device: str = "cuda:0", batch_bytes: int | None = None,
+    def __init__(self, ds, bank, device: str = "cuda:0", batch_bytes: int | None = None,
                  graphs: bool = False):
         import torch
 
         from . import binding as B
 
         self.B = B
-        self.parts = parts
+        self.ds = ds
         self.bank = bank
         self.ctx = B.Context(torch.device(device).index or 0)
         self.stream = torch.cuda.Stream(device=device)
@@ -282,10 +343,22 @@ class GpuExecutor:
         import torch
 
         with torch.cuda.stream(self.stream):
-            outs, sts = self.ctx.spl_render_batch(self.parts, [r.pose for r in reqs],
-                                                  [self.params(r.mode, r.look) for r in reqs])
+            if len(reqs) == 1:
+                r = reqs[0]
+                out, st = self.ctx.spl_render_dataset(self.ds, r.pose, self.params(r.mode, r.look))
+                outs, sts = [out], [st]
+            else:
+                outs, sts = self.ctx.spl_render_batch_dataset(
+                    self.ds, [r.pose for r in reqs], [self.params(r.mode, r.look) for r in reqs])
         self.stream.synchronize()
         return outs, sts
+
+    def workspace_bytes(self) -> int:
+        return self.ctx.workspace_bytes()
+
+    def trim(self):
+        self.stream.synchronize()
+        self.ctx.spl_trim()
 
     def close(self):
         self.stream.synchronize()

@@ -46,9 +46,10 @@ def test_results_alone_equal_results_in_the_mix():
     mix = _requests(48, seed=7)
     tagged = set(range(0, 48, 3))  # 16 tagged requests
     keep = lambda r: r.rid in tagged
-    cost = lambda r: serve.request_bytes(parts.n, r.pose.width, r.pose.height, r.mode == 2)
+    cost = lambda r: serve.request_cost(parts.n, r.pose.width, r.pose.height, r.mode == 2)
     srv = serve.Server(lambda w: serve.GpuExecutor(parts, bank), n_workers=2,
-                       budget_bytes=6 * cost(mix[0]), max_views=8, cost=cost, keep=keep).start()
+                       budget_bytes=6 * sum(cost(mix[0])), max_views=8, cost=cost,
+                       keep=keep).start()
     arrivals = synth.poisson_arrivals(len(mix), rate_per_s=2000.0, seed=5)
     serve.drive(srv, mix, arrivals)
     srv.stop()

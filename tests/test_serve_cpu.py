@@ -148,8 +148,111 @@ def test_one_per_call_baseline_and_summary():
     assert 0 < s["frames_per_s"] <= 1.0 / 0.002 * 1.1
 
 
-def test_request_bytes_model():
-    a = serve.request_bytes(1000, 64, 32, False)
-    b = serve.request_bytes(1000, 64, 32, True)
-    assert a == 12 * 64 * 32 + 1000 * 48 + 4 * serve.MiB
-    assert b > a
+def test_request_cost_model():
+    """Image and workspace terms of one view: records, spans and list entries
+    grow with the particle count, the composite's partial tiles with the
+    list entries (sorted mode)."""
+    n, w, h = 100_000, 64, 32
+    img, ws = serve.request_cost(n, w, h, False)
+    entries = 2 * n
+    items = entries // 1024 + 4 * 2
+    assert img == 12 * w * h
+    assert ws == n * 40 + 4 * entries + 16 * items + 16 * 8 + 4 * serve.MiB
+    img2, ws2 = serve.request_cost(n, w, h, True)
+    assert img2 == img
+    assert ws2 - ws == n * 8 + 16 * entries + items * 16 * 16 * 16
+    # more entries per particle, more workspace
+    assert serve.request_cost(n, w, h, False, entries_per_particle=4.0)[1] > ws
+    assert serve.request_bytes(n, w, h, False) == img + ws
+
+
+class LedgerExecutor:
+    """Fake executor whose context holds workspace like the library's: it
+    grows to the largest batch it rendered and is released by trim().  A
+    shared ledger sums the workspace of every executor and the images of the
+    requests it is rendering, so the test can check the budget at every
+    moment."""
+
+    def __init__(self, ledger, lock, per_batch=0.003):
+        self.ledger, self.lock, self.per_batch = ledger, lock, per_batch
+        self.held = 0
+
+    def _note(self, delta):
+        with self.lock:
+            self.ledger["now"] += delta
+            self.ledger["peak"] = max(self.ledger["peak"], self.ledger["now"])
+
+    def run(self, reqs):
+        need = sum(r.ws_bytes for r in reqs)
+        img = sum(r.img_bytes for r in reqs)
+        grow = max(need - self.held, 0)
+        self._note(grow + img)
+        self.held += grow
+        time.sleep(self.per_batch)
+        self._note(-img)
+        return [None] * len(reqs), [{}] * len(reqs)
+
+    def workspace_bytes(self):
+        return self.held
+
+    def trim(self):
+        self._note(-self.held)
+        self.held = 0
+        with self.lock:
+            self.ledger["trims"] += 1
+
+
+@pytest.mark.parametrize("n_workers", [1, 2, 3])
+def test_held_workspace_counts_against_the_budget(n_workers):
+    """Requests with large and small workspace, a budget that holds one large
+    view and a bit more: the images in flight plus every context's held workspace
+    never exceed the budget, workers release workspace when the head of the
+    queue does not fit, and every request completes (no deadlock)."""
+    ledger, lock = {"now": 0, "peak": 0, "trims": 0}, threading.Lock()
+    big, small = (1000, 40_000), (100, 4_000)
+    costs = {}
+    reqs = []
+    for k in range(60):
+        r = serve.Request(k, synth.Pose((0, 0, 2), (0, 0, 0), (0, 1, 0), 50.0, 0.01, 8, 8), 1)
+        costs[k] = big if k % 5 == 0 else small
+        reqs.append(r)
+    budget = sum(big) + 25_000
+    srv = serve.Server(lambda w: LedgerExecutor(ledger, lock), n_workers=n_workers,
+                       budget_bytes=budget, max_views=4, cost=lambda r: costs[r.rid]).start()
+    serve.drive(srv, reqs, np.zeros(len(reqs)))
+    srv.stop()
+    assert all(r.error is None for r in reqs)
+    assert ledger["peak"] <= budget
+    assert srv.peak_reserved <= budget
+    assert srv.n_trims == ledger["trims"]
+
+
+def test_workers_release_workspace_so_the_head_can_run():
+    """Two workers each keep 30k of workspace from a request they rendered at
+    the same time; the next request needs 45k, which fits the budget alone but
+    not beside the other worker's held workspace: the worker that finds the
+    head blocked releases its own, and the request runs on whichever worker
+    then has room."""
+    ledger, lock = {"now": 0, "peak": 0, "trims": 0}, threading.Lock()
+    pose = synth.Pose((0, 0, 2), (0, 0, 0), (0, 1, 0), 50.0, 0.01, 8, 8)
+    reqs = [serve.Request(k, pose, 1) for k in range(3)]
+    costs = {0: (500, 30_000), 1: (500, 30_000), 2: (1000, 45_000)}
+    budget = 71_000
+    srv = serve.Server(lambda w: LedgerExecutor(ledger, lock, per_batch=0.05), n_workers=2,
+                       budget_bytes=budget, max_views=1, cost=lambda r: costs[r.rid]).start()
+    serve.drive(srv, reqs, np.array([0.0, 0.0, 0.01]))
+    srv.stop()
+    assert all(r.error is None for r in reqs)
+    assert reqs[0].worker != reqs[1].worker
+    assert srv.n_trims == ledger["trims"] >= 1
+    assert ledger["peak"] <= budget
+
+
+def test_a_request_larger_than_the_budget_with_workspace_is_rejected():
+    ledger, lock = {"now": 0, "peak": 0, "trims": 0}, threading.Lock()
+    srv = serve.Server(lambda w: LedgerExecutor(ledger, lock), n_workers=1, budget_bytes=1000,
+                       cost=lambda r: (400, 700)).start()
+    r = serve.Request(0, synth.Pose((0, 0, 2), (0, 0, 0), (0, 1, 0), 50.0, 0.01, 8, 8), 1)
+    serve.drive(srv, [r], np.zeros(1))
+    srv.stop()
+    assert r.error and "budget" in r.error
