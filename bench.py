@@ -258,36 +258,39 @@ def run_additive(args, torch, B):
     log(f"generated {ps.n} particles in {time.time() - t:.1f} s")
     dev = "cuda:0"
     ctx = B.Context(0)
-    parts = B.DeviceParticles(ps, dev, "f32")
-    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals, dev), looks)
+    parts = B.Dataset(ctx, ps, "f32")
+    pal_d = B.Palettes(pals, dev)
+    prm = B.make_params(B.SPL_ADD_AEQE, pal_d, looks)
     imgs = [torch.empty((p.height, p.width, 3), dtype=torch.float32, device=dev) for p in poses]
     torch.cuda.synchronize()
 
-    tile, cut = 16, 32.0
+    tuned = None
     if args.tile:
         # fixed configuration (profiling runs repeat the tuned one)
-        tile, cut = args.tile, args.cut
-        prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals, dev), looks, tile=tile,
-                            large_cut=cut)
+        prm = B.make_params(B.SPL_ADD_AEQE, pal_d, looks, tile=args.tile, large_cut=args.cut)
     elif not args.no_autotune:
-        tile, cut = ctx.spl_autotune(parts, poses[0], prm)
-        log(f"autotune: tile {tile}, large cut {cut}")
+        # the tile size and large-particle cut are tuned per pose: the radii a
+        # pose projects decide whether the large-particle path pays
+        tuned = [ctx.spl_autotune(parts, p, prm) for p in poses]
+        log(f"autotune per pose (tile, cut): {tuned}")
 
     prms = [prm] * len(poses)
 
     # one step: all poses in one call of the batched entry point (one list-size
-    # synchronisation, one persistent splat launch)
+    # synchronisation, one persistent splat launch per tile size)
     def step():
-        ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
+        ctx.spl_render_batch_dataset(parts, poses, prms, outs=imgs, stats=False)
 
     elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps * len(poses) * ps.n / elapsed
     log(f"{args.steps} steps in {elapsed:.3f} s, {ms_per_step:.2f} ms/step, {value:.3e} particles/s")
+    _, bstats = ctx.spl_render_batch_dataset(parts, poses, prms, outs=imgs)
+    tiles_used = sorted({s["tile"] for s in bstats})
 
     # outside the timed region: per-pose statistics and the Gaussian updates
     # the splat had to evaluate (from the device's own records)
-    stats = [ctx.spl_render(parts, p, prm, out=imgs[k])[1] for k, p in enumerate(poses)]
+    stats = [ctx.spl_render_dataset(parts, p, prm, out=imgs[k])[1] for k, p in enumerate(poses)]
     pose_updates, pose_small, pose_rho = [], [], []
     for k, p in enumerate(poses):
         rec, _ = ctx.spl_project(parts, p, prm)
@@ -298,36 +301,58 @@ def run_additive(args, torch, B):
         pose_rho.append(radius_range(rh))
         del rec, rh
     updates = float(sum(pose_updates))
-    # one persistent splat launch per step covers all poses
-    roofline = roofline_for(B, ms, by, args.steps, updates)
+    # one persistent splat launch per step covers all poses (when they share a
+    # tile size)
+    roofline = roofline_for(B, ms, by, args.steps * len(tiles_used), updates / len(tiles_used))
     roofline["kernel"] = "k_splat_add_views" if roofline["kernel"] == "k_splat_add" else roofline["kernel"]
-    roofline["traffic"] = measured_traffic(roofline["kernel"], ps.n, tile, cut)
+    roofline["traffic"] = measured_traffic(roofline["kernel"], ps.n, bstats[0]["tile"],
+                                           bstats[0]["large_cut"])
 
     # the same step one view per call, with the library's per-stage events
     def pstep():
         for k, pose in enumerate(poses):
-            ctx.spl_render(parts, pose, prm, out=imgs[k], stats=False)
+            ctx.spl_render_dataset(parts, pose, prm, out=imgs[k], stats=False)
 
     p_elapsed, p_ms, p_by, p_frames = timed_steps(ctx, pstep, args.steps, args.warmup, torch)
     per_view = {"ms_per_step": 1e3 * p_elapsed / args.steps,
                 "particles_per_s": args.steps * len(poses) * ps.n / p_elapsed,
                 "stages": stage_table(B, p_ms, p_by, p_frames)}
     log(f"one view per call: {per_view['ms_per_step']:.2f} ms/step")
-    # per pose: splat time and the footprint that drives it
+    # per pose: splat time and the footprint that drives it, and the frame
+    # time at each large-particle cut (the evidence behind the tuned choice)
+    si, li = B.STAGES.index("splat"), B.STAGES.index("large_splat")
     per_pose = []
     for k, p in enumerate(poses):
-        ctx.spl_set_timing(True)
-        ctx.spl_get_timing()
-        ctx.spl_render(parts, p, prm, out=imgs[k], stats=False)
-        pm, _, pf = ctx.spl_get_timing()
-        ctx.spl_set_timing(False)
-        per_pose.append({"n_active": stats[k]["n_active"], "n_pairs": stats[k]["n_pairs"],
-                         "box_px": pose_updates[k],
-                         "n_large": stats[k]["n_large"],
-                         "rho_px": pose_rho[k],
-                         "box_px_per_active": pose_updates[k] / max(stats[k]["n_active"], 1),
-                         "frame_ms": sum(pm) / max(pf, 1),
-                         "splat_ms": pm[B.STAGES.index("splat")] / max(pf, 1)})
+        def timed(q, reps=3):
+            ctx.spl_render_dataset(parts, p, q, out=imgs[k], stats=False)
+            ctx.spl_set_timing(True)
+            ctx.spl_get_timing()
+            for _ in range(reps):
+                ctx.spl_render_dataset(parts, p, q, out=imgs[k], stats=False)
+            pm, _, pf = ctx.spl_get_timing()
+            ctx.spl_set_timing(False)
+            return pm, max(pf, 1)
+
+        pm, pf = timed(prm)
+        row = {"n_active": stats[k]["n_active"], "n_pairs": stats[k]["n_pairs"],
+               "n_large": stats[k]["n_large"], "tile": stats[k]["tile"],
+               "large_cut": stats[k]["large_cut"], "rho_px": pose_rho[k],
+               "box_px": pose_updates[k],
+               "box_px_per_active": pose_updates[k] / max(stats[k]["n_active"], 1),
+               "frame_ms": sum(pm) / pf, "splat_ms": pm[si] / pf}
+        if not args.no_cut_table:
+            cuts = {}
+            for cut in (16.0, 32.0, 64.0, 128.0, -1.0):
+                q = B.make_params(B.SPL_ADD_AEQE, pal_d, looks, tile=stats[k]["tile"],
+                                  large_cut=cut)
+                cm, cf = timed(q)
+                cuts["off" if cut < 0 else f"{cut:g}"] = {
+                    "frame_ms": sum(cm) / cf, "splat_ms": cm[si] / cf,
+                    "large_splat_ms": cm[li] / cf}
+            row["frame_ms_by_cut"] = cuts
+        per_pose.append(row)
+    log("per pose: " + json.dumps([{k: v for k, v in r.items() if k != "rho_px"}
+                                    for r in per_pose])[:2000])
 
     # the batched step replayed as a captured graph
     graphs = None
@@ -355,41 +380,19 @@ def run_additive(args, torch, B):
         torch.cuda.synchronize()
         del src, dst
 
-    # bandwidth probe: the same particle count with the small radii of the
-    # blob set (0.5-8 px), where the splat moves more bytes per evaluation
+    # out-of-core rendering of the same set from page-locked host memory, in
+    # chunks through two device buffers (copies overlapped with rendering)
+    stream_rec = None
+    if not args.no_stream:
+        stream_rec = stream_leg(args, torch, B, ctx, ps, poses[0], prm, parts)
+        log("out-of-core: " + json.dumps(stream_rec))
+
+    # bandwidth probe: the same particle count with small radii (0.5-8 px,
+    # the small blob case's distribution) at 1024 x 1024
     probe = None
     if not args.no_probe:
-        from paper_1606_04427_amd import synth
-
-        pb = synth.blobs(ps.n, seed=1000)
-        bparts = B.DeviceParticles(pb, dev, "f32")
-        s_ = pb.scalar[pb.scalar > 0]
-        blook = [dict(log10=1, brightness=0.3, lo=float(np.log10(s_.min())),
-                      hi=float(np.log10(s_.max())))]
-        bprm = B.make_params(B.SPL_ADD_AEQE, B.Palettes([synth.palette(0)], dev), blook, tile=16,
-                             large_cut=-1.0)
-        bcam = synth.blobs_camera(256, 256)
-        bimg = torch.empty((256, 256, 3), dtype=torch.float32, device=dev)
-        for _ in range(2):
-            ctx.spl_render(bparts, bcam, bprm, out=bimg, stats=False)
-        ctx.spl_set_timing(True)
-        ctx.spl_get_timing()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ctx.spl_render(bparts, bcam, bprm, out=bimg, stats=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        pm, pby, pf = ctx.spl_get_timing()
-        ctx.spl_set_timing(False)
-        si = B.STAGES.index("splat")
-        probe = {"workload": f"{pb.n} particles in 64 Gaussian blobs, projected radii 0.5-8 px, "
-                             "256x256, fixed camera, additive",
-                 "particles_per_s": args.steps * pb.n / dt, "ms_per_frame": 1e3 * dt / args.steps,
-                 "splat_ms": pm[si] / pf, "splat_GBps": pby[si] / (pm[si] * 1e-3) / 1e9,
-                 "stages_ms": {B.STAGES[i]: pm[i] / pf for i in range(len(B.STAGES))}}
+        probe = bandwidth_probe(args, torch, B, ctx, ps.n)
         log("bandwidth probe: " + json.dumps(probe))
-        del bparts
 
     frame_bytes = sum(by[k] for k in range(len(B.STAGES)) if B.STAGES[k] != "host_gap_items")
     frame_bytes /= max(frames, 1)
@@ -397,8 +400,8 @@ def run_additive(args, torch, B):
         "workload": "Soneira-Peebles clustered set (4 levels x 8), 10M particles, 2 species, "
                     "1024x1024, 8 random poses per step in one batched call, additive "
                     "absorption=emission, FP32",
-        "n_particles": ps.n, "image": [1024, 1024], "poses": len(poses), "tile": tile,
-        "large_cut_px": cut})
+        "n_particles": ps.n, "image": [1024, 1024], "poses": len(poses),
+        "tiles": tiles_used, "tuned_per_pose": tuned})
     out.update({
         "hbm_GBps_per_frame": frame_bytes / (ms_per_step * 1e-3 / len(poses)) / 1e9,
         "ms_per_frame": ms_per_step / len(poses),
@@ -407,12 +410,17 @@ def run_additive(args, torch, B):
         "one_view_per_call": per_view,
         "batched_graph_replay": graphs,
         "per_pose": per_pose,
+        "out_of_core": stream_rec,
         "bandwidth_probe": probe,
         "mean_box_px_per_small_particle": footprint(pose_updates, pose_small),
         "frames": [{"n_active": s["n_active"], "n_pairs": s["n_pairs"], "n_large": s["n_large"],
-                    "n_large_pairs": s["n_large_pairs"]} for s in stats],
+                    "n_large_pairs": s["n_large_pairs"], "tile": s["tile"],
+                    "large_cut": s["large_cut"]} for s in bstats],
     })
+    parts.close()
     ctx.close()
+    if not args.no_serving:
+        out["serving"] = serving_leg(args, torch, B)
     if not args.no_cpu_baseline:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(ps, poses, looks, pals, args.cpu_sample or 5_000_000,
@@ -421,6 +429,89 @@ def run_additive(args, torch, B):
             ps, poses, looks, pals, args.cpu_sample or 5_000_000, B.SPL_ADD_AEQE)
         log(f"cpu baseline in {time.time() - t:.1f} s")
     return out
+
+
+def stream_leg(args, torch, B, ctx, ps, pose, prm, parts):
+    """Out-of-core rendering: the set from page-locked host memory in chunks
+    (Sect. 3.1's double-buffered copies).  Reports the streamed frame time,
+    the copy time of the same bytes alone and the resident frame time, and the
+    share of the copy time the overlap hides."""
+    chunk = args.stream_chunk
+    host = B.PinnedParticles(ps)
+    img = torch.empty((pose.height, pose.width, 3), dtype=torch.float32, device="cuda:0")
+    reps = max(3, args.steps // 2)
+
+    def time_it(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    streamed = time_it(lambda: ctx.spl_render_stream(host, chunk, pose, prm, out=img, stats=False))
+    resident = time_it(lambda: ctx.spl_render_dataset(parts, pose, prm, out=img, stats=False))
+    # the same bytes copied host -> device alone (pinned source)
+    nbytes = ps.n * (12 + 12 + 1)
+    src = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    copy = time_it(lambda: dst.copy_(src, non_blocking=True))
+    del src, dst
+    host.close()
+    hidden = (copy + resident - streamed) / copy if copy > 0 else 0.0
+    return {"chunk_particles": chunk, "chunks": -(-ps.n // chunk), "bytes_copied": nbytes,
+            "streamed_ms": streamed, "resident_ms": resident, "copy_alone_ms": copy,
+            "copy_GBps": nbytes / (copy * 1e-3) / 1e9,
+            "copy_hidden_fraction": max(0.0, min(1.0, hidden)),
+            "particles_per_s": ps.n / (streamed * 1e-3)}
+
+
+def bandwidth_probe(args, torch, B, ctx, n):
+    """n blob particles whose projected radii follow the small case's
+    log-normal distribution (0.5-8 px) at 1024 x 1024: the regime where the
+    splat moves the most bytes per Gaussian evaluation."""
+    from paper_1606_04427_amd import synth
+
+    pb = synth.blobs(n, seed=1000)
+    # the blob recipe sizes h for a 256-px view; four times the pixels per
+    # world unit at 1024 px, so h / 4 keeps the radii in px
+    pb.h = (pb.h / 4.0).astype(np.float32)
+    bparts = B.Dataset(ctx, pb, "f32")
+    s_ = pb.scalar[pb.scalar > 0]
+    blook = [dict(log10=1, brightness=0.3, lo=float(np.log10(s_.min())),
+                  hi=float(np.log10(s_.max())))]
+    bprm = B.make_params(B.SPL_ADD_AEQE, B.Palettes([synth.palette(0)]), blook, tile=16,
+                         large_cut=-1.0)
+    bcam = synth.blobs_camera(1024, 1024)
+    bimg = torch.empty((1024, 1024, 3), dtype=torch.float32, device="cuda:0")
+    for _ in range(2):
+        ctx.spl_render_dataset(bparts, bcam, bprm, out=bimg, stats=False)
+    ctx.spl_set_timing(True)
+    ctx.spl_get_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.spl_render_dataset(bparts, bcam, bprm, out=bimg, stats=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pm, pby, pf = ctx.spl_get_timing()
+    ctx.spl_set_timing(False)
+    st = ctx.spl_render_dataset(bparts, bcam, bprm, out=bimg)[1]
+    rec, _ = ctx.spl_project(bparts, bcam, bprm)
+    upd, small = box_pixels(rec.cpu().numpy(), 1024, 1024, -1.0)
+    del rec
+    bparts.close()
+    si = B.STAGES.index("splat")
+    splat_s = pm[si] / pf * 1e-3
+    return {"workload": f"{pb.n} particles in 64 Gaussian blobs, projected radii 0.5-8 px "
+                        "(log-normal about 2 px), 1024x1024, fixed camera, additive",
+            "particles_per_s": args.steps * pb.n / dt, "ms_per_frame": 1e3 * dt / args.steps,
+            "n_pairs": st["n_pairs"], "box_px_per_particle": upd / max(small, 1),
+            "splat_ms": pm[si] / pf, "splat_GBps": pby[si] / pf / splat_s / 1e9,
+            "splat_hbm_frac": pby[si] / pf / splat_s / 1e9 / HBM_PEAK_GBS,
+            "splat_TFLOPs": FLOPS_PER_UPDATE * upd / splat_s / 1e12,
+            "stages_ms": {B.STAGES[i]: pm[i] / pf for i in range(len(B.STAGES))}}
 
 
 # ----------------------------------------------------------------------------
@@ -608,12 +699,12 @@ def run_batched(args, torch, B):
         parts = B.DeviceParticles(ps, dev, dt_name)
         torch.cuda.synchronize()
         prms = [prm] * len(poses)
+        tuned = {}
         if not args.no_autotune:
-            # one tuning per image size; the library keeps the choice per
-            # (particle count, image size, mode)
-            tuned = {}
+            # one tuning per image size; the library applies the latest choice
+            # for an image size to the poses it did not tune
             for p in (big[0], small[0]):
-                tuned[f"{p.width}x{p.height}"] = ctx.spl_autotune(parts, p, prm)
+                tuned[p.width] = ctx.spl_autotune(parts, p, prm)
             log(f"{dt_name} autotune (tile, cut): {tuned}")
 
         def bstep():
@@ -646,18 +737,24 @@ def run_batched(args, torch, B):
             log(f"{dt_name} {name}: {res[name]}")
         del parts
         # error against the FP64 oracle on a fixed 1M subsample, views
-        # alternating 4096^2 and 1024^2
+        # alternating 4096^2 and 1024^2, rendered by the batched call with the
+        # tile and cut the timed run used at each image size
         sparts = B.DeviceParticles(sub, dev, dt_name)
         L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
         RP = R.Particles(sub)
         errs = []
         t_err = time.time()
-        for p in poses[: args.error_views]:
-            g, _ = ctx.spl_render(sparts, p, prm)
+        eposes = poses[: args.error_views]
+        eprms = []
+        for p in eposes:
+            tile, cut = tuned.get(p.width, (0, 0.0))
+            eprms.append(B.make_params(B.SPL_ADD_AEQE, pal_d, looks, tile=tile, large_cut=cut))
+        gots, _ = ctx.spl_render_batch(sparts, eposes, eprms)
+        for p, g in zip(eposes, gots):
             want = R.render(RP, p, R.params(R.ADD_AEQE, L))
             got = g.cpu().numpy().astype(np.float64)
             den = np.linalg.norm(want)
-            errs.append({"image": [p.width, p.height],
+            errs.append({"image": [p.width, p.height], "tile_cut": list(tuned.get(p.width, ())),
                          "rel_l2": float(np.linalg.norm(got - want) / den) if den else 0.0,
                          "max_abs": float(np.abs(got - want).max()),
                          "max_ref": float(np.abs(want).max())})
@@ -680,19 +777,26 @@ def run_batched(args, torch, B):
 
 
 # ----------------------------------------------------------------------------
-def run_serving(args, torch, B):
+def serving_experiment(args, torch, B, n, n_requests, rates, workers):
+    """The request loop on a resident clustered set: image sizes uniform over
+    256^2 .. 4096^2, 80% absorption = emission and 20% depth-sorted views,
+    random poses and looks.  Returns the closed-loop capacity of one call per
+    view, the server's closed-loop throughput, and p50/p99 latency of both
+    under Poisson arrivals at each rate (a multiple of the one-call-per-view
+    capacity)."""
     from paper_1606_04427_amd import serve, synth
 
-    n = args.n or 100_000_000
     t = time.time()
     ps = synth.soneira_peebles(n, seed=1004, absorption=True)
-    log(f"generated {ps.n} particles in {time.time() - t:.1f} s")
+    log(f"serving: generated {ps.n} particles in {time.time() - t:.1f} s")
     dev = "cuda:0"
-    parts = B.DeviceParticles(ps, dev, "f32")
+    up = B.Context(0)
+    ds = B.Dataset(up, ps, "f32")
     bank = []
     for k in range(8):
         looks, pals = looks_for(ps, scale=1.0 + 0.25 * k, palette_offset=k)
         bank.append((B.Palettes(pals, dev), looks))
+    del ps
     sizes = [256, 512, 1024, 2048, 4096]
     rng = np.random.Generator(np.random.PCG64(41))
 
@@ -705,63 +809,81 @@ def run_serving(args, torch, B):
             out.append(serve.Request(base + k, pose, mode, look=int(rng.integers(8))))
         return out
 
-    cost = lambda r: serve.request_bytes(parts.n, r.pose.width, r.pose.height,
-                                         r.mode == B.SPL_SORTED)
+    cost = lambda r: serve.request_cost(ds.n, r.pose.width, r.pose.height,
+                                        r.mode == B.SPL_SORTED)
     keep = lambda r: False
-    result = {}
+    result = {"n_particles": ds.n, "workers": workers, "budget_bytes": args.budget,
+              "max_views": args.max_views}
     # plain path: one request per call on one stream, closed loop (capacity)
-    ex = serve.GpuExecutor(parts, bank)
+    ex = serve.GpuExecutor(ds, bank)
     warm = make(args.warm_requests, 10_000)
     for r in warm:
         r.pose.width = r.pose.height = max(sizes)
     serve.one_per_call(ex, warm, keep=keep)
-    base = serve.one_per_call(ex, make(args.requests, 20_000), keep=keep)
-    cap = serve.summary(base)
+    cap = serve.summary(serve.one_per_call(ex, make(n_requests, 20_000), keep=keep))
     result["one_per_call_closed_loop"] = cap
     log(f"one per call, closed loop: {cap}")
     capacity = cap["frames_per_s"]
-
-    def server():
-        return serve.Server(lambda w: serve.GpuExecutor(parts, bank, batch_bytes=args.budget),
-                            n_workers=args.workers, budget_bytes=args.budget,
-                            max_views=args.max_views, cost=cost, keep=keep).start()
-
-    srv = server()
+    srv = serve.Server(lambda w: serve.GpuExecutor(ds, bank,
+                                                   batch_bytes=args.budget // workers),
+                       n_workers=workers, budget_bytes=args.budget, max_views=args.max_views,
+                       cost=cost, keep=keep).start()
     # warm-up: full batches of the largest views on every worker, so the
     # workspaces reach their final size before timing
-    warm = make(args.workers * args.max_views, 30_000)
+    warm = make(workers * args.max_views, 30_000)
     for r in warm:
         r.pose.width = r.pose.height = max(sizes)
     serve.drive(srv, warm, np.zeros(len(warm)))
-    reqs = make(args.requests, 40_000)
+    reqs = make(n_requests, 40_000)
     serve.drive(srv, reqs, np.zeros(len(reqs)))
     closed = serve.summary(reqs)
     closed["batches"] = srv.n_batches
     result["server_closed_loop"] = closed
     log(f"server, closed loop: {closed}")
-    for frac in args.rates:
+    for frac in rates:
         rate = frac * capacity
-        arr = synth.poisson_arrivals(args.requests, rate, seed=int(1000 * frac))
-        reqs = make(args.requests, int(50_000 + 10_000 * frac))
+        arr = synth.poisson_arrivals(n_requests, rate, seed=int(1000 * frac))
+        reqs = make(n_requests, int(50_000 + 10_000 * frac))
         serve.drive(srv, reqs, arr)
-        s = serve.summary(reqs)
-        s["offered_rate"] = rate
-        result[f"server_poisson_{frac:g}x"] = s
-        log(f"server at {frac:g} x capacity: {s}")
-        reqs = make(args.requests, int(60_000 + 10_000 * frac))
+        s_ = serve.summary(reqs)
+        s_["offered_rate"] = rate
+        result[f"server_poisson_{frac:g}x"] = s_
+        log(f"server at {frac:g} x capacity: {s_}")
+        reqs = make(n_requests, int(60_000 + 10_000 * frac))
         b = serve.summary(serve.one_per_call(ex, reqs, arr, keep=keep))
         b["offered_rate"] = rate
         result[f"one_per_call_poisson_{frac:g}x"] = b
         log(f"one per call at {frac:g} x capacity: {b}")
+    result["trims"] = srv.n_trims
+    result["peak_accounted_bytes"] = srv.peak_reserved
     srv.stop()
     ex.close()
-    value = closed["frames_per_s"]
+    result["speedup_vs_one_per_call"] = closed["frames_per_s"] / capacity
+    ds.close()
+    up.close()
+    return result
+
+
+def serving_leg(args, torch, B):
+    """The serving sub-record of the default line: 100M resident particles,
+    closed-loop throughput and p50/p99 at 1.0x the one-call-per-view
+    capacity."""
+    torch.cuda.empty_cache()
+    return serving_experiment(args, torch, B, args.serving_n, args.serving_requests, [1.0],
+                              args.workers)
+
+
+def run_serving(args, torch, B):
+    result = serving_experiment(args, torch, B, args.n or 100_000_000, args.requests, args.rates,
+                                args.workers)
+    value = result["server_closed_loop"]["frames_per_s"]
     out = base_record(args, value, 1e3 / value, "f32", {
-        "workload": f"serving: {ps.n} resident clustered particles, views 256^2..4096^2, "
-                    "80% additive / 20% depth-sorted, 8 looks", "n_particles": ps.n,
-        "workers": args.workers, "budget_bytes": args.budget, "max_views": args.max_views})
+        "workload": f"serving: {result['n_particles']} resident clustered particles, views "
+                    "256^2..4096^2, 80% additive / 20% depth-sorted, 8 looks",
+        "n_particles": result["n_particles"], "workers": args.workers,
+        "budget_bytes": args.budget, "max_views": args.max_views})
     out["unit"] = "frames/s"
-    out["speedup_vs_one_per_call"] = value / capacity
+    out["speedup_vs_one_per_call"] = result["speedup_vs_one_per_call"]
     out["serving"] = result
     return out
 
@@ -780,6 +902,13 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="additive: fixed tile (no autotune)")
     ap.add_argument("--cut", type=float, default=32.0, help="additive: fixed large cut with --tile")
     ap.add_argument("--no-probe", action="store_true", help="additive: skip the bandwidth probe")
+    ap.add_argument("--no-stream", action="store_true", help="additive: skip out-of-core rendering")
+    ap.add_argument("--stream-chunk", type=int, default=2_500_000,
+                    help="additive: particles per out-of-core chunk")
+    ap.add_argument("--no-cut-table", action="store_true",
+                    help="additive: skip the per-pose frame times at each large cut")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="additive: skip the serving sub-record")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="additive: skip the timing of the captured-graph replay")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -789,7 +918,11 @@ def main():
     ap.add_argument("--error-views", type=int, default=4, help="batched: views checked")
     ap.add_argument("--requests", type=int, default=150, help="serving: requests per run")
     ap.add_argument("--warm-requests", type=int, default=20)
-    ap.add_argument("--workers", type=int, default=2)
+    ap.add_argument("--workers", type=int, default=1)
+    ap.add_argument("--serving-n", type=int, default=100_000_000,
+                    help="additive: particles of the serving sub-record")
+    ap.add_argument("--serving-requests", type=int, default=60,
+                    help="additive: requests per serving measurement")
     ap.add_argument("--max-views", type=int, default=16)
     ap.add_argument("--budget", type=int, default=48 << 30)
     ap.add_argument("--rates", type=float, nargs="*", default=[0.5, 0.8, 1.0, 1.2])
