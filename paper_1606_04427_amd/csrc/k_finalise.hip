@@ -18,6 +18,15 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, in
     p[i] = v;
 }
 
+// Small device-to-host read-back: one workgroup copies 32-bit words into
+// page-locked host memory mapped into the device's address space.  Kept off
+// the copy engines, so it never queues behind a large host-to-device copy on
+// another stream.
+__global__ __launch_bounds__(kBlock) void k_readback(const uint32_t *__restrict__ src,
+                                                     uint32_t *__restrict__ dst, int words) {
+  for (int i = threadIdx.x; i < words; i += kBlock) dst[i] = src[i];
+}
+
 __global__ void k_fill_f64(double *p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
 }
@@ -197,6 +206,13 @@ int blocks_for(int64_t n, int cap) {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 2048)), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_readback, dim3(1), dim3(kBlock), 0, s, static_cast<const uint32_t *>(src),
+                     static_cast<uint32_t *>(dst_mapped), (int)(bytes / 4));
   return hipGetLastError();
 }
 

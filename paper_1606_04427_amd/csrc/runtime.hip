@@ -93,8 +93,10 @@ struct spl_ctx {
       partial, fin, stats, totals, minmax, himg, chunk[2];
   hipStream_t copy_stream = nullptr;  // host-to-device copies of spl_render_stream
   hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
-  Totals *h_tot = nullptr;
+  Totals *h_tot = nullptr;   // page-locked host memory ...
   double *h_stats = nullptr;
+  void *m_tot = nullptr;     // ... and its device-side addresses, written by
+  void *m_stats = nullptr;   // the read-back kernel
   int64_t bytes = 0;
   // autotuner choices: per (n, W, H, mode, camera pose), and the most
   // recent choice per (n, W, H, mode) for poses that were not tuned
@@ -114,6 +116,7 @@ struct spl_ctx {
   ViewK *h_views = nullptr;
   uint32_t *h_ctr = nullptr;
   double *h_bstats = nullptr;
+  void *m_btot = nullptr, *m_bstats = nullptr;  // device-side addresses
   int h_cap = 0;  // views the pinned host arrays hold
   bool graphs = false;
   hipStream_t cap_stream = nullptr;   // capture stream for batch graphs
@@ -489,7 +492,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   const int minc[3] = {1, 1, kSortChunk + 1};
   HIPTRY(c, launch_scan(counts, nb, tk.n_tiles, offsets, cursor, chunk, cchunk, minc, item_off, tot, s));
   mark(tf, 3, s);
-  HIPTRY(c, hipMemcpyAsync(c->h_tot, tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, launch_readback(tot, c->m_tot, sizeof(Totals), s));
   HIPTRY(c, hipStreamSynchronize(s));
   if (c->timing) resolve_timing(c, false);
   const Totals T = *c->h_tot;
@@ -582,8 +585,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   }
   if (st) {
     if (f.finish || f.flux_check) {
-      HIPTRY(c, hipMemcpyAsync(c->h_stats, c->stats.p, kStatWords * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
+      HIPTRY(c, launch_readback(c->stats.p, c->m_stats, kStatWords * sizeof(double), s));
       HIPTRY(c, hipStreamSynchronize(s));
     }
     st->n_active = (int64_t)T.n_active;
@@ -685,6 +687,9 @@ spl_status ensure_host(spl_ctx *c, int views) {
       hipHostMalloc((void **)&c->h_bstats, kStatWords * sizeof(double) * views,
                     hipHostMallocDefault) != hipSuccess)
     return fail(c, SPL_ENOMEM, "pinned host allocation failed");
+  if (hipHostGetDevicePointer(&c->m_btot, c->h_btot, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&c->m_bstats, c->h_bstats, 0) != hipSuccess)
+    return fail(c, SPL_EDEVICE, "device address of pinned host memory unavailable");
   c->h_cap = views;
   return SPL_OK;
 }
@@ -740,7 +745,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   mark(tf, 1, s);
   mark(tf, 2, s);
   mark(tf, 3, s);
-  HIPTRY(c, hipMemcpyAsync(c->h_btot, tot, sizeof(Totals) * nv, hipMemcpyDeviceToHost, s));
+  HIPTRY(c, launch_readback(tot, c->m_btot, sizeof(Totals) * nv, s));
   HIPTRY(c, hipStreamSynchronize(s));
   // item length: the long items when there are enough of them for every
   // resident workgroup of the persistent splat
@@ -918,8 +923,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   bool any_stats = false;
   for (int v = 0; v < nv; ++v) any_stats = any_stats || st[v];
   if (any_stats) {
-    HIPTRY(c, hipMemcpyAsync(c->h_bstats, stats, kStatWords * sizeof(double) * nv,
-                             hipMemcpyDeviceToHost, s));
+    HIPTRY(c, launch_readback(stats, c->m_bstats, kStatWords * sizeof(double) * nv, s));
     HIPTRY(c, hipStreamSynchronize(s));
     for (int v = 0; v < nv; ++v) {
       if (!st[v]) continue;
@@ -1339,8 +1343,7 @@ spl_status render_stream(spl_ctx *c, const spl_particles *hp, int64_t chunk,
   // the map, the FP64 reductions and the normalisation, once, on the sum
   TRY(finish_image(c, img, npx, prm->mode, prm->normalise, s));
   if (st) {
-    HIPTRY(c, hipMemcpyAsync(c->h_stats, c->stats.p, kStatWords * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
+    HIPTRY(c, launch_readback(c->stats.p, c->m_stats, kStatWords * sizeof(double), s));
     HIPTRY(c, hipStreamSynchronize(s));
     *st = acc;
     for (int ch = 0; ch < 3; ++ch) {
@@ -1401,6 +1404,14 @@ spl_status spl_create(int device, spl_ctx **out) {
     if (c->h_tot) (void)hipHostFree(c->h_tot);
     delete c;
     return SPL_ENOMEM;
+  }
+  if (hipHostGetDevicePointer(&c->m_tot, c->h_tot, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&c->m_stats, c->h_stats, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipHostFree(c->h_tot);
+    (void)hipHostFree(c->h_stats);
+    delete c;
+    return SPL_EDEVICE;
   }
   *out = c;
   return SPL_OK;
@@ -1553,7 +1564,7 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
   uint32_t *item_off = (uint32_t *)c->item_off.p;
   HIPTRY(c, launch_scan(counts, nb, nb, offsets, (uint32_t *)c->cursor.p, chunk, cchunk, minc,
                         item_off, tot, s));
-  HIPTRY(c, hipMemcpyAsync(c->h_tot, tot, sizeof(Totals), hipMemcpyDeviceToHost, s));
+  HIPTRY(c, launch_readback(tot, c->m_tot, sizeof(Totals), s));
   HIPTRY(c, hipStreamSynchronize(s));
   const Totals T = *c->h_tot;
   if (T.n_pairs >= 0xffffffffull) return fail(c, SPL_EUNSUPPORTED, "too many list entries");

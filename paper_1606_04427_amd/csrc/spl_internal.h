@@ -184,6 +184,9 @@ __host__ __device__ __forceinline__ int merge_passes(uint32_t c, uint32_t k0) {
 // Launch wrappers (each returns hipSuccess or the launch error).
 // ---------------------------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+// Copies bytes (a multiple of 4) from device memory into page-locked host
+// memory through its device-side address, with a kernel.
+hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 
 // With counts != NULL and project_counts(tk), the projection also adds the

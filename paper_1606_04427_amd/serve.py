@@ -4,9 +4,11 @@ Continuous batching: requests queue as they arrive.  Each of `n_workers`
 workers owns one library context and one HIP stream.  Whenever a worker is
 free it takes, in arrival order, the queued requests that fit its view-slot
 limit and the memory budget (the head of the queue waits when it does not
-fit), renders them with one `spl_render_batch` call and releases their memory
-as soon as the images are ready.  With two or more workers, requests admitted
-while another batch is on the GPU run beside it on the device.
+fit), renders them (one batched call for a set small enough that one view
+does not fill the device, else view by view with each request completed as
+its image is ready) and releases their memory as soon as the images are
+ready.  With two or more workers, requests admitted while another batch is on
+the GPU run beside it on the device.
 
 The scheduler is independent of the GPU: it drives any executor with a
 `run(requests) -> (images, stats)` method, so its admission and ordering logic
@@ -234,25 +236,45 @@ class Server:
                 t = self.clock()
                 for r in batch:
                     r.admitted, r.batch, r.worker = t, seq, w
+                finished = set()
+
+                def done(r, im, st):
+                    # a request completes as soon as its image is ready (an
+                    # executor that renders view by view reports each one)
+                    t_done = self.clock()
+                    r.stats = st
+                    r.error = None
+                    r.image = im if self.keep(r) else None
+                    with self.cv:
+                        r.done = t_done
+                        self.reserved -= r.img_bytes
+                        self.in_flight -= 1
+                        self.completed.append(r)
+                        finished.add(r.rid)
+                        self.cv.notify_all()
+
                 try:
-                    images, stats = ex.run(batch)
+                    if getattr(ex, "run_each", None):
+                        ex.run_each(batch, done)
+                    else:
+                        images, stats = ex.run(batch)
+                        for r, im, st in zip(batch, images, stats):
+                            done(r, im, st)
                     err = None
-                except Exception as e:  # a failed batch fails its requests only
-                    images, stats, err = [None] * len(batch), [None] * len(batch), repr(e)
+                except Exception as e:  # a failed batch fails its unfinished requests only
+                    err = repr(e)
                 held = getattr(ex, "workspace_bytes", None)
                 t = self.clock()
-                for r, im, st in zip(batch, images, stats):
-                    r.stats = st
-                    r.error = err
-                    r.image = im if self.keep(r) else None
                 with self.cv:
                     for r in batch:
-                        r.done = t
-                    self.reserved -= sum(r.img_bytes for r in batch)
+                        if r.rid in finished:
+                            continue
+                        r.stats, r.error, r.image, r.done = None, err, None, t
+                        self.reserved -= r.img_bytes
+                        self.in_flight -= 1
+                        self.completed.append(r)
                     self.held[w] = int(held()) if held else self.planned[w]
                     self.planned[w] = 0
-                    self.in_flight -= len(batch)
-                    self.completed.extend(batch)
                     self.cv.notify_all()
         except BaseException as e:
             with self.cv:
@@ -312,12 +334,20 @@ def summary(requests) -> dict:
 class GpuExecutor:
     """Renders batches through the HIP library on its own context and stream,
     from a data set resident in device memory (binding.Dataset, shared by every
-    worker).  A batch of one view takes the single-view call.
+    worker).
+
+    A set of at most `batch_particles` particles renders a batch with one
+    batched call (one persistent splat launch for all its views: a view of a
+    small set does not fill the device alone).  A larger set renders the
+    batch's views one call each and completes every request as soon as its own
+    image is ready (run_each): one view of such a set already fills the
+    device, so the batched call saves nothing and would hold every result
+    until the last view of the batch is done.
 
     bank: list of (Palettes, looks) pairs, indexed by Request.look."""
 
     def __init__(self, ds, bank, device: str = "cuda:0", batch_bytes: int | None = None,
-                 graphs: bool = False):
+                 graphs: bool = False, batch_particles: int = 32_000_000):
         import torch
 
         from . import binding as B
@@ -331,6 +361,8 @@ class GpuExecutor:
             self.ctx.spl_set_option(B.SPL_OPT_BATCH_BYTES, int(batch_bytes))
         self.ctx.spl_set_option(B.SPL_OPT_GRAPHS, int(graphs))
         self._params = {}
+        if ds.n > batch_particles:
+            self.run_each = self._run_each
 
     def params(self, mode, look):
         key = (mode, look)
@@ -352,6 +384,16 @@ class GpuExecutor:
                     self.ds, [r.pose for r in reqs], [self.params(r.mode, r.look) for r in reqs])
         self.stream.synchronize()
         return outs, sts
+
+    def _run_each(self, reqs, done):
+        import torch
+
+        for r in reqs:
+            with torch.cuda.stream(self.stream):
+                out, st = self.ctx.spl_render_dataset(self.ds, r.pose,
+                                                      self.params(r.mode, r.look))
+            self.stream.synchronize()
+            done(r, out, st)
 
     def workspace_bytes(self) -> int:
         return self.ctx.workspace_bytes()

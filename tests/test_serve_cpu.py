@@ -256,3 +256,46 @@ def test_a_request_larger_than_the_budget_with_workspace_is_rejected():
     serve.drive(srv, [r], np.zeros(1))
     srv.stop()
     assert r.error and "budget" in r.error
+
+
+class EachExecutor:
+    """Fake executor that renders view by view and reports each request as
+    it completes; fails at request fail_on."""
+
+    def __init__(self, per_view=0.01, fail_on=None):
+        self.per_view, self.fail_on = per_view, fail_on
+
+    def run_each(self, reqs, done):
+        for r in reqs:
+            if r.rid == self.fail_on:
+                raise RuntimeError("injected")
+            time.sleep(self.per_view)
+            done(r, f"img{r.rid}", {"rid": r.rid})
+
+
+def test_requests_complete_one_by_one_inside_a_batch():
+    srv = serve.Server(lambda w: EachExecutor(), n_workers=1, max_views=8).start()
+    reqs = _reqs(6)
+    serve.drive(srv, reqs, np.zeros(6))
+    srv.stop()
+    assert all(r.image == f"img{r.rid}" for r in reqs)
+    one_batch = [r for r in reqs if r.batch == reqs[-1].batch]
+    assert len(one_batch) > 2
+    done = [r.done for r in one_batch]
+    assert done == sorted(done) and done[-1] - done[0] >= 0.01 * (len(one_batch) - 1) * 0.9
+    assert srv.reserved == 0 and srv.in_flight == 0
+
+
+def test_a_failure_inside_a_batch_fails_only_the_unfinished_requests():
+    srv = serve.Server(lambda w: EachExecutor(per_view=0.002, fail_on=3), n_workers=1,
+                       max_views=8).start()
+    reqs = _reqs(6)
+    serve.drive(srv, reqs, np.zeros(6))
+    srv.stop()
+    batch_of_3 = reqs[3].batch
+    for r in reqs:
+        if r.batch == batch_of_3 and r.rid >= 3:
+            assert r.error and "injected" in r.error
+        else:
+            assert r.error is None and r.image == f"img{r.rid}"
+    assert srv.reserved == 0 and srv.in_flight == 0
