@@ -418,6 +418,9 @@ def run_additive(args, torch, B):
                     "large_cut": s["large_cut"]} for s in bstats],
     })
     parts.close()
+    if not args.no_sorted_leg:
+        out["sorted"] = sorted_leg(args, torch, B, ctx)
+        log("sorted: " + json.dumps({k: v for k, v in out["sorted"].items() if k != "stages"}))
     ctx.close()
     if not args.no_serving:
         out["serving"] = serving_leg(args, torch, B)
@@ -429,6 +432,35 @@ def run_additive(args, torch, B):
             ps, poses, looks, pals, args.cpu_sample or 5_000_000, B.SPL_ADD_AEQE)
         log(f"cpu baseline in {time.time() - t:.1f} s")
     return out
+
+
+def sorted_leg(args, torch, B, ctx):
+    """The depth-sorted transfer config: the same clustered set with
+    absorption U[0.01, 0.5], one 2048 x 2048 view (the first pose), tuned
+    tile; particles/s, stage times and the dominant kernel's roofline."""
+    ps, poses, looks, pals = workload(args.n or 10_000_000, width=2048, height=2048,
+                                      absorption=True)
+    parts = B.Dataset(ctx, ps, "f32")
+    prm = B.make_params(B.SPL_SORTED, B.Palettes(pals), looks)
+    pose = poses[0]
+    tile = None if args.no_autotune else ctx.spl_autotune(parts, pose, prm)[0]
+    img = torch.empty((pose.height, pose.width, 3), dtype=torch.float32, device="cuda:0")
+
+    def step():
+        ctx.spl_render_dataset(parts, pose, prm, out=img, stats=False)
+
+    elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
+    st = ctx.spl_render_dataset(parts, pose, prm, out=img)[1]
+    roof = roofline_for(B, ms, by, frames)
+    if roof["kernel"] == "k_splat_add":
+        roof["kernel"] = "k_composite"  # the sorted mode's splat stage
+    parts.close()
+    return {"workload": f"{ps.n} clustered particles with absorption U[0.01,0.5], 2048x2048, "
+                        "depth-sorted transfer, FP32",
+            "particles_per_s": args.steps * ps.n / elapsed,
+            "ms_per_frame": 1e3 * elapsed / args.steps, "tile": st["tile"],
+            "n_active": st["n_active"], "n_pairs": st["n_pairs"], "roofline": roof,
+            "stages": stage_table(B, ms, by, frames)}
 
 
 def stream_leg(args, torch, B, ctx, ps, pose, prm, parts):
@@ -947,6 +979,8 @@ def main():
                     help="additive: skip the per-pose frame times at each large cut")
     ap.add_argument("--no-serving", action="store_true",
                     help="additive: skip the serving sub-record")
+    ap.add_argument("--no-sorted-leg", action="store_true",
+                    help="additive: skip the depth-sorted sub-record")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="additive: skip the timing of the captured-graph replay")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
