@@ -826,7 +826,8 @@ def serving_experiment(args, torch, B, n, n_requests, rates, workers):
     random poses and looks.  Returns the closed-loop capacity of one call per
     view, the server's closed-loop throughput, and p50/p99 latency of both
     under Poisson arrivals at each rate (a multiple of the one-call-per-view
-    capacity)."""
+    capacity).  Each comparison runs the same list of views through both
+    paths."""
     from paper_1606_04427_amd import serve, synth
 
     t = time.time()
@@ -852,6 +853,11 @@ def serving_experiment(args, torch, B, n, n_requests, rates, workers):
             out.append(serve.Request(base + k, pose, mode, look=int(rng.integers(8))))
         return out
 
+    def fresh(reqs):
+        """The same views (pose, size, mode, look) as new requests, so that
+        the server and the plain path are timed on identical work."""
+        return [serve.Request(r.rid, r.pose, r.mode, look=r.look) for r in reqs]
+
     cost = lambda r: serve.request_cost(ds.n, r.pose.width, r.pose.height,
                                         r.mode == B.SPL_SORTED)
     keep = lambda r: False
@@ -863,7 +869,8 @@ def serving_experiment(args, torch, B, n, n_requests, rates, workers):
     for r in warm:
         r.pose.width = r.pose.height = max(sizes)
     serve.one_per_call(ex, warm, keep=keep)
-    cap = serve.summary(serve.one_per_call(ex, make(n_requests, 20_000), keep=keep))
+    closed_set = make(n_requests, 20_000)
+    cap = serve.summary(serve.one_per_call(ex, fresh(closed_set), keep=keep))
     result["one_per_call_closed_loop"] = cap
     log(f"one per call, closed loop: {cap}")
     capacity = cap["frames_per_s"]
@@ -880,7 +887,7 @@ def serving_experiment(args, torch, B, n, n_requests, rates, workers):
     for r in warm:
         r.pose.width = r.pose.height = max(sizes)
     serve.drive(srv, warm, np.zeros(len(warm)))
-    reqs = make(n_requests, 40_000)
+    reqs = fresh(closed_set)
     serve.drive(srv, reqs, np.zeros(len(reqs)))
     closed = serve.summary(reqs)
     closed["batches"] = srv.n_batches
@@ -889,14 +896,14 @@ def serving_experiment(args, torch, B, n, n_requests, rates, workers):
     for frac in rates:
         rate = frac * capacity
         arr = synth.poisson_arrivals(n_requests, rate, seed=int(1000 * frac))
-        reqs = make(n_requests, int(50_000 + 10_000 * frac))
+        views = make(n_requests, int(50_000 + 10_000 * frac))
+        reqs = fresh(views)
         serve.drive(srv, reqs, arr)
         s_ = serve.summary(reqs)
         s_["offered_rate"] = rate
         result[f"server_poisson_{frac:g}x"] = s_
         log(f"server at {frac:g} x capacity: {s_}")
-        reqs = make(n_requests, int(60_000 + 10_000 * frac))
-        b = serve.summary(serve.one_per_call(ex, reqs, arr, keep=keep))
+        b = serve.summary(serve.one_per_call(ex, fresh(views), arr, keep=keep))
         b["offered_rate"] = rate
         result[f"one_per_call_poisson_{frac:g}x"] = b
         log(f"one per call at {frac:g} x capacity: {b}")
