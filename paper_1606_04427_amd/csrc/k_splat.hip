@@ -44,24 +44,28 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
 
 // A batch of up to 256 list entries is staged in LDS (offsets, width,
 // premultiplied colour).  The tile is split into 4 x 4 micro-tiles and each
-// staged entry appends itself to the list of every micro-tile its box meets
-// (LDS integer atomics; order inside a list is free for a sum).  The lists,
-// laid end to end, are cut into 32 ranges whose lengths differ by at most
-// one, one per 8-lane group; all groups step through their ranges together,
-// one list entry per step, so the eight groups of a wave, which run in
-// lockstep, take the same number of steps however unevenly the entries fall
-// on the micro-tiles.  The per-step work is one compare for the end of the
-// current list, the entry's staging offset and the Gaussian; the step that
-// only the longer ranges take is peeled off the loop.  Two pixels per lane,
-// rows r and r + 2 of one micro-tile column: the entry read from LDS and the
-// horizontal distance serve both (LDS reads, not the vector ALU alone, bound
-// the walk).  The running sums stay in registers while consecutive entries
-// belong to the same micro-tile and are added into a 32-bit fixed-point LDS
-// accumulator (integer atomics: neighbouring ranges may share a micro-tile)
-// when the group moves on.  The batch scale 2^S keeps the batch's summed peak
-// amplitude below 2^30, so no pixel sum overflows.  After each batch the
-// integer sums are folded into per-pixel Neumaier-compensated FP32 sums in
-// registers.
+// staged entry appends itself to the list of every micro-tile its truncation
+// disc can reach (LDS integer atomics; order inside a list is free for a
+// sum).  Those micro-tiles are found row by row: the disc's half-width at the
+// row band of micro-tiles gives the interval of micro-tile columns, so one
+// square root per row band replaces a test per micro-tile, and the appends
+// run over the set bits of the resulting mask.  The lists, laid end to end,
+// are cut into 32 ranges whose lengths differ by at most one, one per 8-lane
+// group; all groups step through their ranges together, one list entry per
+// step, so the eight groups of a wave, which run in lockstep, take the same
+// number of steps however unevenly the entries fall on the micro-tiles.  The
+// per-step work is one compare for the end of the current list, the entry's
+// staging offset and the Gaussian; the step that only the longer ranges take
+// is peeled off the loop.  Two pixels per lane, rows r and r + 2 of one
+// micro-tile column: the entry read from LDS and the horizontal distance
+// serve both (LDS reads, not the vector ALU alone, bound the walk).  The
+// running sums stay in registers while consecutive entries belong to the same
+// micro-tile and are added into a 32-bit fixed-point LDS accumulator (integer
+// atomics: neighbouring ranges may share a micro-tile) when the group moves
+// on to the next non-empty list.  The staged colours carry the batch scale
+// 2^S, which keeps the batch's summed peak amplitude below 2^30, so a flush
+// only rounds and no pixel sum overflows.  After each batch the integer sums
+// are folded into per-pixel FP64 sums in registers.
 template <int T>
 __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__restrict__ pairs,
                                                const float4 *__restrict__ rec,
@@ -73,9 +77,14 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   constexpr int NQ = MX * MX;          // micro-tiles per tile (16 or 64)
   constexpr float kLog2e = 1.4426950408889634f;
   constexpr float kRootLog2e = 1.2011224087864498f;  // sqrt(log2 e)
-  // with g = sqrt(log2 e)/sigma: Xi - x0, (0.5 - Xf) g, Yi - y0, (0.5 - Yf) g
-  __shared__ float4 s_pos[kBlock];
-  __shared__ float4 s_col[kBlock];     // g, premultiplied colour
+  constexpr float kHalfSpan = 0.5f * (float)(T - 1);  // tile centre, in pixels
+  // micro-tile masks: bit qy * MX + qx
+  using MT = typename std::conditional<(NQ > 32), uint64_t, uint32_t>::type;
+  // with g = sqrt(log2 e)/sigma and pixel positions taken from the tile
+  // centre (c = column - (T - 1)/2): the scaled offset g (x - X) of a pixel
+  // centre from the particle is g c + ox, and the same down the column
+  __shared__ float4 s_pos[kBlock];     // ox, oy, g, red x 2^S
+  __shared__ float4 s_col[kBlock];     // green, blue x 2^S (first two words)
   // list entries: byte offsets into s_pos / s_col (16-bit, 16 px tiles) or
   // staging slots (8-bit, 32 px tiles, where the lists take 4x the LDS)
   using LT = typename std::conditional<T == 16, uint16_t, uint8_t>::type;
@@ -83,6 +92,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   __shared__ __align__(4) LT s_list[NQ][kBlock];
   __shared__ int s_len[2][NQ];         // list lengths; batches alternate buffers
   __shared__ int s_start[NQ + 1];      // list offsets laid end to end
+  __shared__ int s_next[NQ];           // next non-empty list after each list
   __shared__ int s_iacc[3][NP];        // batch sums, fixed point
   __shared__ float s_amp[4];           // per-wave summed peak amplitudes
 
@@ -95,14 +105,11 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   const int lx = l & 3, ly = l >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
 
-  float sum[PX][3], comp[PX][3];
+  double acc[PX][3];
 #pragma unroll
   for (int m = 0; m < PX; ++m)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      sum[m][c] = 0.f;
-      comp[m][c] = 0.f;
-    }
+    for (int c = 0; c < 3; ++c) acc[m][c] = 0.0;
   for (int i = tid; i < 3 * NP; i += kBlock) (&s_iacc[0][0])[i] = 0;
   if (tid < 2 * NQ) (&s_len[0][0])[tid] = 0;
   __syncthreads();
@@ -111,49 +118,66 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   for (uint32_t base = it.y; base < it.z; base += kBlock, cur ^= 1) {
     int *const len = s_len[cur];
     // stage one list entry per lane, append it to the list of every
-    // micro-tile its box meets, sum the peak amplitudes
+    // micro-tile its disc reaches, sum the peak amplitudes.  Listed records
+    // are finite with sigma > 0 (the binning lists no other).
     const uint32_t k = base + tid;
     float amax = 0.f;
+    float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float g = 0.f, ox = 0.f, oy = 0.f;
     if (k < it.z) {
       const uint32_t pid = pairs[k];
       const float4 r0 = rec[2 * (size_t)pid];
-      const float4 r1 = rec[2 * (size_t)pid + 1];
-      int i0, i1, j0, j1;
-      if (record_box(r0.x, r0.y, r0.z, r0.w, r1.x, tk.nu, tk.W, tk.H, i0, i1, j0, j1)) {
-        const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
-        const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
-        if (li0 <= li1 && lj0 <= lj1) {
-          const float g = kRootLog2e / r1.x;
-          s_pos[tid] = make_float4(r0.x - (float)x0, (0.5f - r0.y) * g, r0.z - (float)y0,
-                                   (0.5f - r0.w) * g);
-          s_col[tid] = make_float4(g, r1.y, r1.z, r1.w);
-          amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
-          // micro-tiles of the box whose pixel centres the truncation disc
-          // can reach (tested against the micro-tile's rectangle of pixel
-          // centres, with a margin over the evaluation's rounding)
-          const float ux = (r0.x - (float)x0) + (r0.y - 0.5f);
-          const float uy = (r0.z - (float)y0) + (r0.w - 0.5f);
-          const float rr = tk.nu * r1.x;
-          const float r2m = fmaf(rr * rr, 1.0001f, 1e-3f);
-          for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy) {
-            const float ey = fmaxf(fmaxf((float)(4 * qy) - uy, uy - (float)(4 * qy + 3)), 0.f);
-            const float ey2 = ey * ey;
-            for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
-              const float ex = fmaxf(fmaxf((float)(4 * qx) - ux, ux - (float)(4 * qx + 3)), 0.f);
-              if (fmaf(ex, ex, ey2) <= r2m) {
-                const int q = qy * MX + qx;
-                s_list[q][atomicAdd(&len[q], 1)] = (LT)(tid << (4 - kShift));
-              }
-            }
-          }
-        }
+      r1 = rec[2 * (size_t)pid + 1];
+      g = kRootLog2e * __builtin_amdgcn_rcpf(r1.x);
+      // the integer differences are exact; two roundings each
+      ox = fmaf(kHalfSpan - (r0.x - (float)x0), g, (0.5f - r0.y) * g);
+      oy = fmaf(kHalfSpan - (r0.z - (float)y0), g, (0.5f - r0.w) * g);
+      amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
+      // micro-tiles whose rectangle of pixel centres the truncation disc can
+      // reach, with a margin over the rounding of this test and of the
+      // evaluation.  Lengths in micro-tiles (4 px): the centre (cx, cy), the
+      // radius with margin rq; row band qy (pixel rows 4 qy .. 4 qy + 3) lies
+      // at ey = max(qy - cy, cy - qy - 3/4, 0) from the centre and is reached
+      // when ey <= rq, and then so are its columns a..b, those within
+      // sqrt(rq^2 - ey^2) the same way
+      const float cx = ((r0.x - (float)x0) + (r0.y - 0.5f)) * 0.25f;
+      const float cy = ((r0.z - (float)y0) + (r0.w - 0.5f)) * 0.25f;
+      const float rr = tk.nu * r1.x;
+      const float r2q = fmaf(rr * rr, 1.0001f, 1e-3f) * 0.0625f;
+      const float rq = __builtin_amdgcn_sqrtf(r2q);
+      const int qy0 = max((int)ceilf((cy - 0.75f) - rq), 0);
+      const int qy1 = min((int)floorf(cy + rq), MX - 1);
+      const float ca = cx - 0.75f;
+      MT mask = 0;
+      float fy = (float)qy0 - cy;
+      for (int qy = qy0; qy <= qy1; ++qy, fy += 1.f) {
+        const float ey = fmaxf(fmaxf(fy, -0.75f - fy), 0.f);
+        const float hw = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-ey, ey, r2q), 0.f));
+        const int a = max((int)ceilf(ca - hw), 0);
+        const int b = min((int)floorf(cx + hw), MX - 1);
+        if (a <= b) mask |= (MT)(((MT)1 << (b - a + 1)) - 1) << (a + qy * MX);
+      }
+      while (mask) {
+        const int q = NQ > 32 ? (int)__builtin_ctzll((unsigned long long)mask)
+                              : (int)__builtin_ctz((unsigned)mask);
+        mask &= mask - 1;
+        s_list[q][atomicAdd(&len[q], 1)] = (LT)(tid << (4 - kShift));
       }
     }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) amax += __shfl_xor(amax, o);
     if ((tid & 63) == 0) s_amp[wave] = amax;
     __syncthreads();
-    // list offsets (one wave: NQ <= 64)
+    int ex = 0;
+    (void)frexpf(s_amp[0] + s_amp[1] + s_amp[2] + s_amp[3], &ex);  // sum <= 2^ex
+    const int S = 30 - ex;
+    // colours scaled by 2^S (exact); only the walk, after the next barrier,
+    // reads them
+    if (k < it.z) {
+      s_pos[tid] = make_float4(ox, oy, g, ldexpf(r1.y, S));
+      *reinterpret_cast<float2 *>(&s_col[tid]) = make_float2(ldexpf(r1.z, S), ldexpf(r1.w, S));
+    }
+    // list offsets and the next non-empty list of each list (one wave: NQ <= 64)
     if (tid < 64) {
       const int v = tid < NQ ? len[tid] : 0;
       int incl = v;
@@ -162,13 +186,15 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         const int u = __shfl_up(incl, o);
         if (tid >= o) incl += u;
       }
-      if (tid < NQ) s_start[tid] = incl - v;
+      const unsigned long long full = __ballot(v > 0);
+      const unsigned long long later = tid < 63 ? full & (~0ull << (tid + 1)) : 0ull;
+      if (tid < NQ) {
+        s_start[tid] = incl - v;
+        s_next[tid] = later ? (int)__builtin_ctzll(later) : NQ;
+      }
       if (tid == NQ - 1) s_start[NQ] = incl;
     }
     __syncthreads();
-    int ex = 0;
-    (void)frexpf(s_amp[0] + s_amp[1] + s_amp[2] + s_amp[3], &ex);  // sum <= 2^ex
-    const int S = 30 - ex;
     {
       // the lists laid end to end are cut into 32 ranges whose lengths differ
       // by at most one: every group takes `steps` entries, the first `rem`
@@ -185,7 +211,8 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       int lp = q * kBlock + (r0 - s_start[q]);
       int le = q * kBlock + (s_start[q + 1] - s_start[q]);
       int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
-      float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
+      float px = (float)((q % MX) * 4 + lx) - kHalfSpan;
+      float py = (float)((q / MX) * 4 + ly) - kHalfSpan;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
       // steps in blocks of four read the list at entry b + u (u = 0..3,
       // an immediate offset from the byte offset bo of entry b); the end
@@ -195,34 +222,31 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       int bo = lp * kLB, d = le - lp;
       auto step = [&](const int u) {
         if (d == u) {
-          // next micro-tile: flush the running sums
-          atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
-          atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
-          atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
-          atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(ldexpf(b0, S)));
-          atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(ldexpf(b1, S)));
-          atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(ldexpf(b2, S)));
+          // next micro-tile: flush the running sums (already scaled by 2^S)
+          atomicAdd(&s_iacc[0][pix], (int)rintf(a0));
+          atomicAdd(&s_iacc[1][pix], (int)rintf(a1));
+          atomicAdd(&s_iacc[2][pix], (int)rintf(a2));
+          atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(b0));
+          atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(b1));
+          atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(b2));
           a0 = a1 = a2 = 0.f;
           b0 = b1 = b2 = 0.f;
-          do {
-            ++q;
-          } while (s_start[q + 1] == s_start[q]);
+          q = s_next[q];
           bo = (q * kBlock - u) * kLB;
           d = u + (s_start[q + 1] - s_start[q]);
           const int qx = (int)((unsigned)q % MX), qy = (int)((unsigned)q / MX);
           pix = qy * 4 * T + qx * 4 + ly * T + lx;
-          px = (float)(qx * 4 + lx);
-          py = (float)(qy * 4 + ly);
+          px = (float)(qx * 4 + lx) - kHalfSpan;
+          py = (float)(qy * 4 + ly) - kHalfSpan;
         }
         // byte offset of the entry's staging slot
         const int jb = (int)*reinterpret_cast<const LT *>(s_lb + bo + u * kLB) << kShift;
         const float4 p = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_pos) + jb);
-        const float4 c = *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(s_col) + jb);
-        // distances in units of sigma / sqrt(log2 e): the integer
-        // difference is exact, the FMA rounds once
-        const float dx = fmaf(px - p.x, c.x, p.y);
-        const float dy = fmaf(py - p.z, c.x, p.w);
-        const float dz = fmaf((py + 2.f) - p.z, c.x, p.w);
+        const float2 c = *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(s_col) + jb);
+        // distances in units of sigma / sqrt(log2 e); two rows down adds 2 g
+        const float dx = fmaf(px, p.z, p.x);
+        const float dy = fmaf(py, p.z, p.y);
+        const float dz = fmaf(2.f, p.z, dy);
         const float dx2 = dx * dx;
         const float qq = fmaf(dy, dy, dx2);
         const float qz = fmaf(dz, dz, dx2);
@@ -230,12 +254,12 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         // the hardware exponential needs no range fix-up
         const float e = (qq <= qmax) ? __builtin_amdgcn_exp2f(-qq) : 0.f;
         const float f = (qz <= qmax) ? __builtin_amdgcn_exp2f(-qz) : 0.f;
-        a0 += c.y * e;
-        a1 += c.z * e;
-        a2 += c.w * e;
-        b0 += c.y * f;
-        b1 += c.z * f;
-        b2 += c.w * f;
+        a0 += p.w * e;
+        a1 += c.x * e;
+        a2 += c.y * e;
+        b0 += p.w * f;
+        b1 += c.x * f;
+        b2 += c.y * f;
       };
       int t = 0;
       for (; t + 4 <= steps; t += 4) {  // uniform across the workgroup
@@ -253,19 +277,19 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       }
       if (grp < rem) step(0);
       if (steps > 0 || grp < rem) {
-        atomicAdd(&s_iacc[0][pix], (int)rintf(ldexpf(a0, S)));
-        atomicAdd(&s_iacc[1][pix], (int)rintf(ldexpf(a1, S)));
-        atomicAdd(&s_iacc[2][pix], (int)rintf(ldexpf(a2, S)));
-        atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(ldexpf(b0, S)));
-        atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(ldexpf(b1, S)));
-        atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(ldexpf(b2, S)));
+        atomicAdd(&s_iacc[0][pix], (int)rintf(a0));
+        atomicAdd(&s_iacc[1][pix], (int)rintf(a1));
+        atomicAdd(&s_iacc[2][pix], (int)rintf(a2));
+        atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(b0));
+        atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(b1));
+        atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(b2));
       }
     }
     // the other length buffer was last read before the previous batch's
     // final barrier and is next written after this batch's
     if (tid < NQ) s_len[cur ^ 1][tid] = 0;
     __syncthreads();
-    // fold the batch sums into the compensated per-pixel sums
+    // fold the batch sums into the per-pixel FP64 sums
 #pragma unroll
     for (int m = 0; m < PX; ++m) {
       const int p2 = tid + m * kBlock;
@@ -273,7 +297,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       for (int c = 0; c < 3; ++c) {
         const int v = s_iacc[c][p2];
         s_iacc[c][p2] = 0;
-        neumaier(sum[m][c], comp[m][c], ldexpf((float)v, -S));
+        acc[m][c] += ldexp((double)v, -S);
       }
     }
     __syncthreads();
@@ -286,7 +310,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       float *o = img + 3 * ((size_t)gy * tk.W + gx);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float v = sum[m][c] + comp[m][c];
+        const float v = (float)acc[m][c];
         if (multi)
           unsafeAtomicAdd(o + c, v);
         else
