@@ -38,6 +38,13 @@ __device__ __forceinline__ void neumaier(float &sum, float &comp, float v) {
   sum = t;
 }
 
+// Nearest integer, halves rounded up (one instruction: floor(x + 0.5)).
+__device__ __forceinline__ int round_half_up(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
   return (uint32_t)a0 | ((uint32_t)a1 << 8) | ((uint32_t)b0 << 16) | ((uint32_t)b1 << 24);
 }
@@ -92,7 +99,10 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   __shared__ __align__(4) LT s_list[NQ][kBlock];
   __shared__ int s_len[2][NQ];         // list lengths; batches alternate buffers
   __shared__ int s_start[NQ + 1];      // list offsets laid end to end
-  __shared__ int s_next[NQ];           // next non-empty list after each list
+  // per list, the next non-empty list: its byte offset in s_list, length,
+  // byte offset of its first pixel in s_iacc, own offset in this table; then
+  // its first pixel's centred column and row (floats)
+  __shared__ int4 s_nx[2 * NQ];
   __shared__ int s_iacc[3][NP];        // batch sums, fixed point
   __shared__ float s_amp[4];           // per-wave summed peak amplitudes
 
@@ -188,9 +198,16 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       }
       const unsigned long long full = __ballot(v > 0);
       const unsigned long long later = tid < 63 ? full & (~0ull << (tid + 1)) : 0ull;
+      // (a list with no later non-empty list is never left mid-walk)
+      const int nq = later ? (int)__builtin_ctzll(later) : 0;
+      const int nv = __shfl(v, nq);
       if (tid < NQ) {
         s_start[tid] = incl - v;
-        s_next[tid] = later ? (int)__builtin_ctzll(later) : NQ;
+        const int nqx = nq % MX, nqy = nq / MX;
+        s_nx[2 * tid] = make_int4(nq * kBlock * (int)sizeof(LT), nv,
+                                  4 * (nqy * 4 * T + nqx * 4), nq * 32);
+        s_nx[2 * tid + 1] = make_int4(__float_as_int((float)(nqx * 4) - kHalfSpan),
+                                      __float_as_int((float)(nqy * 4) - kHalfSpan), 0, 0);
       }
       if (tid == NQ - 1) s_start[NQ] = incl;
     }
@@ -210,7 +227,10 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       // lp: index in s_list of the next entry; le: end of the current list
       int lp = q * kBlock + (r0 - s_start[q]);
       int le = q * kBlock + (s_start[q + 1] - s_start[q]);
-      int pix = (q / MX) * 4 * T + (q % MX) * 4 + ly * T + lx;
+      // pb: byte offset of the lane's first pixel in each plane of s_iacc
+      const int loff = 4 * (ly * T + lx);
+      int pb = 4 * ((q / MX) * 4 * T + (q % MX) * 4) + loff;
+      int qo = q * 32;  // byte offset of the list's entry in s_nx
       float px = (float)((q % MX) * 4 + lx) - kHalfSpan;
       float py = (float)((q / MX) * 4 + ly) - kHalfSpan;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, b0 = 0.f, b1 = 0.f, b2 = 0.f;
@@ -220,24 +240,31 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       constexpr int kLB = (int)sizeof(LT);
       const char *const s_lb = reinterpret_cast<const char *>(&s_list[0][0]);
       int bo = lp * kLB, d = le - lp;
+      // the running sums into the fixed-point accumulator, rows r and r + 2
+      auto flush = [&](const int b) {
+        char *const acc_b = reinterpret_cast<char *>(&s_iacc[0][0]) + b;
+        atomicAdd(reinterpret_cast<int *>(acc_b), round_half_up(a0));
+        atomicAdd(reinterpret_cast<int *>(acc_b + 4 * NP), round_half_up(a1));
+        atomicAdd(reinterpret_cast<int *>(acc_b + 8 * NP), round_half_up(a2));
+        atomicAdd(reinterpret_cast<int *>(acc_b + 8 * T), round_half_up(b0));
+        atomicAdd(reinterpret_cast<int *>(acc_b + 4 * NP + 8 * T), round_half_up(b1));
+        atomicAdd(reinterpret_cast<int *>(acc_b + 8 * NP + 8 * T), round_half_up(b2));
+      };
       auto step = [&](const int u) {
         if (d == u) {
           // next micro-tile: flush the running sums (already scaled by 2^S)
-          atomicAdd(&s_iacc[0][pix], (int)rintf(a0));
-          atomicAdd(&s_iacc[1][pix], (int)rintf(a1));
-          atomicAdd(&s_iacc[2][pix], (int)rintf(a2));
-          atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(b0));
-          atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(b1));
-          atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(b2));
+          flush(pb);
           a0 = a1 = a2 = 0.f;
           b0 = b1 = b2 = 0.f;
-          q = s_next[q];
-          bo = (q * kBlock - u) * kLB;
-          d = u + (s_start[q + 1] - s_start[q]);
-          const int qx = (int)((unsigned)q % MX), qy = (int)((unsigned)q / MX);
-          pix = qy * 4 * T + qx * 4 + ly * T + lx;
-          px = (float)(qx * 4 + lx) - kHalfSpan;
-          py = (float)(qy * 4 + ly) - kHalfSpan;
+          const char *const nb = reinterpret_cast<const char *>(s_nx) + qo;
+          const int4 n = *reinterpret_cast<const int4 *>(nb);
+          const int4 nf = *reinterpret_cast<const int4 *>(nb + 16);
+          qo = n.w;
+          bo = n.x - u * kLB;
+          d = u + n.y;
+          pb = n.z + loff;
+          px = __int_as_float(nf.x) + (float)lx;
+          py = __int_as_float(nf.y) + (float)ly;
         }
         // byte offset of the entry's staging slot
         const int jb = (int)*reinterpret_cast<const LT *>(s_lb + bo + u * kLB) << kShift;
@@ -276,14 +303,7 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
         d -= 1;
       }
       if (grp < rem) step(0);
-      if (steps > 0 || grp < rem) {
-        atomicAdd(&s_iacc[0][pix], (int)rintf(a0));
-        atomicAdd(&s_iacc[1][pix], (int)rintf(a1));
-        atomicAdd(&s_iacc[2][pix], (int)rintf(a2));
-        atomicAdd(&s_iacc[0][pix + 2 * T], (int)rintf(b0));
-        atomicAdd(&s_iacc[1][pix + 2 * T], (int)rintf(b1));
-        atomicAdd(&s_iacc[2][pix + 2 * T], (int)rintf(b2));
-      }
+      if (steps > 0 || grp < rem) flush(pb);
     }
     // the other length buffer was last read before the previous batch's
     // final barrier and is next written after this batch's
