@@ -49,6 +49,36 @@ __device__ __forceinline__ uint32_t pack_box(int a0, int a1, int b0, int b1) {
   return (uint32_t)a0 | ((uint32_t)a1 << 8) | ((uint32_t)b0 << 16) | ((uint32_t)b1 << 24);
 }
 
+// The 4 x 4 px micro-tiles of a tile (MX per row) whose rectangle of pixel
+// centres the truncation disc of radius R can reach, one bit each (bit
+// qy * MX + qx), with a margin over the rounding of this test and of the
+// evaluation.  ux, uy: the particle centre minus half a pixel, in pixels
+// from the tile origin.  Lengths below are in micro-tiles (4 px): the centre
+// (cx, cy) and the radius with margin rq; row band qy (pixel rows 4 qy ..
+// 4 qy + 3) lies at ey = max(qy - cy, cy - qy - 3/4, 0) from the centre and
+// is reached when ey <= rq, and then so are its columns a..b, those within
+// sqrt(rq^2 - ey^2) the same way: one square root per row band instead of a
+// test per micro-tile.
+template <int MX, typename MT>
+__device__ __forceinline__ MT disc_micro_tiles(float ux, float uy, float R) {
+  const float cx = ux * 0.25f, cy = uy * 0.25f;
+  const float r2q = fmaf(R * R, 1.0001f, 1e-3f) * 0.0625f;
+  const float rq = __builtin_amdgcn_sqrtf(r2q);
+  const int qy0 = max((int)ceilf((cy - 0.75f) - rq), 0);
+  const int qy1 = min((int)floorf(cy + rq), MX - 1);
+  const float ca = cx - 0.75f;
+  MT mask = 0;
+  float fy = (float)qy0 - cy;
+  for (int qy = qy0; qy <= qy1; ++qy, fy += 1.f) {
+    const float ey = fmaxf(fmaxf(fy, -0.75f - fy), 0.f);
+    const float hw = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-ey, ey, r2q), 0.f));
+    const int a = max((int)ceilf(ca - hw), 0);
+    const int b = min((int)floorf(cx + hw), MX - 1);
+    if (a <= b) mask |= (MT)(((MT)1 << (b - a + 1)) - 1) << (a + qy * MX);
+  }
+  return mask;
+}
+
 // A batch of up to 256 list entries is staged in LDS (offsets, width,
 // premultiplied colour).  The tile is split into 4 x 4 micro-tiles and each
 // staged entry appends itself to the list of every micro-tile its truncation
@@ -143,30 +173,8 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
       ox = fmaf(kHalfSpan - (r0.x - (float)x0), g, (0.5f - r0.y) * g);
       oy = fmaf(kHalfSpan - (r0.z - (float)y0), g, (0.5f - r0.w) * g);
       amax = fmaxf(fmaxf(fabsf(r1.y), fabsf(r1.z)), fabsf(r1.w));
-      // micro-tiles whose rectangle of pixel centres the truncation disc can
-      // reach, with a margin over the rounding of this test and of the
-      // evaluation.  Lengths in micro-tiles (4 px): the centre (cx, cy), the
-      // radius with margin rq; row band qy (pixel rows 4 qy .. 4 qy + 3) lies
-      // at ey = max(qy - cy, cy - qy - 3/4, 0) from the centre and is reached
-      // when ey <= rq, and then so are its columns a..b, those within
-      // sqrt(rq^2 - ey^2) the same way
-      const float cx = ((r0.x - (float)x0) + (r0.y - 0.5f)) * 0.25f;
-      const float cy = ((r0.z - (float)y0) + (r0.w - 0.5f)) * 0.25f;
-      const float rr = tk.nu * r1.x;
-      const float r2q = fmaf(rr * rr, 1.0001f, 1e-3f) * 0.0625f;
-      const float rq = __builtin_amdgcn_sqrtf(r2q);
-      const int qy0 = max((int)ceilf((cy - 0.75f) - rq), 0);
-      const int qy1 = min((int)floorf(cy + rq), MX - 1);
-      const float ca = cx - 0.75f;
-      MT mask = 0;
-      float fy = (float)qy0 - cy;
-      for (int qy = qy0; qy <= qy1; ++qy, fy += 1.f) {
-        const float ey = fmaxf(fmaxf(fy, -0.75f - fy), 0.f);
-        const float hw = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-ey, ey, r2q), 0.f));
-        const int a = max((int)ceilf(ca - hw), 0);
-        const int b = min((int)floorf(cx + hw), MX - 1);
-        if (a <= b) mask |= (MT)(((MT)1 << (b - a + 1)) - 1) << (a + qy * MX);
-      }
+      MT mask = disc_micro_tiles<MX, MT>((r0.x - (float)x0) + (r0.y - 0.5f),
+                                         (r0.z - (float)y0) + (r0.w - 0.5f), tk.nu * r1.x);
       while (mask) {
         const int q = NQ > 32 ? (int)__builtin_ctzll((unsigned long long)mask)
                               : (int)__builtin_ctz((unsigned)mask);
@@ -583,30 +591,13 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
       const uint32_t pid = (uint32_t)(src[k] & 0xffffffffull);
       const float4 r0 = rec[2 * (size_t)pid];
       const float4 r1 = rec[2 * (size_t)pid + 1];
-      int i0, i1, j0, j1;
-      if (record_box(r0.x, r0.y, r0.z, r0.w, r1.x, tk.nu, tk.W, tk.H, i0, i1, j0, j1)) {
-        const int li0 = max(i0 - x0, 0), li1 = min(i1 - x0, T - 1);
-        const int lj0 = max(j0 - y0, 0), lj1 = min(j1 - y0, T - 1);
-        if (li0 <= li1 && lj0 <= lj1) {
-          s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
-          s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
-          s_ap[tid] = rec2[pid].x;
-          // micro-tiles of the box whose pixel centres the disc can reach
-          // (the same test as the additive splat's)
-          const float ux = (r0.x - (float)x0) + (r0.y - 0.5f);
-          const float uy = (r0.z - (float)y0) + (r0.w - 0.5f);
-          const float rr = tk.nu * r1.x;
-          const float r2m = fmaf(rr * rr, 1.0001f, 1e-3f);
-          for (int qy = lj0 >> 2; qy <= (lj1 >> 2); ++qy) {
-            const float ey = fmaxf(fmaxf((float)(4 * qy) - uy, uy - (float)(4 * qy + 3)), 0.f);
-            const float ey2 = ey * ey;
-            for (int qx = li0 >> 2; qx <= (li1 >> 2); ++qx) {
-              const float ex = fmaxf(fmaxf((float)(4 * qx) - ux, ux - (float)(4 * qx + 3)), 0.f);
-              if (fmaf(ex, ex, ey2) <= r2m) mask |= (MaskT)1 << (qy * MX + qx);
-            }
-          }
-        }
-      }
+      // (listed records are finite with sigma > 0)
+      s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
+      s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
+      s_ap[tid] = rec2[pid].x;
+      // micro-tiles the disc can reach (the additive splat's test)
+      mask = disc_micro_tiles<MX, MaskT>((r0.x - (float)x0) + (r0.y - 0.5f),
+                                         (r0.z - (float)y0) + (r0.w - 0.5f), tk.nu * r1.x);
     }
     s_mask[tid] = mask;
     __syncthreads();
