@@ -64,74 +64,72 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
       const float s = load_attr(P.scal, P.dtype, k) * P.s_scale;
       const int sp = P.species ? (int)P.species[k] : 0;
       const float a = (P.mode == SPL_SORTED) ? P.absorb[k] : 0.0f;
-      float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = make_float4(0.f, 0.f, 0.f, 0.f);
-      float2 o2 = make_float2(0.f, 0.f);
-      bool active = false;
-      if (finitef(x) && finitef(y) && finitef(z) && finitef(h) && finitef(I) && finitef(s) &&
-          finitef(a) && h > 0.0f && a >= 0.0f && sp < P.n_species) {
-        const double vx = (double)x - P.e[0], vy = (double)y - P.e[1], vz = (double)z - P.e[2];
-        const double zv = vx * P.f[0] + vy * P.f[1] + vz * P.f[2];
-        if (zv > P.z_near) {
-          const double xv = vx * P.r[0] + vy * P.r[1] + vz * P.r[2];
-          const double yv = vx * P.u[0] + vy * P.u[1] + vz * P.u[2];
-          // 1/zv: hardware reciprocal and two Newton steps (zv > z_near > 0)
-          double iz = __builtin_amdgcn_rcp(zv);
-          iz = fma(iz, fma(-zv, iz, 1.0), iz);
-          iz = fma(iz, fma(-zv, iz, 1.0), iz);
-          const double X = P.cx + P.F * xv * iz;
-          const double Y = P.cy - P.F * yv * iz;
-          const double rho = P.F * (double)h * iz;
-          const double ks = P.k_sigma * rho;
-          const double sig = sqrt(ks * ks + P.sigma_min * P.sigma_min);
-          const double R = P.nu * sig;
-          if (fabs(X - P.cx) <= 4194304.0 && fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0) {
-            const LookK L = s_looks[sp];
-            float c0, c1, c2;
-            bool colour_ok = true;
-            if (L.vec) {
-              // colour taken directly from the vector field
-              c0 = load_attr(P.rgb, P.dtype, 3 * k) * P.c_scale;
-              c1 = load_attr(P.rgb, P.dtype, 3 * k + 1) * P.c_scale;
-              c2 = load_attr(P.rgb, P.dtype, 3 * k + 2) * P.c_scale;
-              colour_ok = finitef(c0) && finitef(c1) && finitef(c2);
-            } else if (L.M == 1) {
-              c0 = L.rgb[0];
-              c1 = L.rgb[1];
-              c2 = L.rgb[2];
-            } else {
-              float t;
-              if (L.log10)
-                t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
-              else
-                t = (s - L.lo) * L.inv_range;
-              t = fminf(fmaxf(t, 0.0f), 1.0f);
-              const float u = t * (float)(L.M - 1);
-              int j = (int)floorf(u);
-              j = min(max(j, 0), L.M - 2);
-              const float fr = u - (float)j;
-              const float *p0 = L.rgb + 3 * j;
-              c0 = (1.0f - fr) * p0[0] + fr * p0[3];
-              c1 = (1.0f - fr) * p0[1] + fr * p0[4];
-              c2 = (1.0f - fr) * p0[2] + fr * p0[5];
-            }
-            const float bi = L.beta * I;
-            const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
-            const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
-            if (colour_ok && (emits || (P.mode == SPL_SORTED && a > 0.0f))) {
-              // peak amplitude 1/(pi sigma^2) in single precision from the
-              // stored sigma
-              const float sg = (float)sig;
-              const float amp = __builtin_amdgcn_rcpf(3.14159265f * sg * sg);
-              const double fX = floor(X), fY = floor(Y);
-              o0 = make_float4((float)fX, (float)(X - fX), (float)fY, (float)(Y - fY));
-              o1 = make_float4(sg, E0 * amp, E1 * amp, E2 * amp);
-              o2 = make_float2(a * amp, (float)zv);
-              spn = record_span(o0, o1.x, tk);
-              active = spn.x != kInactive;
-            }
-          }
+      // Straight-line form: every lane computes the record and the tests
+      // decide at the end whether it is kept (nested early exits would make
+      // the compiler re-zero the outputs on every level of the main path).
+      const bool in_ok = finitef(x) && finitef(y) && finitef(z) && finitef(h) && finitef(I) &&
+                         finitef(s) && finitef(a) && h > 0.0f && a >= 0.0f && sp < P.n_species;
+      const double vx = (double)x - P.e[0], vy = (double)y - P.e[1], vz = (double)z - P.e[2];
+      const double zv = vx * P.f[0] + vy * P.f[1] + vz * P.f[2];
+      const double xv = vx * P.r[0] + vy * P.r[1] + vz * P.r[2];
+      const double yv = vx * P.u[0] + vy * P.u[1] + vz * P.u[2];
+      // 1/zv: hardware reciprocal and two Newton steps (used when zv > z_near > 0)
+      double iz = __builtin_amdgcn_rcp(zv);
+      iz = fma(iz, fma(-zv, iz, 1.0), iz);
+      iz = fma(iz, fma(-zv, iz, 1.0), iz);
+      const double X = P.cx + P.F * xv * iz;
+      const double Y = P.cy - P.F * yv * iz;
+      const double rho = P.F * (double)h * iz;
+      const double ks = P.k_sigma * rho;
+      const double sig = sqrt(ks * ks + P.sigma_min * P.sigma_min);
+      const double R = P.nu * sig;
+      const bool in_view = in_ok && zv > P.z_near && fabs(X - P.cx) <= 4194304.0 &&
+                           fabs(Y - P.cy) <= 4194304.0 && R <= 4194304.0;
+      const LookK L = s_looks[in_ok ? sp : 0];
+      float c0, c1, c2;
+      bool colour_ok = true;
+      if (L.vec) {
+        // colour taken directly from the vector field
+        c0 = c1 = c2 = 0.0f;
+        if (in_view) {
+          c0 = load_attr(P.rgb, P.dtype, 3 * k) * P.c_scale;
+          c1 = load_attr(P.rgb, P.dtype, 3 * k + 1) * P.c_scale;
+          c2 = load_attr(P.rgb, P.dtype, 3 * k + 2) * P.c_scale;
         }
+        colour_ok = finitef(c0) && finitef(c1) && finitef(c2);
+      } else if (L.M == 1) {
+        c0 = L.rgb[0];
+        c1 = L.rgb[1];
+        c2 = L.rgb[2];
+      } else {
+        float t;
+        if (L.log10)
+          t = (s > 0.0f) ? (log10f(s) - L.lo) * L.inv_range : 0.0f;
+        else
+          t = (s - L.lo) * L.inv_range;
+        t = fminf(fmaxf(t, 0.0f), 1.0f);
+        const float u = t * (float)(L.M - 1);
+        int j = (int)floorf(u);
+        j = min(max(j, 0), L.M - 2);
+        const float fr = u - (float)j;
+        const float *p0 = L.rgb + 3 * j;
+        c0 = (1.0f - fr) * p0[0] + fr * p0[3];
+        c1 = (1.0f - fr) * p0[1] + fr * p0[4];
+        c2 = (1.0f - fr) * p0[2] + fr * p0[5];
       }
+      const float bi = L.beta * I;
+      const float E0 = bi * c0, E1 = bi * c1, E2 = bi * c2;
+      const bool emits = (E0 != 0.0f) || (E1 != 0.0f) || (E2 != 0.0f);
+      const bool keep = in_view && colour_ok && (emits || (P.mode == SPL_SORTED && a > 0.0f));
+      // peak amplitude 1/(pi sigma^2) in single precision from the stored sigma
+      const float sg = (float)sig;
+      const float amp = __builtin_amdgcn_rcpf(3.14159265f * sg * sg);
+      const double fX = floor(X), fY = floor(Y);
+      float4 o0 = make_float4((float)fX, (float)(X - fX), (float)fY, (float)(Y - fY));
+      float4 o1 = make_float4(sg, E0 * amp, E1 * amp, E2 * amp);
+      float2 o2 = make_float2(a * amp, (float)zv);
+      if (keep) spn = record_span(o0, o1.x, tk);
+      const bool active = spn.x != kInactive;
       if (active) {
         ++my_act;
         if (spn.y & kLargeFlag) ++my_large;

@@ -140,6 +140,13 @@ __device__ __forceinline__ bool paper_rule_keeps(float Xi, float Xf, float Yi, f
   return d2 < thr2;
 }
 
+// Tile index of pixel v >= 0 for tiles of t > 0 pixels (t is the same on
+// every lane: a shift when it is a power of two).
+__device__ __forceinline__ uint32_t tile_of(int v, int t) {
+  if ((t & (t - 1)) == 0) return (uint32_t)v >> __builtin_ctz((unsigned)t);
+  return (uint32_t)v / (uint32_t)t;
+}
+
 // Tile span of a record: .x = tx0 | tx1 << 16, .y = ty0 | ty1 << 16, with
 // kLargeFlag set in .y when the span is in large-particle tiles.  kInactive in
 // .x when the record does not reach the image.
@@ -158,12 +165,12 @@ __device__ __forceinline__ uint2 record_span(const float4 r0, float sigma, const
   }
   if (R > tk.large_cut) {
     const int c = tk.ctile;
-    sp.x = (uint32_t)(i0 / c) | ((uint32_t)(i1 / c) << 16);
-    sp.y = ((uint32_t)(j0 / c) | ((uint32_t)(j1 / c) << 16)) | kLargeFlag;
+    sp.x = tile_of(i0, c) | (tile_of(i1, c) << 16);
+    sp.y = (tile_of(j0, c) | (tile_of(j1, c) << 16)) | kLargeFlag;
   } else {
     const int t = tk.tile;
-    sp.x = (uint32_t)(i0 / t) | ((uint32_t)(i1 / t) << 16);
-    sp.y = (uint32_t)(j0 / t) | ((uint32_t)(j1 / t) << 16);
+    sp.x = tile_of(i0, t) | (tile_of(i1, t) << 16);
+    sp.y = tile_of(j0, t) | (tile_of(j1, t) << 16);
   }
   return sp;
 }
