@@ -5,8 +5,11 @@
 // count -> exclusive scan -> scatter into one preallocated array.
 //
 //  k_count    per-chunk tile histogram in LDS (global atomics only to flush
-//             non-zero bins), or direct global atomics when the bins do not
-//             fit in LDS.
+//             non-zero bins).  When the bins do not fit in LDS the count and
+//             the scatter run once per window of bins that does, each pass
+//             over the spans taking the pairs of its window only (a per-pair
+//             global atomic, contended on the bins of dense clusters, had
+//             taken 17-37 ms at 100M particles and 2048^2 or 4096^2).
 //  k_scan     single-workgroup exclusive scan of the bin counts, plus the
 //             work-item counts of up to three chunkings of the lists.
 //  k_items    expands the item counts into (bin, begin, end, chunk) items.
@@ -39,18 +42,14 @@ __device__ __forceinline__ int64_t unit_block(int64_t t) {
   return ((int64_t)blockIdx.x + (t / U) * (int64_t)gridDim.x) * kUnit + (t % U) * NT;
 }
 
-template <bool kLds>
 __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
                                                   const float4 *__restrict__ rec, int64_t n,
                                                   TileK tk, uint32_t *__restrict__ counts) {
   extern __shared__ uint32_t hist[];
   const int nb = tk.n_tiles + tk.n_ctiles;
-  uint32_t *bins = kLds ? hist : counts;
   // the workgroup's histogram covers all its chunks and is flushed once
-  if (kLds) {
-    for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
-    __syncthreads();
-  }
+  for (int i = threadIdx.x; i < nb; i += kBlock) hist[i] = 0;
+  __syncthreads();
   {
     int64_t t = 0, kb = unit_block(0);
     // the next span is loaded while this one is counted
@@ -60,35 +59,37 @@ __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span
       const int64_t kn = unit_block(++t);
       const uint2 s = nxt;
       nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
-      count_span(s, k, rec, tk, bins);
+      count_span(s, k, rec, tk, hist);
       kb = kn;
     }
   }
-  if (kLds) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += kBlock) {
-      const uint32_t v = hist[i];
-      if (v) atomicAdd(&counts[i], v);
-    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    const uint32_t v = hist[i];
+    if (v) atomicAdd(&counts[i], v);
   }
 }
 
 // The same count with two 16-bit bins per LDS word, so that twice as many
-// bins fit (and a workgroup takes half the LDS).  A bin's count in one
-// workgroup never exceeds the particles it takes (a particle adds at most one
-// to a bin), and the grid gives no workgroup more than kPackedUnits units, so
-// no half carries into the other.
+// bins fit (and a workgroup takes half the LDS), over the window of bins
+// [lo, lo + nbw).  A bin's count in one workgroup never exceeds the
+// particles it takes (a particle adds at most one to a bin), and the grid
+// gives no workgroup more than kPackedUnits units, so no half carries into
+// the other.
 constexpr int kPackedUnits = 63;  // 63 x 1024 particles < 2^16
 template <int NT>
 __global__ __launch_bounds__(NT) void k_count_packed(const uint2 *__restrict__ span,
                                                          const float4 *__restrict__ rec, int64_t n,
-                                                         TileK tk, uint32_t *__restrict__ counts) {
+                                                         TileK tk, int lo, int nbw,
+                                                         uint32_t *__restrict__ counts) {
   extern __shared__ uint32_t hist[];
-  const int nb = tk.n_tiles + tk.n_ctiles;
-  const int nw = (nb + 1) / 2;
+  const int nw = (nbw + 1) / 2;
   for (int i = threadIdx.x; i < nw; i += NT) hist[i] = 0;
   __syncthreads();
-  auto add = [&](uint32_t bin, uint32_t v) { atomicAdd(&hist[bin >> 1], v << ((bin & 1u) * 16u)); };
+  auto add = [&](uint32_t bin, uint32_t v) {
+    const uint32_t b = bin - (uint32_t)lo;  // wraps above the window's top when bin < lo
+    if (b < (uint32_t)nbw) atomicAdd(&hist[b >> 1], v << ((b & 1u) * 16u));
+  };
   {
     int64_t t = 0, kb = unit_block<NT>(0);
     uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
@@ -104,68 +105,30 @@ __global__ __launch_bounds__(NT) void k_count_packed(const uint2 *__restrict__ s
   __syncthreads();
   for (int i = threadIdx.x; i < nw; i += NT) {
     const uint32_t v = hist[i];
-    if (v & 0xffffu) atomicAdd(&counts[2 * i], v & 0xffffu);
-    if (v >> 16) atomicAdd(&counts[2 * i + 1], v >> 16);
+    if (v & 0xffffu) atomicAdd(&counts[lo + 2 * i], v & 0xffffu);
+    if (v >> 16) atomicAdd(&counts[lo + 2 * i + 1], v >> 16);
   }
 }
 
-template <bool kLds, bool kKeys, int NT>
+// The scatter over the window of bins [lo, lo + nbw): the pairs of other
+// bins are left to the window that holds them.
+template <bool kKeys, int NT>
 __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
                                                     const float4 *__restrict__ rec,
                                                     const float2 *__restrict__ rec2, int64_t n,
-                                                    TileK tk, uint32_t *__restrict__ cursor,
+                                                    TileK tk, int lo, int nbw,
+                                                    uint32_t *__restrict__ cursor,
                                                     uint32_t *__restrict__ pairs,
                                                     unsigned long long *__restrict__ keys) {
   extern __shared__ uint32_t hist[];
-  const int nb = tk.n_tiles + tk.n_ctiles;
   const bool paper = tk.bin_rule == 1;
-  uint32_t *bins = kLds ? hist : cursor;
-  if (kLds) {
-    // local counts of all the workgroup's chunks, then one global
-    // reservation per bin (the order inside a bin is free: additive lists
-    // are summed, depth-sorted ones are sorted next)
-    for (int i = threadIdx.x; i < nb; i += NT) hist[i] = 0;
-    __syncthreads();
-    {
-      int64_t t = 0, kb = unit_block<NT>(0);
-      uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
-      for (; kb < n; kb = unit_block<NT>(t)) {
-        const int64_t k = kb + threadIdx.x;
-        const int64_t kn = unit_block<NT>(++t);
-        const uint2 s = nxt;
-        nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
-        const bool act = s.x != kInactive;
-        const SpanDec d = decode(s);
-        const int ntx = d.large ? tk.nctx : tk.ntx;
-        const int off = d.large ? tk.n_tiles : 0;
-        const bool filt = paper && !d.large;
-        const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
-        const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
-        int head_of;
-        const int len = wave_runs(single, key, head_of);
-        if (len) atomicAdd(&hist[key], (uint32_t)len);
-        multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, 0u, tk,
-                         [&](uint32_t bin, uint32_t, uint32_t) { atomicAdd(&hist[bin], 1u); });
-      }
-    }
-    __syncthreads();
-    // eight bins per lane in flight at once: each reservation returns its
-    // base, and one at a time the lane would wait a round trip per bin
-    for (int i0 = threadIdx.x; i0 < nb; i0 += 8 * NT) {
-      uint32_t v[8], r[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = i0 + u * NT;
-        v[u] = i < nb ? hist[i] : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) r[u] = v[u] ? atomicAdd(&cursor[i0 + u * NT], v[u]) : 0u;
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (v[u]) hist[i0 + u * NT] = r[u];
-    }
-    __syncthreads();
-  }
+  // (wraps above the window's top when bin < lo)
+  auto in_win = [&](uint32_t bin) { return bin - (uint32_t)lo < (uint32_t)nbw; };
+  // local counts of all the workgroup's chunks, then one global reservation
+  // per bin (the order inside a bin is free: additive lists are summed,
+  // depth-sorted ones are sorted next)
+  for (int i = threadIdx.x; i < nbw; i += NT) hist[i] = 0;
+  __syncthreads();
   {
     int64_t t = 0, kb = unit_block<NT>(0);
     uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
@@ -181,15 +144,57 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
       const bool filt = paper && !d.large;
       const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
       const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
+      int head_of;
+      const int len = wave_runs(single, key, head_of);
+      if (len && in_win((uint32_t)key)) atomicAdd(&hist[key - lo], (uint32_t)len);
+      multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, 0u, tk,
+                       [&](uint32_t bin, uint32_t, uint32_t) {
+                         if (in_win(bin)) atomicAdd(&hist[bin - lo], 1u);
+                       });
+    }
+  }
+  __syncthreads();
+  // eight bins per lane in flight at once: each reservation returns its
+  // base, and one at a time the lane would wait a round trip per bin
+  for (int i0 = threadIdx.x; i0 < nbw; i0 += 8 * NT) {
+    uint32_t v[8], r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT;
+      v[u] = i < nbw ? hist[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r[u] = v[u] ? atomicAdd(&cursor[lo + i0 + u * NT], v[u]) : 0u;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (v[u]) hist[i0 + u * NT] = r[u];
+  }
+  __syncthreads();
+  {
+    int64_t t = 0, kb = unit_block<NT>(0);
+    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    for (; kb < n; kb = unit_block<NT>(t)) {
+      const int64_t k = kb + threadIdx.x;
+      const int64_t kn = unit_block<NT>(++t);
+      const uint2 s = nxt;
+      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      const bool act = s.x != kInactive;
+      const SpanDec d = decode(s);
+      const int ntx = d.large ? tk.nctx : tk.ntx;
+      const int off = d.large ? tk.n_tiles : 0;
+      const bool filt = paper && !d.large;
+      const bool single = act && !filt && d.tx0 == d.tx1 && d.ty0 == d.ty1;
+      const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
+      const bool mine = single && in_win((uint32_t)key);
       unsigned long long key_hi = 0;
       if (kKeys && act) key_hi = (unsigned long long)__float_as_uint(rec2[k].y) << 32;
       int head_of;
       const int len = wave_runs(single, key, head_of);
       uint32_t rb = 0;
-      if (len) rb = atomicAdd(&bins[key], (uint32_t)len);
+      if (len && mine) rb = atomicAdd(&hist[key - lo], (uint32_t)len);
       // every lane takes part in the shuffle; run members read their head's base
       const uint32_t hb = (uint32_t)__shfl((int)rb, head_of);
-      if (single) {
+      if (mine) {
         const uint32_t slot = hb + (uint32_t)(__lane_id() - head_of);
         if (kKeys)
           keys[slot] = key_hi | (unsigned long long)(uint32_t)k;
@@ -198,7 +203,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
       }
       multi_tile_pairs(act && !single, d, filt, off, ntx, rec, k, (uint32_t)(key_hi >> 32), tk,
                        [&](uint32_t bin, uint32_t pk, uint32_t zbits) {
-                         const uint32_t slot = atomicAdd(&bins[bin], 1u);
+                         if (!in_win(bin)) return;
+                         const uint32_t slot = atomicAdd(&hist[bin - lo], 1u);
                          if (kKeys)
                            keys[slot] = ((unsigned long long)zbits << 32) | (unsigned long long)pk;
                          else
@@ -436,19 +442,23 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   if (nb <= kLdsBins / 2) {
     const size_t sh = nb * sizeof(uint32_t);
-    const int64_t g = bin_pass_grid(k_count<true>, sh, n, nb);
-    hipLaunchKernelGGL(k_count<true>, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
-  } else if (nb <= 2 * kLdsBins) {
-    const size_t sh = (size_t)((nb + 1) / 2) * sizeof(uint32_t);
-    const int64_t units = (n + kUnit - 1) / kUnit;
+    const int64_t g = bin_pass_grid(k_count, sh, n, nb);
+    hipLaunchKernelGGL(k_count, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
+    return hipGetLastError();
+  }
+  // packed 16-bit bins, in as many equal windows of at most 2 kLdsBins bins
+  // as the bins need (one pass over the spans each)
+  const int n_win = (nb + 2 * kLdsBins - 1) / (2 * kLdsBins);
+  const int per = (((nb + n_win - 1) / n_win) + 1) & ~1;
+  const int64_t units = (n + kUnit - 1) / kUnit;
+  for (int lo = 0; lo < nb; lo += per) {
+    const int nbw = std::min(per, nb - lo);
+    const size_t sh = (size_t)((nbw + 1) / 2) * sizeof(uint32_t);
     // 512 lanes per workgroup, as in the scatter with a large histogram
-    const int64_t g = std::max(bin_pass_grid(k_count_packed<2 * kBlock>, sh, n, nb, 2 * kBlock),
+    const int64_t g = std::max(bin_pass_grid(k_count_packed<2 * kBlock>, sh, n, nbw, 2 * kBlock),
                                (units + kPackedUnits - 1) / kPackedUnits);
     hipLaunchKernelGGL(k_count_packed<2 * kBlock>, dim3((int)g), dim3(2 * kBlock), sh, s, span, r,
-                       n, tk, counts);
-  } else {
-    const int64_t g = bin_pass_grid(k_count<false>, 0, n, nb);
-    hipLaunchKernelGGL(k_count<false>, dim3((int)g), dim3(kBlock), 0, s, span, r, n, tk, counts);
+                       n, tk, lo, nbw, counts);
   }
   return hipGetLastError();
 }
@@ -506,30 +516,32 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
   const int nb = tk.n_tiles + tk.n_ctiles;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
-  const bool lds = nb <= kLdsBins;
-  const size_t sh = lds ? nb * sizeof(uint32_t) : 0;
-  auto launch = [&](auto kernel, int nt) {
-    const int64_t g = bin_pass_grid(kernel, sh, n, nb, nt);
-    hipLaunchKernelGGL(kernel, dim3((int)g), dim3(nt), sh, s, span, r, r2, n, tk, cursor, pairs,
-                       keys);
-  };
-  // a histogram above 32 KB leaves few workgroups per CU: 512 lanes each
-  // keep more waves resident
-  const bool wide = lds && nb > kLdsBins / 2;
-  if (keys) {
-    if (wide)
-      launch(k_scatter<true, true, 2 * kBlock>, 2 * kBlock);
-    else if (lds)
-      launch(k_scatter<true, true, kBlock>, kBlock);
-    else
-      launch(k_scatter<false, true, kBlock>, kBlock);
-  } else {
-    if (wide)
-      launch(k_scatter<true, false, 2 * kBlock>, 2 * kBlock);
-    else if (lds)
-      launch(k_scatter<true, false, kBlock>, kBlock);
-    else
-      launch(k_scatter<false, false, kBlock>, kBlock);
+  // equal windows of at most kLdsBins bins, one launch (two passes over the
+  // spans) each
+  const int n_win = (nb + kLdsBins - 1) / kLdsBins;
+  const int per = (nb + n_win - 1) / n_win;
+  for (int lo = 0; lo < nb; lo += per) {
+    const int nbw = std::min(per, nb - lo);
+    const size_t sh = (size_t)nbw * sizeof(uint32_t);
+    auto launch = [&](auto kernel, int nt) {
+      const int64_t g = bin_pass_grid(kernel, sh, n, nbw, nt);
+      hipLaunchKernelGGL(kernel, dim3((int)g), dim3(nt), sh, s, span, r, r2, n, tk, lo, nbw, cursor,
+                         pairs, keys);
+    };
+    // a histogram above 32 KB leaves few workgroups per CU: 512 lanes each
+    // keep more waves resident
+    const bool wide = nbw > kLdsBins / 2;
+    if (keys) {
+      if (wide)
+        launch(k_scatter<true, 2 * kBlock>, 2 * kBlock);
+      else
+        launch(k_scatter<true, kBlock>, kBlock);
+    } else {
+      if (wide)
+        launch(k_scatter<false, 2 * kBlock>, 2 * kBlock);
+      else
+        launch(k_scatter<false, kBlock>, kBlock);
+    }
   }
   return hipGetLastError();
 }

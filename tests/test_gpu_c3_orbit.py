@@ -92,6 +92,31 @@ def test_batched_4096_and_1024_views_match_oracle(env, c3, store):
     ds.close()
 
 
+def test_4096_views_with_16px_tiles_match_oracle(env, c3):
+    """The 4096^2 views of the same shape at 16 px tiles with the
+    large-particle path at 32 px: 65536 + 4096 bins, so the count runs in
+    three windows of packed bins and the scatter in five windows of bins, one
+    pass over the spans each (the binning parity tests cover the depth-keyed
+    scatter over several windows)."""
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals, poses, refs = c3
+    ds = B.Dataset(ctx, ps, "f32")
+    prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals), looks, tile=16, large_cut=32.0)
+    for pose, ref in zip(poses, refs):
+        if pose.width != 4096:
+            continue
+        img, st = ctx.spl_render_dataset(ds, pose, prm)
+        torch.cuda.synchronize()
+        err = rel_l2(img.cpu().numpy().astype(np.float64), ref)
+        print(f"4096^2 tile 16: n_active={st['n_active']} n_large={st['n_large']} "
+              f"rel_l2={err:.3e}", flush=True)
+        assert st["tile"] == 16 and st["n_active"] > 10_000
+        assert err < 1e-5
+    ds.close()
+
+
 @pytest.fixture(scope="module")
 def paths(env):
     ps, looks, pals = _scaled_set(1_000_000, 1005, 55_000_000)

@@ -116,8 +116,8 @@ def test_binning_10M_bit_exact(env, clustered, tile):
     bit-identical to the oracle's binning of the same FP32 records, the
     unordered lists equal as sets per tile, the depth-ordered ones equal
     outright.  32 and 16 px tiles keep the histogram in LDS (16384 bins, the
-    most it holds, at 16 px); 15 px tiles (18769 bins) take the global-atomic
-    path."""
+    most it holds, at 16 px); 15 px tiles (18769 bins) take two windows of
+    bins, one pass over the spans each."""
     import torch
 
     B, ctx, R = env
