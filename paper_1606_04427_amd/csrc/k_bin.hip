@@ -42,6 +42,18 @@ __device__ __forceinline__ int64_t unit_block(int64_t t) {
   return ((int64_t)blockIdx.x + (t / U) * (int64_t)gridDim.x) * kUnit + (t % U) * NT;
 }
 
+// Whether any (particle, tile) pair of span s can fall in the window of bins
+// [lo, lo + nbw): the span's bins lie between its first and last bin.
+__device__ __forceinline__ bool span_meets_window(uint2 s, const TileK &tk, int lo, int nbw) {
+  if (s.x == kInactive) return false;
+  if (lo == 0 && nbw >= tk.n_tiles + tk.n_ctiles) return true;  // one window
+  const SpanDec d = decode(s);
+  const int ntx = d.large ? tk.nctx : tk.ntx;
+  const int off = d.large ? tk.n_tiles : 0;
+  const int b0 = off + d.ty0 * ntx + d.tx0, b1 = off + d.ty1 * ntx + d.tx1;
+  return b1 >= lo && b0 < lo + nbw;
+}
+
 __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
                                                   const float4 *__restrict__ rec, int64_t n,
                                                   TileK tk, uint32_t *__restrict__ counts) {
@@ -98,7 +110,8 @@ __global__ __launch_bounds__(NT) void k_count_packed(const uint2 *__restrict__ s
       const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
       nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
-      count_span_with(s, k, rec, tk, add);
+      // a wave whose particles all miss the window skips it (uniform)
+      if (__ballot(span_meets_window(s, tk, lo, nbw)) != 0ull) count_span_with(s, k, rec, tk, add);
       kb = kn;
     }
   }
@@ -137,6 +150,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
       const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
       nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      // a wave whose particles all miss the window skips it (uniform)
+      if (__ballot(span_meets_window(s, tk, lo, nbw)) == 0ull) continue;
       const bool act = s.x != kInactive;
       const SpanDec d = decode(s);
       const int ntx = d.large ? tk.nctx : tk.ntx;
@@ -178,6 +193,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
       const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
       nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      // a wave whose particles all miss the window skips it (uniform)
+      if (__ballot(span_meets_window(s, tk, lo, nbw)) == 0ull) continue;
       const bool act = s.x != kInactive;
       const SpanDec d = decode(s);
       const int ntx = d.large ? tk.nctx : tk.ntx;
