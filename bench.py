@@ -997,7 +997,8 @@ def main():
     ap.add_argument("--error-views", type=int, default=4, help="batched: views checked")
     ap.add_argument("--requests", type=int, default=150, help="serving: requests per run")
     ap.add_argument("--warm-requests", type=int, default=20)
-    ap.add_argument("--workers", type=int, default=1)
+    ap.add_argument("--workers", type=int, default=2,
+                    help="serving: request-loop workers (contexts and streams)")
     ap.add_argument("--serving-n", type=int, default=100_000_000,
                     help="additive: particles of the serving sub-record")
     ap.add_argument("--serving-requests", type=int, default=60,
