@@ -742,13 +742,37 @@ def run_batched(args, torch, B):
         parts = B.DeviceParticles(ps, dev, dt_name)
         torch.cuda.synchronize()
         prms = [prm] * len(poses)
-        tuned = {}
+        tuned, trials = {}, {}
         if not args.no_autotune:
             # one tuning per image size; the library applies the latest choice
             # for an image size to the poses it did not tune
             for p in (big[0], small[0]):
                 tuned[p.width] = ctx.spl_autotune(parts, p, prm)
             log(f"{dt_name} autotune (tile, cut): {tuned}")
+            # the single-view timing does not see the batch (its 4096-entry
+            # work items, the binning of 32 large views): each image size's
+            # choice is confirmed by timing the batched call itself with each
+            # candidate, the other size held at its current choice
+            def batch_time(choice):
+                cp = [B.make_params(B.SPL_ADD_AEQE, pal_d, looks, tile=choice[p.width][0],
+                                    large_cut=choice[p.width][1]) for p in poses]
+                ctx.spl_render_batch(parts, poses, cp, outs=imgs, stats=False)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.spl_render_batch(parts, poses, cp, outs=imgs, stats=False)
+                torch.cuda.synchronize()
+                return time.perf_counter() - t0
+
+            for w, extra in ((big[0].width, [(16, -1.0), (32, -1.0)]),
+                             (small[0].width, [(16, -1.0)])):
+                times = {}
+                for tc in sorted({tuple(tuned[w]), *extra}):
+                    times[tc] = batch_time({**tuned, w: tc})
+                tuned[w] = min(times, key=times.get)
+                trials[w] = {f"{k[0]}/{k[1]:g}": round(v * 1e3) for k, v in times.items()}
+            prms = [B.make_params(B.SPL_ADD_AEQE, pal_d, looks, tile=tuned[p.width][0],
+                                  large_cut=tuned[p.width][1]) for p in poses]
+            log(f"{dt_name} batched choices: {tuned} (step ms per candidate: {trials})")
 
         def bstep():
             ctx.spl_render_batch(parts, poses, prms, outs=imgs, stats=False)
@@ -764,7 +788,7 @@ def run_batched(args, torch, B):
 
         def pstep():
             for k, p in enumerate(poses):
-                ctx.spl_render(parts, p, prm, out=imgs[k], stats=False)
+                ctx.spl_render(parts, p, prms[k], out=imgs[k], stats=False)
 
         res = {}
         for name, fn in (("batched", bstep), ("batched_graph", gstep), ("per_view", pstep)):
@@ -804,6 +828,8 @@ def run_batched(args, torch, B):
         res["error_vs_fp64_oracle_1M_subsample"] = errs
         log(f"{dt_name} error check on {len(errs)} views in {time.time() - t_err:.1f} s: "
             + ", ".join(f"{e['rel_l2']:.2e}" for e in errs))
+        res["tile_cut_by_size"] = {str(k): list(v) for k, v in tuned.items()}
+        res["batched_step_ms_by_choice"] = {str(k): v for k, v in trials.items()}
         results[dt_name] = res
         ctx.close()
         del sparts
@@ -992,7 +1018,8 @@ def main():
                     help="additive: skip the timing of the captured-graph replay")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="additive: also run one plain device copy of this size")
-    ap.add_argument("--dtypes", default="bf16,f16", help="batched: attribute dtypes")
+    ap.add_argument("--dtypes", default="bf16,f16,f32",
+                    help="batched: attribute dtypes (the first gives the value; FP32 is the comparison)")
     ap.add_argument("--views", type=int, default=64, help="batched: views per step")
     ap.add_argument("--error-views", type=int, default=4, help="batched: views checked")
     ap.add_argument("--requests", type=int, default=150, help="serving: requests per run")
