@@ -17,6 +17,18 @@ namespace spl {
 
 namespace {
 
+// kDt: the stored attribute type (SPL_F32, SPL_BF16 or SPL_F16), fixed per
+// kernel instance so that the loads need no branch.
+template <int kDt>
+__device__ __forceinline__ float load_attr_t(const void *p, int64_t i) {
+  if (kDt == SPL_F32) return static_cast<const float *>(p)[i];
+  if (kDt == SPL_BF16) {
+    const uint32_t b = static_cast<const uint16_t *>(p)[i];
+    return __uint_as_float(b << 16);
+  }
+  return (float)static_cast<const _Float16 *>(p)[i];
+}
+
 __device__ __forceinline__ float load_attr(const void *p, int dtype, int64_t i) {
   if (dtype == SPL_F32) return static_cast<const float *>(p)[i];
   if (dtype == SPL_BF16) {
@@ -31,7 +43,7 @@ __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v);
 // kCount: the tile counts of the binning stage are accumulated here too, in
 // an LDS histogram per workgroup flushed once at the end, which saves a pass
 // over the spans.
-template <bool kCount>
+template <bool kCount, int kDt>
 __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *__restrict__ rec,
                                                     float2 *__restrict__ rec2,
                                                     uint2 *__restrict__ span, int write_inactive,
@@ -59,9 +71,9 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
     uint2 spn = make_uint2(kInactive, kInactive);
     if (k < P.n) {
       const float x = P.x[k], y = P.y[k], z = P.z[k];
-      const float h = load_attr(P.h, P.dtype, k) * P.h_scale;
-      const float I = load_attr(P.inten, P.dtype, k) * P.i_scale;
-      const float s = load_attr(P.scal, P.dtype, k) * P.s_scale;
+      const float h = load_attr_t<kDt>(P.h, k) * P.h_scale;
+      const float I = load_attr_t<kDt>(P.inten, k) * P.i_scale;
+      const float s = load_attr_t<kDt>(P.scal, k) * P.s_scale;
       const int sp = P.species ? (int)P.species[k] : 0;
       const float a = (P.mode == SPL_SORTED) ? P.absorb[k] : 0.0f;
       // Straight-line form: every lane computes the record and the tests
@@ -92,9 +104,9 @@ __global__ __launch_bounds__(kBlock) void k_project(ProjK P, TileK tk, float4 *_
         // colour taken directly from the vector field
         c0 = c1 = c2 = 0.0f;
         if (in_view) {
-          c0 = load_attr(P.rgb, P.dtype, 3 * k) * P.c_scale;
-          c1 = load_attr(P.rgb, P.dtype, 3 * k + 1) * P.c_scale;
-          c2 = load_attr(P.rgb, P.dtype, 3 * k + 2) * P.c_scale;
+          c0 = load_attr_t<kDt>(P.rgb, 3 * k) * P.c_scale;
+          c1 = load_attr_t<kDt>(P.rgb, 3 * k + 1) * P.c_scale;
+          c2 = load_attr_t<kDt>(P.rgb, 3 * k + 2) * P.c_scale;
         }
         colour_ok = finitef(c0) && finitef(c1) && finitef(c2);
       } else if (L.M == 1) {
@@ -258,18 +270,29 @@ bool project_counts(const TileK &tk) { return tk.n_tiles + tk.n_ctiles <= kProje
 hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *rec2, uint2 *span,
                           int write_inactive, Totals *tot, hipStream_t s, uint32_t *counts) {
   if (pk.n == 0) return hipSuccess;
+  auto launch = [&](auto kernel, int g, size_t sh, uint32_t *cnt) {
+    hipLaunchKernelGGL(kernel, dim3(g), dim3(kBlock), sh, s, pk, tk,
+                       reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
+                       write_inactive, tot, cnt);
+  };
   if (counts && project_counts(tk)) {
     // fewer, longer-lived workgroups: each flushes its histogram once
     const int g = grid_for(pk.n, kBlock, 4096);
     const size_t sh = (size_t)(tk.n_tiles + tk.n_ctiles) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_project<true>, dim3(g), dim3(kBlock), sh, s, pk, tk,
-                       reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
-                       write_inactive, tot, counts);
+    if (pk.dtype == SPL_BF16)
+      launch(k_project<true, SPL_BF16>, g, sh, counts);
+    else if (pk.dtype == SPL_F16)
+      launch(k_project<true, SPL_F16>, g, sh, counts);
+    else
+      launch(k_project<true, SPL_F32>, g, sh, counts);
   } else {
     const int g = grid_for(pk.n, kBlock, 8192);
-    hipLaunchKernelGGL(k_project<false>, dim3(g), dim3(kBlock), 0, s, pk, tk,
-                       reinterpret_cast<float4 *>(rec), reinterpret_cast<float2 *>(rec2), span,
-                       write_inactive, tot, nullptr);
+    if (pk.dtype == SPL_BF16)
+      launch(k_project<false, SPL_BF16>, g, 0, nullptr);
+    else if (pk.dtype == SPL_F16)
+      launch(k_project<false, SPL_F16>, g, 0, nullptr);
+    else
+      launch(k_project<false, SPL_F32>, g, 0, nullptr);
   }
   return hipGetLastError();
 }
