@@ -35,7 +35,7 @@ constexpr int kChunk = 4096;     // particles per workgroup when the grid is not
 // tile list (the splat's batches are cheaper when their entries are close).
 // unit_block(t) is the first particle of the workgroup's t-th block of 256.
 // (NT-lane workgroups take blocks of NT particles.)
-constexpr int kUnit = 1024;
+constexpr int kUnit = kUnitParticles;
 template <int NT = kBlock>
 __device__ __forceinline__ int64_t unit_block(int64_t t) {
   constexpr int U = kUnit / NT;
@@ -52,6 +52,30 @@ __device__ __forceinline__ bool span_meets_window(uint2 s, const TileK &tk, int 
   const int off = d.large ? tk.n_tiles : 0;
   const int b0 = off + d.ty0 * ntx + d.tx0, b1 = off + d.ty1 * ntx + d.tx1;
   return b1 >= lo && b0 < lo + nbw;
+}
+
+// Unit masks: when the scatter needs three or more windows of bins, the bins are
+// also cut into 32 equal bands and each unit of kUnit particles gets the
+// bands its particles' pairs can fall in (computed by the first count pass),
+// so that a later pass skips, without reading their spans, the units that
+// cannot reach its window.
+constexpr int kBands = 32;
+__host__ __device__ __forceinline__ int band_of_bins(int nb) { return (nb + kBands - 1) / kBands; }
+__device__ __forceinline__ uint32_t band_bits(int b0, int b1, int band) {
+  const int q0 = b0 / band, q1 = b1 / band;
+  return q1 - q0 >= 31 ? (~0u << q0) : (((2u << (q1 - q0)) - 1u) << q0);
+}
+__device__ __forceinline__ uint32_t span_bands(uint2 s, const TileK &tk, int band) {
+  if (s.x == kInactive) return 0u;
+  const SpanDec d = decode(s);
+  const int ntx = d.large ? tk.nctx : tk.ntx;
+  const int off = d.large ? tk.n_tiles : 0;
+  return band_bits(off + d.ty0 * ntx + d.tx0, off + d.ty1 * ntx + d.tx1, band);
+}
+// Whether the unit of particle kb (kb < n) cannot reach the window's bands
+// wb (a uniform test: every lane of the workgroup reads the same word).
+__device__ __forceinline__ bool unit_skips(const uint32_t *umask, int64_t kb, uint32_t wb) {
+  return umask && (umask[kb / kUnit] & wb) == 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_count(const uint2 *__restrict__ span,
@@ -93,9 +117,16 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_count_packed(const uint2 *__restrict__ span,
                                                          const float4 *__restrict__ rec, int64_t n,
                                                          TileK tk, int lo, int nbw,
-                                                         uint32_t *__restrict__ counts) {
+                                                         uint32_t *__restrict__ counts,
+                                                         uint32_t *__restrict__ umask,
+                                                         int make_mask) {
   extern __shared__ uint32_t hist[];
   const int nw = (nbw + 1) / 2;
+  // make_mask: this pass builds the unit masks (it reads every span); else a
+  // non-null umask lets it skip the units that miss its window
+  const int band = band_of_bins(tk.n_tiles + tk.n_ctiles);
+  const uint32_t wb = band_bits(lo, lo + nbw - 1, band);
+  const uint32_t *skip_mask = make_mask ? nullptr : umask;
   for (int i = threadIdx.x; i < nw; i += NT) hist[i] = 0;
   __syncthreads();
   auto add = [&](uint32_t bin, uint32_t v) {
@@ -104,12 +135,23 @@ __global__ __launch_bounds__(NT) void k_count_packed(const uint2 *__restrict__ s
   };
   {
     int64_t t = 0, kb = unit_block<NT>(0);
-    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    uint2 nxt = (kb + threadIdx.x < n && !unit_skips(skip_mask, kb, wb))
+                    ? span[kb + threadIdx.x]
+                    : make_uint2(kInactive, kInactive);
     while (kb < n) {  // uniform trip count
       const int64_t k = kb + threadIdx.x;
       const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
-      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      nxt = (kn + threadIdx.x < n && !unit_skips(skip_mask, kn, wb))
+                ? span[kn + threadIdx.x]
+                : make_uint2(kInactive, kInactive);
+      if (make_mask) {
+        // the bands of the wave's pairs (the wave's particles share a unit)
+        uint32_t bits = span_bands(s, tk, band);
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) bits |= (uint32_t)__shfl_xor((int)bits, o);
+        if (bits && __lane_id() == 0) atomicOr(&umask[kb / kUnit], bits);
+      }
       // a wave whose particles all miss the window skips it (uniform)
       if (__ballot(span_meets_window(s, tk, lo, nbw)) != 0ull) count_span_with(s, k, rec, tk, add);
       kb = kn;
@@ -132,8 +174,11 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
                                                     TileK tk, int lo, int nbw,
                                                     uint32_t *__restrict__ cursor,
                                                     uint32_t *__restrict__ pairs,
-                                                    unsigned long long *__restrict__ keys) {
+                                                    unsigned long long *__restrict__ keys,
+                                                    const uint32_t *__restrict__ umask) {
   extern __shared__ uint32_t hist[];
+  // a non-null umask: units whose bands miss the window are skipped unread
+  const uint32_t wb = band_bits(lo, lo + nbw - 1, band_of_bins(tk.n_tiles + tk.n_ctiles));
   const bool paper = tk.bin_rule == 1;
   // (wraps above the window's top when bin < lo)
   auto in_win = [&](uint32_t bin) { return bin - (uint32_t)lo < (uint32_t)nbw; };
@@ -144,12 +189,16 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
   __syncthreads();
   {
     int64_t t = 0, kb = unit_block<NT>(0);
-    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    uint2 nxt = (kb + threadIdx.x < n && !unit_skips(umask, kb, wb))
+                    ? span[kb + threadIdx.x]
+                    : make_uint2(kInactive, kInactive);
     for (; kb < n; kb = unit_block<NT>(t)) {
       const int64_t k = kb + threadIdx.x;
       const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
-      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      nxt = (kn + threadIdx.x < n && !unit_skips(umask, kn, wb))
+                ? span[kn + threadIdx.x]
+                : make_uint2(kInactive, kInactive);
       // a wave whose particles all miss the window skips it (uniform)
       if (__ballot(span_meets_window(s, tk, lo, nbw)) == 0ull) continue;
       const bool act = s.x != kInactive;
@@ -187,12 +236,16 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
   __syncthreads();
   {
     int64_t t = 0, kb = unit_block<NT>(0);
-    uint2 nxt = (kb + threadIdx.x < n) ? span[kb + threadIdx.x] : make_uint2(kInactive, kInactive);
+    uint2 nxt = (kb + threadIdx.x < n && !unit_skips(umask, kb, wb))
+                    ? span[kb + threadIdx.x]
+                    : make_uint2(kInactive, kInactive);
     for (; kb < n; kb = unit_block<NT>(t)) {
       const int64_t k = kb + threadIdx.x;
       const int64_t kn = unit_block<NT>(++t);
       const uint2 s = nxt;
-      nxt = (kn + threadIdx.x < n) ? span[kn + threadIdx.x] : make_uint2(kInactive, kInactive);
+      nxt = (kn + threadIdx.x < n && !unit_skips(umask, kn, wb))
+                ? span[kn + threadIdx.x]
+                : make_uint2(kInactive, kInactive);
       // a wave whose particles all miss the window skips it (uniform)
       if (__ballot(span_meets_window(s, tk, lo, nbw)) == 0ull) continue;
       const bool act = s.x != kInactive;
@@ -453,7 +506,7 @@ static int64_t bin_pass_grid(K kernel, size_t sh, int64_t n, int nb, int nt = kB
 }
 
 hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
-                        uint32_t *counts, hipStream_t s) {
+                        uint32_t *counts, uint32_t *umask, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
@@ -464,10 +517,17 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
     return hipGetLastError();
   }
   // packed 16-bit bins, in as many equal windows of at most 2 kLdsBins bins
-  // as the bins need (one pass over the spans each)
+  // as the bins need (one pass over the spans each); when the scatter will
+  // need several windows the first pass also builds the unit masks
   const int n_win = (nb + 2 * kLdsBins - 1) / (2 * kLdsBins);
   const int per = (((nb + n_win - 1) / n_win) + 1) & ~1;
   const int64_t units = (n + kUnit - 1) / kUnit;
+  // (worth its cost from three scatter windows on)
+  if (nb <= 2 * kLdsBins) umask = nullptr;
+  if (umask) {
+    const hipError_t e = launch_fill_u32(umask, 0u, units, s);
+    if (e != hipSuccess) return e;
+  }
   for (int lo = 0; lo < nb; lo += per) {
     const int nbw = std::min(per, nb - lo);
     const size_t sh = (size_t)((nbw + 1) / 2) * sizeof(uint32_t);
@@ -475,7 +535,7 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
     const int64_t g = std::max(bin_pass_grid(k_count_packed<2 * kBlock>, sh, n, nbw, 2 * kBlock),
                                (units + kPackedUnits - 1) / kPackedUnits);
     hipLaunchKernelGGL(k_count_packed<2 * kBlock>, dim3((int)g), dim3(2 * kBlock), sh, s, span, r,
-                       n, tk, lo, nbw, counts);
+                       n, tk, lo, nbw, counts, umask, (int)(lo == 0 && umask != nullptr));
   }
   return hipGetLastError();
 }
@@ -528,7 +588,7 @@ hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, i
 
 hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,
                           const TileK &tk, uint32_t *cursor, uint32_t *pairs,
-                          unsigned long long *keys, hipStream_t s) {
+                          unsigned long long *keys, const uint32_t *umask, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const int nb = tk.n_tiles + tk.n_ctiles;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
@@ -537,13 +597,14 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
   // spans) each
   const int n_win = (nb + kLdsBins - 1) / kLdsBins;
   const int per = (nb + n_win - 1) / n_win;
+  if (n_win < 3) umask = nullptr;  // (built by the count from three windows on)
   for (int lo = 0; lo < nb; lo += per) {
     const int nbw = std::min(per, nb - lo);
     const size_t sh = (size_t)nbw * sizeof(uint32_t);
     auto launch = [&](auto kernel, int nt) {
       const int64_t g = bin_pass_grid(kernel, sh, n, nbw, nt);
       hipLaunchKernelGGL(kernel, dim3((int)g), dim3(nt), sh, s, span, r, r2, n, tk, lo, nbw, cursor,
-                         pairs, keys);
+                         pairs, keys, umask);
     };
     // a histogram above 32 KB leaves few workgroups per CU: 512 lanes each
     // keep more waves resident

@@ -91,6 +91,7 @@ struct spl_ctx {
   std::string err;
   DevBuf rec, rec2, span, counts, offsets, cursor, item_off, items[3], pairs, keysA, keysB,
       partial, fin, stats, totals, minmax, himg, chunk[2];
+  DevBuf umask;  // bands of bins per unit of particles (binning in windows)
   hipStream_t copy_stream = nullptr;  // host-to-device copies of spl_render_stream
   hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
   Totals *h_tot = nullptr;   // page-locked host memory ...
@@ -111,7 +112,7 @@ struct spl_ctx {
   int64_t acc_frames = 0;
   // many-view batches
   DevBuf b_rec, b_span, b_counts, b_offsets, b_cursor, b_itemoff, b_totals, b_pairs, b_itf,
-      b_itc, b_views, b_ctr, b_fin, b_stats;
+      b_itc, b_views, b_ctr, b_fin, b_stats, b_umask;
   Totals *h_btot = nullptr;
   ViewK *h_views = nullptr;
   uint32_t *h_ctr = nullptr;
@@ -485,7 +486,10 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   const uint2 *span = (const uint2 *)c->span.p;
   TimedFrame *tf = f.tf;
 
-  if (!f.counted) HIPTRY(c, launch_count(span, f.rec, f.n, tk, counts, s));
+  // unit masks for binning in windows (one word per kUnitParticles)
+  TRY(ensure(c, c->umask, (size_t)(f.n / kUnitParticles + 1) * 4));
+  uint32_t *umask = (uint32_t *)c->umask.p;
+  if (!f.counted) HIPTRY(c, launch_count(span, f.rec, f.n, tk, counts, umask, s));
   mark(tf, 2, s);
   const int chunk[3] = {kChunkSplat, sorted ? kSortChunk : 0, sorted ? kMergeOut : 0};
   const int cchunk[3] = {kChunkLarge, 0, 0};
@@ -519,7 +523,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   unsigned long long *keysB = (unsigned long long *)c->keysB.p;
   mark(tf, 4, s);
   HIPTRY(c, launch_scatter(span, f.rec, f.rec2, f.n, tk, cursor, (uint32_t *)c->pairs.p,
-                           sorted ? keysA : nullptr, s));
+                           sorted ? keysA : nullptr, umask, s));
   mark(tf, 5, s);
   const Item *items0 = (const Item *)c->items[0].p;
   int passes = 0;
@@ -717,6 +721,9 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   TRY(ensure(c, c->b_ctr, 4 * sizeof(uint32_t)));
   TRY(ensure(c, c->b_fin, (size_t)nv * kFinBlocks * kStatPartials * 8));
   TRY(ensure(c, c->b_stats, (size_t)nv * kStatWords * 8));
+  const size_t mstride = (size_t)(n / kUnitParticles + 1);
+  TRY(ensure(c, c->b_umask, (size_t)nv * mstride * 4));
+  uint32_t *umask = (uint32_t *)c->b_umask.p;
   float *rec = (float *)c->b_rec.p;
   uint2 *span = (uint2 *)c->b_span.p;
   uint32_t *counts = (uint32_t *)c->b_counts.p, *offsets = (uint32_t *)c->b_offsets.p;
@@ -737,7 +744,8 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     uint2 *sv = span + (size_t)v * n;
     HIPTRY(c, launch_fill_u32(counts + v * bstride, 0u, nb, s));
     HIPTRY(c, launch_project(pk[v], tk[v], rv, nullptr, sv, 0, tot + v, s, counts + v * bstride));
-    if (!project_counts(tk[v])) HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, s));
+    if (!project_counts(tk[v]))
+      HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, umask + v * mstride, s));
     HIPTRY(c, launch_scan(counts + v * bstride, nb, tk[v].n_tiles, offsets + v * bstride,
                           cursor + v * bstride, chunk, cchunk, minc, itemoff + v * 3 * bstride,
                           tot + v, s));
@@ -830,7 +838,8 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
                                        itc + cb[v], (uint32_t)T.n_fine_items[ks],
                                        (uint32_t)(v - v0)));
         HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n,
-                                 tk[v], cursor + v * bstride, pairs + pb[v], nullptr, q));
+                                 tk[v], cursor + v * bstride, pairs + pb[v], nullptr,
+                                 umask + v * mstride, q));
         HIPTRY(c, launch_fill_f32(outs[v], 0.0f, 3 * (int64_t)tk[v].W * tk[v].H, q));
       }
       ViewK *dviews = (ViewK *)c->b_views.p + v0;
@@ -1424,7 +1433,7 @@ spl_status spl_create(int device, spl_ctx **out) {
    &c->fin, &c->stats, &c->totals, &c->minmax, &c->b_rec, &c->b_span, &c->b_counts,          \
    &c->b_offsets, &c->b_cursor, &c->b_itemoff, &c->b_totals, &c->b_pairs, &c->b_itf,        \
    &c->b_itc, &c->b_views, &c->b_ctr, &c->b_fin, &c->b_stats, &c->himg, &c->chunk[0],        \
-   &c->chunk[1]}
+   &c->chunk[1], &c->umask, &c->b_umask}
 
 spl_status spl_trim(spl_ctx *c) {
   if (!c) return SPL_EINVAL;
@@ -1557,7 +1566,9 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
   HIPTRY(c, launch_fill_u32((uint32_t *)c->totals.p, 0u, sizeof(Totals) / 4, s));
   Totals *tot = (Totals *)c->totals.p;
   HIPTRY(c, launch_span_from_records(rec, n, tk, (uint2 *)c->span.p, tot, s));
-  HIPTRY(c, launch_count((const uint2 *)c->span.p, rec, n, tk, counts, s));
+  TRY(ensure(c, c->umask, (size_t)(n / kUnitParticles + 1) * 4));
+  uint32_t *umask = (uint32_t *)c->umask.p;
+  HIPTRY(c, launch_count((const uint2 *)c->span.p, rec, n, tk, counts, umask, s));
   const int chunk[3] = {0, by_depth ? kSortChunk : 0, by_depth ? kMergeOut : 0};
   const int cchunk[3] = {0, 0, 0};
   const int minc[3] = {1, 1, kSortChunk + 1};
@@ -1574,7 +1585,7 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
     return fail(c, SPL_ENOMEM, "pairs_cap %lld < %llu entries", (long long)pairs_cap, T.n_pairs);
   if (!by_depth) {
     HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, rec2, n, tk, (uint32_t *)c->cursor.p,
-                             pairs, nullptr, s));
+                             pairs, nullptr, umask, s));
     HIPTRY(c, hipStreamSynchronize(s));
     return SPL_OK;
   }
@@ -1588,7 +1599,7 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
   }
   unsigned long long *A = (unsigned long long *)c->keysA.p, *B = (unsigned long long *)c->keysB.p;
   HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, rec2, n, tk, (uint32_t *)c->cursor.p,
-                           nullptr, A, s));
+                           nullptr, A, umask, s));
   HIPTRY(c, launch_sort_chunks(A, (const Item *)c->items[1].p, (int)T.n_items[1], s));
   int passes = 0;
   for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {
@@ -1694,7 +1705,7 @@ spl_status spl_render_noalloc(spl_ctx *c, const spl_particles *p, const spl_came
   DevBuf *bufs[] = {&c->rec,      &c->rec2,     &c->span,  &c->counts,  &c->offsets,
                     &c->cursor,   &c->item_off, &c->items[0], &c->items[1], &c->items[2],
                     &c->pairs,    &c->keysA,    &c->keysB, &c->partial, &c->fin,
-                    &c->stats,    &c->totals};
+                    &c->stats,    &c->totals,   &c->umask};
   constexpr int kBufs = (int)(sizeof(bufs) / sizeof(bufs[0]));
   DevBuf saved[kBufs];
   for (int k = 0; k < kBufs; ++k) {

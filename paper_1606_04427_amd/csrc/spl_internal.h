@@ -208,8 +208,13 @@ hipError_t launch_span_from_records(const float *rec, int64_t n, const TileK &tk
 hipError_t launch_scalar_range(const ProjK &pk, int n_species, int log10, double *out_minmax,
                                hipStream_t s);
 
+// Bin counts from the spans.  umask: ceil(n / kUnitParticles) words the
+// count fills with the bands of bins each unit of particles reaches when the
+// scatter will need three or more windows of bins (else untouched); pass the
+// same buffer to launch_scatter.
+constexpr int kUnitParticles = 1024;
 hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
-                        uint32_t *counts, hipStream_t s);
+                        uint32_t *counts, uint32_t *umask, hipStream_t s);
 // Exclusive scan of counts (n_bins) into offsets (n_bins + 1) and cursor; item
 // counts for up to three chunk sizes (chunk[k] > 0, powers of two; bins below min_count[k]
 // get no item; fine chunk applies to fine bins, cchunk[k] to large bins).
@@ -227,7 +232,7 @@ hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, i
                               uint32_t view = 0);
 hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,
                           const TileK &tk, uint32_t *cursor, uint32_t *pairs,
-                          unsigned long long *keys, hipStream_t s);
+                          unsigned long long *keys, const uint32_t *umask, hipStream_t s);
 
 hipError_t launch_sort_chunks(unsigned long long *keys, const Item *items, int n_items,
                               hipStream_t s);

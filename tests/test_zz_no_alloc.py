@@ -75,6 +75,38 @@ def test_noalloc_equals_render_on_two_calls(env, mode):
     ctx.close()
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_noalloc_with_binning_in_windows(env, mode):
+    """16 px tiles at 4096 x 2304 (36864 fine bins and the large-particle
+    bins): the count runs in two windows of packed bins and the scatter in
+    three with the unit masks, whose buffer the no-allocation call also takes
+    from the scratch and gives back."""
+    import torch
+
+    B, R = env
+    ctx = B.Context(0)
+    ps = synth.soneira_peebles(200_000, seed=63, absorption=True)
+    looks, pals = _looks(ps)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    prm = B.make_params(mode, B.Palettes(pals), looks, tile=16)
+    pose = synth.random_poses(1, seed=403, width=4096, height=2304)[0]
+    print(f"noalloc windows mode={mode}", flush=True)
+    got, st = ctx.spl_render_noalloc(parts, pose, prm)
+    torch.cuda.synchronize()
+    assert ctx.workspace_bytes() == 0
+    ref, st1 = ctx.spl_render(parts, pose, prm)
+    torch.cuda.synchronize()
+    g, r = got.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
+    assert st["n_pairs"] == st1["n_pairs"] and st["n_active"] > 0
+    if mode == 2:
+        assert np.array_equal(g, r)
+    else:
+        assert rel_l2(g, r) < 1e-6
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    assert rel_l2(g, R.render(R.Particles(ps), pose, R.params(mode, L))) < 1e-5
+    ctx.close()
+
+
 def _raw_particles(B, n, h_value):
     """n particles in a thin sheet in front of the camera, all arrays on the
     device; returns the struct and the tensors that keep it alive."""
