@@ -791,6 +791,12 @@ def run_batched(args, torch, B):
                 ctx.spl_render(parts, p, prms[k], out=imgs[k], stats=False)
 
         res = {}
+        # stage times of one batched step (library HIP events)
+        bstep()
+        _, sms, sby, sfr = timed_steps(ctx, bstep, 1, 0, torch)
+        res["stages_ms_per_step"] = {B.STAGES[k]: sms[k] for k in range(len(sms))}
+        log(f"{dt_name} stages per step (ms): "
+            + ", ".join(f"{k} {v:.1f}" for k, v in res["stages_ms_per_step"].items() if v > 0.05))
         for name, fn in (("batched", bstep), ("batched_graph", gstep), ("per_view", pstep)):
             fn()
             torch.cuda.synchronize()
