@@ -521,16 +521,17 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 // Sorted mode.  Staging as in splat_add_item (with log2(e)/sigma^2 in place
 // of its pre-scaled distances); each micro-tile's list is built
 // by ballots in the depth order of the tile list.  The lists, laid end to
-// end, are cut into 16 ranges whose lengths differ by at most one, one per
-// 16-lane group (one pixel per lane), and walked in lockstep as in the
-// additive kernel.  A group
+// end, are cut into 32 ranges whose lengths differ by at most one, one per
+// 8-lane group (two pixels per lane, rows r and r + 2 of a micro-tile
+// column, sharing the entry's LDS reads and horizontal distance), and walked
+// in lockstep as in the additive kernel.  A group
 // composites each piece of a micro-tile list it meets front to back from
 // (C, T) = (0, 1): C += T E tau phi(a tau), T *= exp(-a tau), with
 // phi(x) = (1 - e^-x)/x from a polynomial below x = 1/2 (no cancellation)
 // and from the exponential above, and leaves the piece's
 // (C, T) in LDS.  After the walk each lane merges, for its pixels, the pieces
 // of the batch in list order into the running (C, T): C += T C_piece,
-// T *= T_piece.  The pieces of one batch fill at most NQ + 15 slots: the
+// T *= T_piece.  The pieces of one batch fill at most NQ + 31 slots: the
 // (group, micro-tile) pairs of the walk form a staircase, so group + micro-tile
 // numbers them.
 template <int T>
@@ -548,8 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   constexpr int PX = NP / kBlock;      // pixels per lane in the merge
   constexpr int MX = T / 4;
   constexpr int NQ = MX * MX;
-  constexpr int MT = NQ / 16;          // lists built per group
-  constexpr int NS = NQ + 15;          // piece slots
+  constexpr int MT = NQ / 16;          // lists built per 16-lane group
+  constexpr int NS = NQ + 31;          // piece slots
   constexpr float kLog2e = 1.4426950408889634f;
   __shared__ float4 s_pos[kBlock];
   __shared__ float4 s_col[kBlock];
@@ -569,8 +570,10 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   const bool multi = cnt_tile > (uint32_t)chunk;
   // the buffer the list's merge passes left it in
   const unsigned long long *const src = (merge_passes(cnt_tile, sort_chunk) & 1) ? keys_b : keys;
+  // list building: 16-lane groups; walk: 8-lane groups, lane (lx, ly) of a
+  // group takes the micro-tile pixels (lx, ly) and (lx, ly + 2)
   const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
-  const int lx = l & 3, ly = l >> 2;
+  const int wg = tid >> 3, wl = tid & 7, lx = wl & 3, ly = wl >> 2;
   const float qmax = tk.nu * tk.nu * kLog2e;
 
   // running (C, T) of the lane's pixels p2 = tid + m * kBlock
@@ -631,9 +634,9 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
     }
     __syncthreads();
     const int total = s_start[NQ];
-    const int steps = total >> 4, rem = total & 15;
+    const int steps = total >> 5, rem = total & 31;
     {
-      const int r0 = grp * steps + min(grp, rem);
+      const int r0 = wg * steps + min(wg, rem);
       int q = 0;
 #pragma unroll
       for (int h = NQ / 2; h >= 1; h >>= 1)
@@ -641,32 +644,15 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
       int lp = q * kBlock + (r0 - s_start[q]);
       int le = q * kBlock + (s_start[q + 1] - s_start[q]);
       float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
-      float b0 = 0.f, b1 = 0.f, b2 = 0.f, tr = 1.f;
-      auto step = [&]() {
-        if (lp == le) {
-          // end of this piece of the micro-tile's list
-          s_piece[grp + q][l] = make_float4(b0, b1, b2, tr);
-          b0 = b1 = b2 = 0.f;
-          tr = 1.f;
-          do {
-            ++q;
-          } while (s_start[q + 1] == s_start[q]);
-          lp = q * kBlock;
-          le = lp + (s_start[q + 1] - s_start[q]);
-          px = (float)((q % MX) * 4 + lx);
-          py = (float)((q / MX) * 4 + ly);
-        }
-        const int j = (&s_list[0][0])[lp++];
-        const float4 p = s_pos[j];
-        const float4 c = s_col[j];
-        // the form with pre-scaled distances (as in the additive splat)
-        // takes one register more here, which costs a wave per SIMD
-        const float dx = (px - p.x) + p.y;
-        const float dy = (py - p.z) + p.w;
-        const float qq = (dx * dx + dy * dy) * c.x;
+      // (C, T) of the piece for rows ly (a) and ly + 2 (b)
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, ta = 1.f;
+      float b0 = 0.f, b1 = 0.f, b2 = 0.f, tb = 1.f;
+      // one entry's slab, front to back, onto a pixel's running piece
+      auto slab = [&](const float qq, const float ap, const float4 &c, float &c0, float &c1,
+                      float &c2, float &tr) {
         if (qq <= qmax) {
           const float e = __builtin_amdgcn_exp2f(-qq);
-          const float x = s_ap[j] * e;
+          const float x = ap * e;
           float phi, em;  // phi(x), exp(-x) - 1
           if (x < 0.5f) {
             // degree-5 fit to phi on [0, 1/2], least squares in relative
@@ -683,15 +669,45 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
             phi = -em * __builtin_amdgcn_rcpf(x);
           }
           const float tw = tr * e * phi;
-          b0 = fmaf(tw, c.y, b0);
-          b1 = fmaf(tw, c.z, b1);
-          b2 = fmaf(tw, c.w, b2);
+          c0 = fmaf(tw, c.y, c0);
+          c1 = fmaf(tw, c.z, c1);
+          c2 = fmaf(tw, c.w, c2);
           tr = fmaf(tr, em, tr);
         }
       };
+      auto put_piece = [&]() {
+        s_piece[wg + q][ly * 4 + lx] = make_float4(a0, a1, a2, ta);
+        s_piece[wg + q][(ly + 2) * 4 + lx] = make_float4(b0, b1, b2, tb);
+      };
+      auto step = [&]() {
+        if (lp == le) {
+          // end of this piece of the micro-tile's list
+          put_piece();
+          a0 = a1 = a2 = 0.f;
+          b0 = b1 = b2 = 0.f;
+          ta = tb = 1.f;
+          do {
+            ++q;
+          } while (s_start[q + 1] == s_start[q]);
+          lp = q * kBlock;
+          le = lp + (s_start[q + 1] - s_start[q]);
+          px = (float)((q % MX) * 4 + lx);
+          py = (float)((q / MX) * 4 + ly);
+        }
+        const int j = (&s_list[0][0])[lp++];
+        const float4 p = s_pos[j];
+        const float4 c = s_col[j];
+        const float ap = s_ap[j];
+        const float dx = (px - p.x) + p.y;
+        const float dy = (py - p.z) + p.w;
+        const float dz = ((py + 2.f) - p.z) + p.w;
+        const float dx2 = dx * dx;
+        slab((dx2 + dy * dy) * c.x, ap, c, a0, a1, a2, ta);
+        slab((dx2 + dz * dz) * c.x, ap, c, b0, b1, b2, tb);
+      };
       for (int t = 0; t < steps; ++t) step();  // uniform across the workgroup
-      if (grp < rem) step();
-      if (steps > 0 || grp < rem) s_piece[grp + q][l] = make_float4(b0, b1, b2, tr);
+      if (wg < rem) step();
+      if (steps > 0 || wg < rem) put_piece();
     }
     __syncthreads();
     // merge the pieces of each pixel's micro-tile in list order
