@@ -518,8 +518,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
   }
 }
 
-// Sorted mode.  Staging as in splat_add_item (with log2(e)/sigma^2 in place
-// of its pre-scaled distances); each micro-tile's list is built
+// Sorted mode.  Staging as in splat_add_item; each micro-tile's list is built
 // by ballots in the depth order of the tile list.  The lists, laid end to
 // end, are cut into 32 ranges whose lengths differ by at most one, one per
 // 8-lane group (two pixels per lane, rows r and r + 2 of a micro-tile
@@ -552,8 +551,13 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   constexpr int MT = NQ / 16;          // lists built per 16-lane group
   constexpr int NS = NQ + 31;          // piece slots
   constexpr float kLog2e = 1.4426950408889634f;
-  __shared__ float4 s_pos[kBlock];
-  __shared__ float4 s_col[kBlock];
+  constexpr float kRootLog2e = 1.2011224087864498f;  // sqrt(log2 e)
+  constexpr float kHalfSpan = 0.5f * (float)(T - 1);  // tile centre, in pixels
+  // as in the additive splat: with g = sqrt(log2 e)/sigma and pixel positions
+  // taken from the tile centre, the scaled offset of a pixel centre from the
+  // particle is g c + ox (one FMA)
+  __shared__ float4 s_pos[kBlock];     // ox, oy, g, -
+  __shared__ float4 s_col[kBlock];     // -, colour
   __shared__ float s_ap[kBlock];       // a / (pi sigma^2)
   // micro-tiles each staged entry's truncation disc can reach, one bit each
   using MaskT = typename std::conditional<(NQ > 32), unsigned long long, uint32_t>::type;
@@ -595,8 +599,11 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
       const float4 r0 = rec[2 * (size_t)pid];
       const float4 r1 = rec[2 * (size_t)pid + 1];
       // (listed records are finite with sigma > 0)
-      s_pos[tid] = make_float4(r0.x - (float)x0, 0.5f - r0.y, r0.z - (float)y0, 0.5f - r0.w);
-      s_col[tid] = make_float4(kLog2e / (r1.x * r1.x), r1.y, r1.z, r1.w);
+      const float g = kRootLog2e * __builtin_amdgcn_rcpf(r1.x);
+      s_pos[tid] = make_float4(fmaf(kHalfSpan - (r0.x - (float)x0), g, (0.5f - r0.y) * g),
+                               fmaf(kHalfSpan - (r0.z - (float)y0), g, (0.5f - r0.w) * g), g,
+                               0.f);
+      s_col[tid] = make_float4(0.f, r1.y, r1.z, r1.w);
       s_ap[tid] = rec2[pid].x;
       // micro-tiles the disc can reach (the additive splat's test)
       mask = disc_micro_tiles<MX, MaskT>((r0.x - (float)x0) + (r0.y - 0.5f),
@@ -643,7 +650,8 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
         if (s_start[q + h] <= r0) q += h;
       int lp = q * kBlock + (r0 - s_start[q]);
       int le = q * kBlock + (s_start[q + 1] - s_start[q]);
-      float px = (float)((q % MX) * 4 + lx), py = (float)((q / MX) * 4 + ly);
+      float px = (float)((q % MX) * 4 + lx) - kHalfSpan;
+      float py = (float)((q / MX) * 4 + ly) - kHalfSpan;
       // (C, T) of the piece for rows ly (a) and ly + 2 (b)
       float a0 = 0.f, a1 = 0.f, a2 = 0.f, ta = 1.f;
       float b0 = 0.f, b1 = 0.f, b2 = 0.f, tb = 1.f;
@@ -691,19 +699,21 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
           } while (s_start[q + 1] == s_start[q]);
           lp = q * kBlock;
           le = lp + (s_start[q + 1] - s_start[q]);
-          px = (float)((q % MX) * 4 + lx);
-          py = (float)((q / MX) * 4 + ly);
+          px = (float)((q % MX) * 4 + lx) - kHalfSpan;
+          py = (float)((q / MX) * 4 + ly) - kHalfSpan;
         }
         const int j = (&s_list[0][0])[lp++];
         const float4 p = s_pos[j];
         const float4 c = s_col[j];
         const float ap = s_ap[j];
-        const float dx = (px - p.x) + p.y;
-        const float dy = (py - p.z) + p.w;
-        const float dz = ((py + 2.f) - p.z) + p.w;
+        // squared distances in units of sigma^2 / log2 e; two rows down
+        // adds 2 g
+        const float dx = fmaf(px, p.z, p.x);
+        const float dy = fmaf(py, p.z, p.y);
+        const float dz = fmaf(2.f, p.z, dy);
         const float dx2 = dx * dx;
-        slab((dx2 + dy * dy) * c.x, ap, c, a0, a1, a2, ta);
-        slab((dx2 + dz * dz) * c.x, ap, c, b0, b1, b2, tb);
+        slab(fmaf(dy, dy, dx2), ap, c, a0, a1, a2, ta);
+        slab(fmaf(dz, dz, dx2), ap, c, b0, b1, b2, tb);
       };
       for (int t = 0; t < steps; ++t) step();  // uniform across the workgroup
       if (wg < rem) step();
