@@ -25,6 +25,11 @@ namespace spl {
 namespace {
 
 constexpr int kLdsBins = 16384;  // 64 KB of u32 bins
+// Above that a window takes the CU's whole LDS (160 KB on gfx950): one
+// 1024-lane workgroup per CU with up to kBigBins u32 bins (scatter) or twice
+// as many packed 16-bit bins (count).
+constexpr int kBigThreads = 1024;
+constexpr int kBigBins = 40960;
 constexpr int kChunk = 4096;     // particles per workgroup when the grid is not sized by occupancy
 
 // The count and scatter grids hold no more workgroups than the device keeps
@@ -505,6 +510,22 @@ static int64_t bin_pass_grid(K kernel, size_t sh, int64_t n, int nb, int nt = kB
   return std::min((n + kChunk - 1) / kChunk, cap);
 }
 
+// Windows of the scatter for nb bins: up to kLdsBins bins each while the bins
+// fit 64 KB, else up to kBigBins.
+static int scatter_windows(int nb) {
+  const int cap = nb > kLdsBins ? kBigBins : kLdsBins;
+  return (nb + cap - 1) / cap;
+}
+
+// Lets a kernel take more than 64 KB of dynamic LDS (a host-side attribute,
+// set before each such launch: kernels of one signature share a pointer type).
+template <class K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const TileK &tk,
                         uint32_t *counts, uint32_t *umask, hipStream_t s) {
   if (n == 0) return hipSuccess;
@@ -516,14 +537,17 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
     hipLaunchKernelGGL(k_count, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
     return hipGetLastError();
   }
-  // packed 16-bit bins, in as many equal windows of at most 2 kLdsBins bins
-  // as the bins need (one pass over the spans each); when the scatter will
-  // need several windows the first pass also builds the unit masks
-  const int n_win = (nb + 2 * kLdsBins - 1) / (2 * kLdsBins);
+  // packed 16-bit bins: one 512-lane window up to 2 kLdsBins bins (64 KB),
+  // else equal windows of at most 2 kBigBins bins in the CU's whole LDS (one
+  // pass over the spans each); when the scatter will need three or more
+  // windows (where that pays) the first pass also builds the unit masks
+  const bool big = nb > 2 * kLdsBins;
+  const int cap = big ? 2 * kBigBins : 2 * kLdsBins;
+  const int nt = big ? kBigThreads : 2 * kBlock;
+  const int n_win = (nb + cap - 1) / cap;
   const int per = (((nb + n_win - 1) / n_win) + 1) & ~1;
   const int64_t units = (n + kUnit - 1) / kUnit;
-  // (worth its cost from three scatter windows on)
-  if (nb <= 2 * kLdsBins) umask = nullptr;
+  if (scatter_windows(nb) < 3) umask = nullptr;
   if (umask) {
     const hipError_t e = launch_fill_u32(umask, 0u, units, s);
     if (e != hipSuccess) return e;
@@ -531,13 +555,20 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
   for (int lo = 0; lo < nb; lo += per) {
     const int nbw = std::min(per, nb - lo);
     const size_t sh = (size_t)((nbw + 1) / 2) * sizeof(uint32_t);
-    // 512 lanes per workgroup, as in the scatter with a large histogram
-    const int64_t g = std::max(bin_pass_grid(k_count_packed<2 * kBlock>, sh, n, nbw, 2 * kBlock),
-                               (units + kPackedUnits - 1) / kPackedUnits);
-    hipLaunchKernelGGL(k_count_packed<2 * kBlock>, dim3((int)g), dim3(2 * kBlock), sh, s, span, r,
-                       n, tk, lo, nbw, counts, umask, (int)(lo == 0 && umask != nullptr));
+    auto launch = [&](auto kernel) {
+      hipError_t e = allow_lds(kernel, sh);
+      if (e != hipSuccess) return e;
+      const int64_t g =
+          std::max(bin_pass_grid(kernel, sh, n, nbw, nt), (units + kPackedUnits - 1) / kPackedUnits);
+      hipLaunchKernelGGL(kernel, dim3((int)g), dim3(nt), sh, s, span, r, n, tk, lo, nbw, counts,
+                         umask, (int)(lo == 0 && umask != nullptr));
+      return hipGetLastError();
+    };
+    const hipError_t e = big ? launch(k_count_packed<kBigThreads>)
+                             : launch(k_count_packed<2 * kBlock>);
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t *offsets,
@@ -593,35 +624,35 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
   const int nb = tk.n_tiles + tk.n_ctiles;
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
-  // equal windows of at most kLdsBins bins, one launch (two passes over the
-  // spans) each
-  const int n_win = (nb + kLdsBins - 1) / kLdsBins;
+  // equal windows (one launch, two passes over the spans, each)
+  const int n_win = scatter_windows(nb);
   const int per = (nb + n_win - 1) / n_win;
   if (n_win < 3) umask = nullptr;  // (built by the count from three windows on)
   for (int lo = 0; lo < nb; lo += per) {
     const int nbw = std::min(per, nb - lo);
     const size_t sh = (size_t)nbw * sizeof(uint32_t);
     auto launch = [&](auto kernel, int nt) {
+      hipError_t e = allow_lds(kernel, sh);
+      if (e != hipSuccess) return e;
       const int64_t g = bin_pass_grid(kernel, sh, n, nbw, nt);
       hipLaunchKernelGGL(kernel, dim3((int)g), dim3(nt), sh, s, span, r, r2, n, tk, lo, nbw, cursor,
                          pairs, keys, umask);
+      return hipGetLastError();
     };
     // a histogram above 32 KB leaves few workgroups per CU: 512 lanes each
-    // keep more waves resident
-    const bool wide = nbw > kLdsBins / 2;
-    if (keys) {
-      if (wide)
-        launch(k_scatter<true, 2 * kBlock>, 2 * kBlock);
-      else
-        launch(k_scatter<true, kBlock>, kBlock);
-    } else {
-      if (wide)
-        launch(k_scatter<false, 2 * kBlock>, 2 * kBlock);
-      else
-        launch(k_scatter<false, kBlock>, kBlock);
-    }
+    // keep more waves resident; above 64 KB one 1024-lane workgroup per CU
+    hipError_t e;
+    if (nbw > kLdsBins)
+      e = keys ? launch(k_scatter<true, kBigThreads>, kBigThreads)
+               : launch(k_scatter<false, kBigThreads>, kBigThreads);
+    else if (nbw > kLdsBins / 2)
+      e = keys ? launch(k_scatter<true, 2 * kBlock>, 2 * kBlock)
+               : launch(k_scatter<false, 2 * kBlock>, 2 * kBlock);
+    else
+      e = keys ? launch(k_scatter<true, kBlock>, kBlock) : launch(k_scatter<false, kBlock>, kBlock);
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace spl
