@@ -292,6 +292,30 @@ def test_binning_bit_exact(env, tile, rule):
             assert np.array_equal(np.sort(p), np.sort(rp))
 
 
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_binning_bit_exact_in_windows(env, tile, rule):
+    """More bins than one workgroup's LDS holds: at 512 x 384, 1 px tiles give
+    196608 bins (the count in three windows of packed bins, the scatter in
+    five windows with the per-unit band masks), 2 px tiles 49152 (the scatter
+    in two windows, no masks)."""
+    B, ctx, R = env
+    ps, poses = _sp_case(30000, W=512, H=384, absorption=True)
+    looks, pals = _looks(ps, n_species=2, brightness=0.05)
+    W, H = poses[0].width, poses[0].height
+    rec, rec2, _ = _records(env, ps, poses[0], 2, looks, pals)
+    for by_depth in (False, True):
+        c, o, p = ctx.spl_bin(rec, rec2, W, H, tile, 3.0, rule, by_depth)
+        c, o, p = c.cpu().numpy().view(np.uint32), o.cpu().numpy().view(np.uint32), p.cpu().numpy().view(np.uint32)
+        rc, ro, rp = R.bin_records(rec.cpu().numpy(), rec2.cpu().numpy(), W, H, tile, 3.0, rule, by_depth)
+        assert np.array_equal(c, rc) and np.array_equal(o, ro)
+        if by_depth:
+            assert np.array_equal(p, rp)
+        else:
+            t = np.repeat(np.arange(len(rc), dtype=np.uint64), rc.astype(np.int64)) << np.uint64(32)
+            assert np.array_equal(np.sort(t | p.astype(np.uint64)), np.sort(t | rp.astype(np.uint64)))
+
+
 def test_paper_rule_hand_case_on_device(env):
     import json
     import os

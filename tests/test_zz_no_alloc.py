@@ -77,10 +77,11 @@ def test_noalloc_equals_render_on_two_calls(env, mode):
 
 @pytest.mark.parametrize("mode", [1, 2])
 def test_noalloc_with_binning_in_windows(env, mode):
-    """16 px tiles at 4096 x 2304 (36864 fine bins and the large-particle
-    bins): the count runs in two windows of packed bins and the scatter in
-    three with the unit masks, whose buffer the no-allocation call also takes
-    from the scratch and gives back."""
+    """16 px tiles at 8192 x 3072 (98304 fine bins and 6144 large-particle
+    bins): more bins than the CU's LDS holds, so the count runs in two
+    windows and the scatter in three with the per-unit band masks, whose
+    buffer the no-allocation call also takes from the scratch and gives
+    back."""
     import torch
 
     B, R = env
@@ -89,7 +90,7 @@ def test_noalloc_with_binning_in_windows(env, mode):
     looks, pals = _looks(ps)
     parts = B.DeviceParticles(ps, "cuda:0")
     prm = B.make_params(mode, B.Palettes(pals), looks, tile=16)
-    pose = synth.random_poses(1, seed=403, width=4096, height=2304)[0]
+    pose = synth.random_poses(1, seed=403, width=8192, height=3072)[0]
     print(f"noalloc windows mode={mode}", flush=True)
     got, st = ctx.spl_render_noalloc(parts, pose, prm)
     torch.cuda.synchronize()
