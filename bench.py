@@ -380,6 +380,14 @@ def run_additive(args, torch, B):
         torch.cuda.synchronize()
         del src, dst
 
+    # the additive image in list order (run-to-run bit-identical): the same
+    # poses one view per call, against the unordered one-view-per-call step
+    det_rec = None
+    if not args.no_deterministic_leg:
+        det_rec = deterministic_leg(args, torch, B, ctx, parts, poses, pal_d, looks, imgs,
+                                    per_view["ms_per_step"])
+        log("deterministic: " + json.dumps({k: v for k, v in det_rec.items() if k != "stages"}))
+
     # out-of-core rendering of the same set from page-locked host memory, in
     # chunks through two device buffers (copies overlapped with rendering)
     stream_rec = None
@@ -411,6 +419,7 @@ def run_additive(args, torch, B):
         "batched_graph_replay": graphs,
         "per_pose": per_pose,
         "out_of_core": stream_rec,
+        "deterministic": det_rec,
         "bandwidth_probe": probe,
         "mean_box_px_per_small_particle": footprint(pose_updates, pose_small),
         "frames": [{"n_active": s["n_active"], "n_pairs": s["n_pairs"], "n_large": s["n_large"],
@@ -432,6 +441,36 @@ def run_additive(args, torch, B):
             ps, poses, looks, pals, args.cpu_sample or 5_000_000, B.SPL_ADD_AEQE)
         log(f"cpu baseline in {time.time() - t:.1f} s")
     return out
+
+
+def deterministic_leg(args, torch, B, ctx, parts, poses, pal_d, looks, imgs, free_ms):
+    """The additive frame with spl_params.deterministic = 1 (tile lists in
+    ascending particle index, each list summed in that order): ms per step of
+    the poses one view per call, its stage times, whether two renders of a
+    pose agree bit for bit, and its difference from the unordered image."""
+    prm = B.make_params(B.SPL_ADD_AEQE, pal_d, looks, deterministic=1)
+    free = B.make_params(B.SPL_ADD_AEQE, pal_d, looks)
+
+    def step():
+        for k, pose in enumerate(poses):
+            ctx.spl_render_dataset(parts, pose, prm, out=imgs[k], stats=False)
+
+    elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
+    ms_per_step = 1e3 * elapsed / args.steps
+    same, err = [], []
+    for k in (0, len(poses) // 2):
+        a = ctx.spl_render_dataset(parts, poses[k], prm)[0].cpu().numpy()
+        ctx.spl_render_dataset(parts, poses[k], free, out=imgs[k], stats=False)
+        u = imgs[k].cpu().numpy()
+        b = ctx.spl_render_dataset(parts, poses[k], prm)[0].cpu().numpy()
+        same.append(bool(np.array_equal(a.view(np.uint32), b.view(np.uint32))))
+        den = float(np.linalg.norm(u.astype(np.float64)))
+        err.append(float(np.linalg.norm(a.astype(np.float64) - u)) / max(den, 1e-300))
+    return {"ms_per_step": ms_per_step,
+            "particles_per_s": args.steps * len(poses) * parts.n / elapsed,
+            "vs_unordered_one_view_per_call": free_ms / ms_per_step,
+            "bit_identical_repeats": same, "rel_l2_vs_unordered": err,
+            "stages": stage_table(B, ms, by, frames)}
 
 
 def sorted_leg(args, torch, B, ctx):
@@ -1020,6 +1059,8 @@ def main():
                     help="additive: skip the serving sub-record")
     ap.add_argument("--no-sorted-leg", action="store_true",
                     help="additive: skip the depth-sorted sub-record")
+    ap.add_argument("--no-deterministic-leg", action="store_true",
+                    help="additive: skip the list-order (bit-identical) frames")
     ap.add_argument("--no-graph-replay", action="store_true",
                     help="additive: skip the timing of the captured-graph replay")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,

@@ -121,6 +121,18 @@ typedef struct {
   int32_t flux_check; /* additive modes, 1: also compute the expected flux
                          (spl_stats.expected_flux), one more pass over the
                          particles' pixel boxes */
+  int32_t deterministic; /* additive modes, 1: the image is the same bit for
+                         bit on every run (Sect. 3.1: each tile's pixels are
+                         drawn by the one worker that owns them, so nothing
+                         races).  Each tile list is put in ascending particle
+                         index (the scatter's list, then a sort of each list
+                         on the index) and drawn in that order: per pixel the
+                         contributions are summed in list order, long lists
+                         in chunk order.  The large-particle path is off.
+                         Costs about what the depth sort of SPL_SORTED costs.
+                         0: sums in an order the device schedule picks
+                         (reproducible to rounding).  Ignored in SPL_SORTED,
+                         which is always deterministic. */
 } spl_params;
 
 /* Per-render statistics; flux and max are FP64 reductions over the final
@@ -184,8 +196,9 @@ spl_status spl_project(spl_ctx *ctx, const spl_particles *p, const spl_camera *c
 /* Tile lists from records (Sect. 3.1; tile-list pseudocode figure): counts
  * (n_tiles), offsets (n_tiles + 1, exclusive scan) and pairs (particle
  * indices grouped by tile).  Within a tile, pairs are in ascending
- * (view-depth bits, index) order when by_depth = 1 (needs rec2), otherwise in
- * no specified order.  tile: any edge >= 1 px.  Device arrays; *n_pairs
+ * (view-depth bits, index) order when by_depth = 1 (needs rec2), in ascending
+ * index when by_depth = 2 (the stable order), and in no specified order when
+ * by_depth = 0.  tile: any edge >= 1 px.  Device arrays; *n_pairs
  * (host) gets the total.  SPL_ENOMEM if pairs_cap is too small (counts and
  * offsets are still written).  Synchronises. */
 spl_status spl_bin(spl_ctx *ctx, int64_t n, const float *rec, const float *rec2,

@@ -58,7 +58,7 @@ class spl_params(C.Structure):
                 ("looks", spl_look * SPL_MAX_SPECIES), ("k_sigma", C.c_double),
                 ("sigma_min", C.c_double), ("nu", C.c_double), ("tile", C.c_int32),
                 ("bin_rule", C.c_int32), ("large_cut", C.c_double), ("normalise", C.c_int32),
-                ("flux_check", C.c_int32)]
+                ("flux_check", C.c_int32), ("deterministic", C.c_int32)]
 
 
 class spl_stats(C.Structure):
@@ -313,7 +313,8 @@ class Palettes:
 
 
 def make_params(mode, palettes: Palettes, looks, k_sigma=1.0 / 3.0, sigma_min=0.5, nu=3.0,
-                tile=0, bin_rule=0, large_cut=0.0, normalise=0, flux_check=0) -> spl_params:
+                tile=0, bin_rule=0, large_cut=0.0, normalise=0, flux_check=0,
+                deterministic=0) -> spl_params:
     """looks: list of dicts with brightness, lo, hi, log10 and vector (1: the
     species takes its colour from the particles' rgb vectors), one per
     species.  The returned parameters keep `palettes` alive: they hold its
@@ -338,6 +339,7 @@ def make_params(mode, palettes: Palettes, looks, k_sigma=1.0 / 3.0, sigma_min=0.
     p.large_cut = large_cut
     p.normalise = normalise
     p.flux_check = flux_check
+    p.deterministic = deterministic
     return p
 
 

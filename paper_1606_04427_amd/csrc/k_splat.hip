@@ -533,7 +533,7 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 // T *= T_piece.  The pieces of one batch fill at most NQ + 31 slots: the
 // (group, micro-tile) pairs of the walk form a staircase, so group + micro-tile
 // numbers them.
-template <int T>
+template <int T, bool kAbs>
 __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ items,
                                                       const unsigned long long *__restrict__ keys,
                                                       const unsigned long long *__restrict__ keys_b,
@@ -604,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
                                fmaf(kHalfSpan - (r0.z - (float)y0), g, (0.5f - r0.w) * g), g,
                                0.f);
       s_col[tid] = make_float4(0.f, r1.y, r1.z, r1.w);
-      s_ap[tid] = rec2[pid].x;
+      if (kAbs) s_ap[tid] = rec2[pid].x;
       // micro-tiles the disc can reach (the additive splat's test)
       mask = disc_micro_tiles<MX, MaskT>((r0.x - (float)x0) + (r0.y - 0.5f),
                                          (r0.z - (float)y0) + (r0.w - 0.5f), tk.nu * r1.x);
@@ -658,6 +658,16 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
       // one entry's slab, front to back, onto a pixel's running piece
       auto slab = [&](const float qq, const float ap, const float4 &c, float &c0, float &c1,
                       float &c2, float &tr) {
+        if (!kAbs) {
+          // no absorption (the ordered additive sum): T stays 1
+          if (qq <= qmax) {
+            const float e = __builtin_amdgcn_exp2f(-qq);
+            c0 = fmaf(e, c.y, c0);
+            c1 = fmaf(e, c.z, c1);
+            c2 = fmaf(e, c.w, c2);
+          }
+          return;
+        }
         if (qq <= qmax) {
           const float e = __builtin_amdgcn_exp2f(-qq);
           const float x = ap * e;
@@ -705,7 +715,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
         const int j = (&s_list[0][0])[lp++];
         const float4 p = s_pos[j];
         const float4 c = s_col[j];
-        const float ap = s_ap[j];
+        const float ap = kAbs ? s_ap[j] : 0.f;
         // squared distances in units of sigma^2 / log2 e; two rows down
         // adds 2 g
         const float dx = fmaf(px, p.z, p.x);
@@ -755,16 +765,18 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
       const int gx = x0 + lpx, gy = y0 + lpy;
       if (gx < tk.W && gy < tk.H) {
         float *o = img + 3 * ((size_t)gy * tk.W + gx);
+        // (the additive sum adds into the image: a frame may come in chunks)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) o[c] = C[m][c] + Cc[m][c];
+        for (int c = 0; c < 3; ++c) o[c] = kAbs ? C[m][c] + Cc[m][c] : o[c] + (C[m][c] + Cc[m][c]);
       }
     }
   }
 }
 
 // Ordered merge of the partial tiles of a long sorted list: chunk c sees the
-// light of chunks 0..c-1 through their transmittance.
-template <int T>
+// light of chunks 0..c-1 through their transmittance (all 1 in the ordered
+// additive sum, which adds the result into the image).
+template <int T, bool kAbs>
 __global__ __launch_bounds__(kBlock) void k_composite_merge(const Item *__restrict__ items,
                                                             const uint32_t *__restrict__ counts,
                                                             int chunk, TileK tk,
@@ -788,9 +800,9 @@ __global__ __launch_bounds__(kBlock) void k_composite_merge(const Item *__restri
     const int gx = tx * T + p % T, gy = ty * T + p / T;
     if (gx < tk.W && gy < tk.H) {
       float *o = img + 3 * ((size_t)gy * tk.W + gx);
-      o[0] = c0;
-      o[1] = c1;
-      o[2] = c2;
+      o[0] = kAbs ? c0 : o[0] + c0;
+      o[1] = kAbs ? c1 : o[1] + c1;
+      o[2] = kAbs ? c2 : o[2] + c2;
     }
   }
 }
@@ -866,28 +878,33 @@ hipError_t launch_composite(int tile, const Item *items, int n_items,
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   float4 *pp = reinterpret_cast<float4 *>(partial);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_b, sort_chunk,
+                       r, r2, counts, chunk, tk, img, pp);
+  };
+  // without rec2 (no absorption): the ordered additive sum
   if (tile == 16)
-    hipLaunchKernelGGL(k_composite<16>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_b, sort_chunk, r, r2,
-                       counts, chunk, tk, img, pp);
+    r2 ? go(k_composite<16, true>) : go(k_composite<16, false>);
   else if (tile == 32)
-    hipLaunchKernelGGL(k_composite<32>, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_b, sort_chunk, r, r2,
-                       counts, chunk, tk, img, pp);
+    r2 ? go(k_composite<32, true>) : go(k_composite<32, false>);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_composite_merge(int tile, const Item *items, int n_items,
+hipError_t launch_composite_merge(int tile, bool absorb, const Item *items, int n_items,
                                   const uint32_t *counts, int chunk, const TileK &tk,
                                   const float *partial, float *img, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
   const float4 *pp = reinterpret_cast<const float4 *>(partial);
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(n_items), dim3(kBlock), 0, s, items, counts, chunk, tk, pp,
+                       img);
+  };
   if (tile == 16)
-    hipLaunchKernelGGL(k_composite_merge<16>, dim3(n_items), dim3(kBlock), 0, s, items, counts,
-                       chunk, tk, pp, img);
+    absorb ? go(k_composite_merge<16, true>) : go(k_composite_merge<16, false>);
   else if (tile == 32)
-    hipLaunchKernelGGL(k_composite_merge<32>, dim3(n_items), dim3(kBlock), 0, s, items, counts,
-                       chunk, tk, pp, img);
+    absorb ? go(k_composite_merge<32, true>) : go(k_composite_merge<32, false>);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -248,6 +248,8 @@ spl_status check_params(spl_ctx *c, const spl_params *p, bool need_looks) {
     return fail(c, SPL_EINVAL, "tile must be 0, 16 or 32 (got %d)", p->tile);
   if (p->bin_rule != 0 && p->bin_rule != 1) return fail(c, SPL_EINVAL, "bin_rule must be 0 or 1");
   if (!std::isfinite(p->large_cut)) return fail(c, SPL_EINVAL, "large_cut must be finite");
+  if (p->deterministic != 0 && p->deterministic != 1)
+    return fail(c, SPL_EINVAL, "deterministic must be 0 or 1");
   if (!need_looks) return SPL_OK;
   if (!(p->k_sigma >= 0.0) || !std::isfinite(p->k_sigma))
     return fail(c, SPL_EINVAL, "k_sigma must be finite and >= 0");
@@ -377,21 +379,32 @@ uint64_t pose_digest(const spl_camera *cam) {
 // Tile size and large cut for a view: explicit parameters win, then the
 // autotuner's choice for this pose, then its latest choice for the image
 // size, then the defaults.
+// Lists drawn in list order: depth-sorted, or additive in index order.
+bool ordered(const spl_params *prm) {
+  return prm->mode == SPL_SORTED || prm->deterministic != 0;
+}
+
+// The mode a tuned choice is kept under (the additive modes in index order
+// run other kernels than the unordered ones).
+int tune_mode(const spl_params *prm) {
+  return prm->mode + (prm->mode != SPL_SORTED && prm->deterministic ? 8 : 0);
+}
+
 void choose(spl_ctx *c, int64_t n, const spl_camera *cam, const spl_params *prm, int &tile,
             double &cut) {
   tile = prm->tile;
   cut = prm->large_cut;
   const int W = cam->width, H = cam->height;
   const std::pair<int, double> *t = nullptr;
-  auto it = c->tune.find(std::make_tuple(n, W, H, prm->mode, pose_digest(cam)));
+  auto it = c->tune.find(std::make_tuple(n, W, H, tune_mode(prm), pose_digest(cam)));
   if (it != c->tune.end()) {
     t = &it->second;
   } else {
-    auto ia = c->tune_any.find(std::make_tuple(n, W, H, prm->mode));
+    auto ia = c->tune_any.find(std::make_tuple(n, W, H, tune_mode(prm)));
     if (ia != c->tune_any.end()) t = &ia->second;
   }
   if (tile == 0) tile = t ? t->first : kDefaultTile;
-  if (prm->mode == SPL_SORTED || cut < 0.0)
+  if (ordered(prm) || cut < 0.0)
     cut = INFINITY;
   else if (cut == 0.0)
     cut = t ? t->second : kDefaultCut;
@@ -410,6 +423,7 @@ struct Frame {
   bool flux_check = false;       // expected flux of the records (additive modes)
   bool clear = true;             // zero the image first (else add into it)
   bool finish = true;            // final map, FP64 reductions, normalisation
+  bool ordered = false;          // keyed lists sorted, drawn by the composite walk
 };
 
 // ---- stage timers ---------------------------------------------------------
@@ -479,6 +493,8 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   const TileK &tk = f.tk;
   const int nb = tk.n_tiles + tk.n_ctiles;
   const bool sorted = f.mode == SPL_SORTED;
+  // sorted mode, and the additive modes in list order (keys = index alone)
+  const bool ordered = sorted || f.ordered;
   const int64_t npx = (int64_t)tk.W * tk.H;
   uint32_t *counts = (uint32_t *)c->counts.p, *offsets = (uint32_t *)c->offsets.p,
            *cursor = (uint32_t *)c->cursor.p, *item_off = (uint32_t *)c->item_off.p;
@@ -491,7 +507,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   uint32_t *umask = (uint32_t *)c->umask.p;
   if (!f.counted) HIPTRY(c, launch_count(span, f.rec, f.n, tk, counts, umask, s));
   mark(tf, 2, s);
-  const int chunk[3] = {kChunkSplat, sorted ? kSortChunk : 0, sorted ? kMergeOut : 0};
+  const int chunk[3] = {kChunkSplat, ordered ? kSortChunk : 0, ordered ? kMergeOut : 0};
   const int cchunk[3] = {kChunkLarge, 0, 0};
   const int minc[3] = {1, 1, kSortChunk + 1};
   HIPTRY(c, launch_scan(counts, nb, tk.n_tiles, offsets, cursor, chunk, cchunk, minc, item_off, tot, s));
@@ -506,7 +522,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     if (T.n_items[k] > 0x7fffffffull)
       return fail(c, SPL_EUNSUPPORTED, "too many work items (%llu)", T.n_items[k]);
 
-  if (sorted) {
+  if (ordered) {
     TRY(ensure(c, c->keysA, T.n_pairs * 8));
     TRY(ensure(c, c->keysB, T.n_pairs * 8));
   } else {
@@ -523,11 +539,11 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   unsigned long long *keysB = (unsigned long long *)c->keysB.p;
   mark(tf, 4, s);
   HIPTRY(c, launch_scatter(span, f.rec, f.rec2, f.n, tk, cursor, (uint32_t *)c->pairs.p,
-                           sorted ? keysA : nullptr, umask, s));
+                           ordered ? keysA : nullptr, umask, s));
   mark(tf, 5, s);
   const Item *items0 = (const Item *)c->items[0].p;
   int passes = 0;
-  if (!sorted) {
+  if (!ordered) {
     mark(tf, 6, s);
     if (f.clear) HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
     const int nfi = (int)T.n_fine_items[0];
@@ -547,13 +563,13 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
       ++passes;
     }
     mark(tf, 6, s);
-    HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
+    if (f.clear) HIPTRY(c, launch_fill_f32(f.out, 0.0f, 3 * npx, s));
     mark(tf, 7, s);
     const int ni = (int)T.n_items[0];
     TRY(ensure(c, c->partial, (size_t)ni * tk.tile * tk.tile * 16));
     HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, keysB, (uint32_t)kSortChunk, f.rec, f.rec2, counts, kChunkSplat, tk,
                                f.out, (float *)c->partial.p, s));
-    HIPTRY(c, launch_composite_merge(tk.tile, items0, ni, counts, kChunkSplat, tk,
+    HIPTRY(c, launch_composite_merge(tk.tile, sorted, items0, ni, counts, kChunkSplat, tk,
                                      (const float *)c->partial.p, f.out, s));
     mark(tf, 8, s);
   }
@@ -572,17 +588,18 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     B[1] = f.counted ? 0.0 : n * 8.0 + 4.0 * nb;
     B[2] = 4.0 * nb * 3.0;
     B[3] = 16.0 * (double)(T.n_items[0] + T.n_items[1] + T.n_items[2]);
-    B[4] = n * 8.0 + pairs * (sorted ? 8.0 : 4.0);
+    B[4] = n * 8.0 + pairs * (ordered ? 8.0 : 4.0);
     // chunk sort: every key read and written once; each merge pass: the
     // keys of the merged lists
-    B[5] = sorted ? pairs * 16.0 + (double)T.n_merge_keys * 16.0 : 0.0;
-    if (!sorted) {
+    B[5] = ordered ? pairs * 16.0 + (double)T.n_merge_keys * 16.0 : 0.0;
+    if (!ordered) {
       B[6] = 12.0 * npx + large * 36.0 +
              24.0 * std::min((double)npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);
       B[7] = fine * 36.0 + 24.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
     } else {
       B[6] = 12.0 * npx;
-      B[7] = pairs * 48.0 + 12.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
+      B[7] = pairs * (sorted ? 48.0 : 40.0) +
+             12.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
     }
     B[8] = (f.mode == SPL_ADD_AEQE ? 24.0 : 12.0) * npx + (f.normalise ? 24.0 * npx : 0.0);
     c->pending.push_back(*tf);
@@ -668,6 +685,7 @@ spl_status render_one(spl_ctx *c, const spl_particles *p, const spl_camera *cam,
   f.clear = clear;
   f.finish = finish;
   f.flux_check = prm->flux_check != 0 && !sorted;
+  f.ordered = ordered(prm);
   return render_timed(c, f, tf, st, s);
 }
 
@@ -977,8 +995,9 @@ spl_status render_batch(spl_ctx *c, const spl_particles *p, int nv, const spl_ca
   }
   if (any_sorted) TRY(check_particles(c, p, SPL_SORTED));
   for (int v = 0; v < nv; ++v) {
-    // views that need a depth-sorted composite take the single-view path
-    if (prms[v].mode == SPL_SORTED) {
+    // views drawn in list order (depth-sorted, or additive in index order)
+    // take the single-view path
+    if (ordered(&prms[v])) {
       TRY(render_one(c, p, &cams[v], &prms[v], outs[v], st ? &st[v] : nullptr, s));
       continue;
     }
@@ -1546,7 +1565,8 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
   if (!c) return SPL_EINVAL;
   if (n < 0 || n >= (int64_t)0xffffffffll) return fail(c, SPL_EINVAL, "bad record count");
   if (n > 0 && !rec) return fail(c, SPL_EINVAL, "rec is NULL");
-  if (by_depth && n > 0 && !rec2) return fail(c, SPL_EINVAL, "by_depth needs rec2");
+  if (by_depth < 0 || by_depth > 2) return fail(c, SPL_EINVAL, "by_depth must be 0, 1 or 2");
+  if (by_depth == 1 && n > 0 && !rec2) return fail(c, SPL_EINVAL, "by_depth 1 needs rec2");
   if (width < 1 || height < 1 || width > 32768 || height > 32768 || tile < 1)
     return fail(c, SPL_EINVAL, "bad image or tile size");
   if (!(nu > 0.0)) return fail(c, SPL_EINVAL, "nu must be > 0");
@@ -1598,8 +1618,9 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
                                    item_off + k * (nb + 1), (Item *)c->items[k].p, s));
   }
   unsigned long long *A = (unsigned long long *)c->keysA.p, *B = (unsigned long long *)c->keysB.p;
-  HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, rec2, n, tk, (uint32_t *)c->cursor.p,
-                           nullptr, A, umask, s));
+  // keys: depth bits and index, or the index alone (by_depth = 2)
+  HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, by_depth == 1 ? rec2 : nullptr, n, tk,
+                           (uint32_t *)c->cursor.p, nullptr, A, umask, s));
   HIPTRY(c, launch_sort_chunks(A, (const Item *)c->items[1].p, (int)T.n_items[1], s));
   int passes = 0;
   for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {
@@ -1645,6 +1666,7 @@ spl_status spl_render_records(spl_ctx *c, int64_t n, const float *rec, const flo
   mark(tf, 1, s);
   Frame f{n, rec, prm->mode == SPL_SORTED ? rec2 : nullptr, tk, prm->mode, prm->normalise, out,
           32.0, 0.0, false, nullptr};
+  f.ordered = ordered(prm);
   return render_timed(c, f, tf, st, s);
 }
 
@@ -1863,8 +1885,8 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
   const int tiles[2] = {16, 32};
   const double cuts_add[5] = {16.0, 32.0, 64.0, 128.0, -1.0};
   const double cuts_sorted[1] = {-1.0};
-  const double *cuts = prm->mode == SPL_SORTED ? cuts_sorted : cuts_add;
-  const int ncut = prm->mode == SPL_SORTED ? 1 : 5;
+  const double *cuts = ordered(prm) ? cuts_sorted : cuts_add;
+  const int ncut = ordered(prm) ? 1 : 5;
   float best = INFINITY;
   int best_tile = kDefaultTile;
   double best_cut = kDefaultCut;
@@ -1897,8 +1919,8 @@ spl_status spl_autotune(spl_ctx *c, const spl_particles *p, const spl_camera *ca
   (void)hipFree(img);
   if (rc != SPL_OK) return rc;
   const std::pair<int, double> choice(best_tile, best_cut < 0 ? INFINITY : best_cut);
-  c->tune[std::make_tuple(p->n, cam->width, cam->height, prm->mode, pose_digest(cam))] = choice;
-  c->tune_any[std::make_tuple(p->n, cam->width, cam->height, prm->mode)] = choice;
+  c->tune[std::make_tuple(p->n, cam->width, cam->height, tune_mode(prm), pose_digest(cam))] = choice;
+  c->tune_any[std::make_tuple(p->n, cam->width, cam->height, tune_mode(prm))] = choice;
   *tile_out = best_tile;
   *cut_out = best_cut;
   return SPL_OK;

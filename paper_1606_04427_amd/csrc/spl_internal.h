@@ -262,11 +262,14 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
                               uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s);
 // keys: the buffer the scatter wrote; keys_b: the merge passes' other buffer
 // (each list is read from the one its merge passes end in, sort_chunk = k0).
+// rec2 NULL: no absorption, the ordered additive sum, added into img (the
+// depth-sorted composite, with rec2, writes img).
 hipError_t launch_composite(int tile, const Item *items, int n_items,
                             const unsigned long long *keys, const unsigned long long *keys_b,
                             uint32_t sort_chunk, const float *rec, const float *rec2, const uint32_t *counts, int chunk,
                             const TileK &tk, float *img, float *partial, hipStream_t s);
-hipError_t launch_composite_merge(int tile, const Item *items, int n_items,
+// absorb: as rec2 != NULL in the composite it follows.
+hipError_t launch_composite_merge(int tile, bool absorb, const Item *items, int n_items,
                                   const uint32_t *counts, int chunk, const TileK &tk,
                                   const float *partial, float *img, hipStream_t s);
 

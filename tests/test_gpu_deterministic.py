@@ -1,0 +1,235 @@
+"""The additive modes in list order (spl_params.deterministic = 1).
+
+Sect. 3.1: each tile's pixels are drawn by the worker that owns them, so no
+two workers race on a pixel; with the tile lists in a fixed order (ascending
+particle index, the stable scatter) and each list summed in that order, the
+image is the same bit for bit on every run.  Checked here:
+  * spl_bin's stable lists (by_depth = 2) equal the oracle's lists entry for
+    entry, in order (the oracle appends particles in index order), including
+    the windowed scatter of more bins than one workgroup's LDS holds;
+  * the image against the FP64 oracle (rel-L2 <= 1e-5 and the per-pixel
+    bound), in both additive modes and both tile sizes, with tiles whose
+    lists span many work items (merged in chunk order);
+  * repeated renders, other work between them, a second context, the
+    no-allocation entry point and a view inside a batch all give the same
+    bits; the unordered render agrees to rounding (rel-L2 <= 1e-6);
+  * out-of-core frames in index order: repeatable bit for bit and equal to
+    the resident render to rounding;
+  * the large-particle path stays off, and bad flag values are refused.
+"""
+import numpy as np
+import pytest
+
+from paper_1606_04427_amd import synth
+from tests.helpers import particles, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(oracle):
+    import torch
+
+    from paper_1606_04427_amd import binding as B
+
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    ctx = B.Context(0)
+    yield B, ctx, oracle
+    ctx.close()
+
+
+def _looks(ps, n_species=1, brightness=0.05):
+    looks, pals = [], []
+    for k in range(n_species):
+        s = ps.scalar[ps.species == k] if n_species > 1 else ps.scalar
+        s = s[s > 0]
+        looks.append(dict(log10=1, brightness=brightness * (1 + k), lo=float(np.log10(s.min())),
+                          hi=float(np.log10(s.max()))))
+        pals.append(synth.palette(k))
+    return looks, pals
+
+
+def _check(got, ref, what, tol=1e-5):
+    e = rel_l2(got, ref)
+    assert e <= tol, f"{what}: rel-L2 {e:.3e} > {tol:.1e}"
+    bound = 1e-3 * np.abs(ref) + 1e-5 * np.abs(ref).max()
+    bad = np.abs(got - ref) > bound
+    assert not bad.any(), f"{what}: {int(bad.sum())} pixels outside the max-pixel bound"
+
+
+def _ref(R, ps, pose, mode, looks, pals):
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    return R.render(R.Particles(ps), pose, R.params(mode, L))
+
+
+def _dense_case():
+    """Thousands of particles in a few tiles: lists of several work items."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    n = 30000
+    pts = rng.normal(0.0, 0.004, size=(n, 3))
+    ps = particles(pts, h=rng.uniform(0.001, 0.02, n), intensity=rng.lognormal(0, 0.5, n),
+                   scalar=rng.uniform(0.5, 2.0, n))
+    cam = synth.Pose((0.0, 0.0, 3.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 30.0, 1e-3, 128, 96)
+    return ps, cam
+
+
+def _render(B, ctx, parts, pose, prm):
+    import torch
+
+    img, st = ctx.spl_render(parts, pose, prm)
+    torch.cuda.synchronize()
+    return img.cpu().numpy(), st
+
+
+@pytest.mark.parametrize("tile", [1, 16, 32, 64])
+def test_stable_lists_equal_the_oracle_in_order(env, tile):
+    B, ctx, R = env
+    ps = synth.soneira_peebles(30000, seed=31)
+    pose = synth.random_poses(1, seed=41, width=256, height=256)[0]
+    looks, pals = _looks(ps)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    rec, _ = ctx.spl_project(parts, pose, B.make_params(0, B.Palettes(pals), looks))
+    print(f"stable lists tile={tile}", flush=True)
+    c, o, p = ctx.spl_bin(rec, None, 256, 256, tile, 3.0, 0, 2)
+    c, o, p = (a.cpu().numpy().view(np.uint32) for a in (c, o, p))
+    rc, ro, rp = R.bin_records(rec.cpu().numpy(), None, 256, 256, tile, 3.0, 0, False)
+    assert np.array_equal(c, rc) and np.array_equal(o, ro)
+    assert np.array_equal(p, rp)
+    # strictly ascending inside every tile
+    d = np.diff(p.astype(np.int64))
+    starts = np.zeros(len(p), bool)
+    starts[o[:-1][c > 0]] = True
+    assert np.all(d[~starts[1:]] > 0)
+
+
+def test_stable_lists_in_bin_windows(env):
+    """512 x 384 at 1 px tiles: 196608 bins, the scatter in several windows
+    with the per-unit band masks."""
+    B, ctx, R = env
+    ps = synth.soneira_peebles(30000, seed=33)
+    pose = synth.random_poses(1, seed=43, width=512, height=384)[0]
+    looks, pals = _looks(ps)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    rec, _ = ctx.spl_project(parts, pose, B.make_params(0, B.Palettes(pals), looks))
+    for rule in (0, 1):
+        print(f"stable lists in windows rule={rule}", flush=True)
+        c, o, p = ctx.spl_bin(rec, None, 512, 384, 1, 3.0, rule, 2)
+        c, o, p = (a.cpu().numpy().view(np.uint32) for a in (c, o, p))
+        rc, ro, rp = R.bin_records(rec.cpu().numpy(), None, 512, 384, 1, 3.0, rule, False)
+        assert np.array_equal(c, rc) and np.array_equal(o, ro) and np.array_equal(p, rp)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("tile", [16, 32])
+def test_index_order_matches_oracle_and_repeats(env, mode, tile):
+    B, ctx, R = env
+    ps = synth.soneira_peebles(60000, seed=35)
+    pose = synth.random_poses(3, seed=45, width=256, height=192, dist_range=(0.5, 1.5))[2]
+    looks, pals = _looks(ps)
+    P = B.Palettes(pals)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    det = B.make_params(mode, P, looks, tile=tile, deterministic=1)
+    print(f"index order mode={mode} tile={tile}", flush=True)
+    a, st = _render(B, ctx, parts, pose, det)
+    assert st["large_cut"] == -1.0 and st["n_large"] == 0
+    _check(a.astype(np.float64), _ref(R, ps, pose, mode, looks, pals), f"mode {mode} tile {tile}")
+    # other work in between, then the same bits
+    free, _ = _render(B, ctx, parts, pose, B.make_params(mode, P, looks, tile=tile))
+    assert rel_l2(free.astype(np.float64), a.astype(np.float64)) <= 1e-6
+    b, _ = _render(B, ctx, parts, pose, det)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_long_lists_merge_in_chunk_order(env):
+    B, ctx, R = env
+    ps, cam = _dense_case()
+    looks, pals = _looks(ps, brightness=0.01)
+    P = B.Palettes(pals)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    # some lists span several work items (1024 entries each)
+    rec, _ = ctx.spl_project(parts, cam, B.make_params(0, P, looks))
+    counts, _, _ = ctx.spl_bin(rec, None, cam.width, cam.height, 16, 3.0, 0, 0)
+    assert int(counts.max()) > 4 * 1024
+    for mode in (0, 1):
+        prm = B.make_params(mode, P, looks, tile=16, deterministic=1)
+        print(f"dense index order mode={mode}", flush=True)
+        a, st = _render(B, ctx, parts, cam, prm)
+        _check(a.astype(np.float64), _ref(R, ps, cam, mode, looks, pals), f"dense mode {mode}")
+        for _ in range(2):
+            b, _ = _render(B, ctx, parts, cam, prm)
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_same_bits_across_contexts_noalloc_and_batches(env):
+    import torch
+
+    B, ctx, R = env
+    ps = synth.soneira_peebles(100000, seed=37)
+    poses = synth.random_poses(3, seed=47, width=320, height=240, dist_range=(0.6, 1.4))
+    looks, pals = _looks(ps)
+    P = B.Palettes(pals)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    det = B.make_params(1, P, looks, tile=16, deterministic=1)
+    free = B.make_params(1, P, looks, tile=16)
+    want, _ = _render(B, ctx, parts, poses[1], det)
+    print("second context", flush=True)
+    other = B.Context(0)
+    try:
+        got, _ = _render(B, other, parts, poses[1], det)
+    finally:
+        other.close()
+    assert np.array_equal(want.view(np.uint32), got.view(np.uint32))
+    print("no-allocation entry point", flush=True)
+    img, _ = ctx.spl_render_noalloc(parts, poses[1], det)
+    torch.cuda.synchronize()
+    assert np.array_equal(want.view(np.uint32), img.cpu().numpy().view(np.uint32))
+    print("view inside a batch", flush=True)
+    outs, _ = ctx.spl_render_batch(parts, poses, [free, det, free])
+    torch.cuda.synchronize()
+    assert np.array_equal(want.view(np.uint32), outs[1].cpu().numpy().view(np.uint32))
+
+
+def test_streamed_frames_in_index_order(env):
+    import torch
+
+    B, ctx, R = env
+    ps = synth.soneira_peebles(200000, seed=39)
+    looks, pals = _looks(ps)
+    P = B.Palettes(pals)
+    pose = synth.random_poses(1, seed=49, width=256, height=256, dist_range=(0.6, 1.2))[0]
+    det = B.make_params(1, P, looks, tile=16, deterministic=1)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    res, _ = _render(B, ctx, parts, pose, det)
+    host = B.PinnedParticles(ps)
+    try:
+        imgs = []
+        for _ in range(2):
+            print("streamed frame in index order", flush=True)
+            img, st = ctx.spl_render_stream(host, 45_000, pose, det)  # 5 chunks, ragged
+            torch.cuda.synchronize()
+            imgs.append(img.cpu().numpy())
+        assert st["large_cut"] == -1.0
+    finally:
+        host.close()
+    assert np.array_equal(imgs[0].view(np.uint32), imgs[1].view(np.uint32))
+    assert rel_l2(imgs[0].astype(np.float64), res.astype(np.float64)) <= 1e-6
+    _check(imgs[0].astype(np.float64), _ref(R, ps, pose, 1, looks, pals), "streamed")
+
+
+def test_bad_flag_values_are_refused(env):
+    B, ctx, R = env
+    ps = synth.soneira_peebles(1000, seed=3)
+    looks, pals = _looks(ps)
+    parts = B.DeviceParticles(ps, "cuda:0", "f32")
+    pose = synth.random_poses(1, seed=5, width=64, height=64)[0]
+    prm = B.make_params(0, B.Palettes(pals), looks, deterministic=2)
+    with pytest.raises(B.SplotchError) as e:
+        ctx.spl_render(parts, pose, prm)
+    assert e.value.status == B.SPL_EINVAL
+    rec, _ = ctx.spl_project(parts, pose, B.make_params(0, B.Palettes(pals), looks))
+    with pytest.raises(B.SplotchError) as e:
+        ctx.spl_bin(rec, None, 64, 64, 16, 3.0, 0, 3)
+    assert e.value.status == B.SPL_EINVAL
+    with pytest.raises(B.SplotchError) as e:
+        ctx.spl_bin(rec, None, 64, 64, 16, 3.0, 0, 1)  # depth order needs rec2
+    assert e.value.status == B.SPL_EINVAL
