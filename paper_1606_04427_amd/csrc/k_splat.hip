@@ -4,7 +4,7 @@
 // the tile's pixels live in registers and LDS, so no two workgroups share a
 // pixel except the chunks of one long list, which merge by hardware float
 // atomics (additive) or by an ordered merge of partial (colour,
-// transmittance) tiles (sorted).
+// transmittance) tiles (sorted, and the additive sum in list order).
 //
 // k_splat_add<T>   additive modes, T x T tile, 256 lanes.  Each batch of list
 //                  entries is staged in LDS and appended to the lists of the
@@ -12,15 +12,16 @@
 //                  cut into 32 near-equal ranges for the 8-lane groups (two
 //                  pixels per lane), with running sums in registers flushed into a
 //                  32-bit fixed-point LDS accumulator at micro-tile changes.
-//                  Batch sums fold into per-pixel Neumaier-compensated FP32
-//                  sums.
+//                  Batch sums fold into per-pixel FP64 sums in registers.
 // k_splat_large    the large-particle path: 64 x 64 px tiles, 512 lanes, 8
 //                  pixels per lane, gather only (a large particle covers most
 //                  of the pixels it is tested against).
-// k_composite<T>   sorted mode: staging as above, in-order micro-tile lists
-//                  built by ballots, walked in near-equal ranges by the
-//                  16-lane groups; front-to-back slab compositing of each
-//                  list piece, pieces merged per pixel in list order.
+// k_composite<T,A> sorted mode (A) and the additive sum in list order (not
+//                  A: no absorption): staging as above, in-order micro-tile
+//                  lists built by ballots, walked in near-equal ranges by
+//                  8-lane groups (two pixels per lane); front-to-back slab
+//                  compositing of each list piece, pieces merged per pixel in
+//                  list order.
 #include <type_traits>
 
 #include "spl_internal.h"
