@@ -278,9 +278,12 @@ int64_t spl_noalloc_scratch_bytes(void);
 
 /* Many views of one resident particle set (the paper's scene-file frame
  * sequence, Sect. 2.1).  cams, prms, outs: host arrays of n_views entries
- * (outs[v] device images).  Projection of all views runs in one launch and
- * the splat of all views in one persistent launch over (view, tile-chunk)
- * work items.  st: host array of n_views entries or NULL. */
+ * (outs[v] device images).  The projections, tile counts and scans of all
+ * views are enqueued back to back before one host synchronisation reads all
+ * list sizes; the splat of all views then runs as one persistent launch over
+ * (view, tile-chunk) work items.  Views drawn in list order (SPL_SORTED, or
+ * deterministic additive views) are rendered one after another as by
+ * spl_render.  st: host array of n_views entries or NULL. */
 spl_status spl_render_batch(spl_ctx *ctx, const spl_particles *p, int32_t n_views,
                             const spl_camera *cams, const spl_params *prms,
                             float *const *outs, spl_stats *st, void *stream);

@@ -33,6 +33,7 @@ class Request:
     pose: object          # synth.Pose (camera and image size)
     mode: int             # spl_mode
     look: int = 0         # index into the executor's bank of looks
+    deterministic: bool = False  # additive modes: the bit-identical list order
     arrival: float = math.nan    # server clock, s
     admitted: float = math.nan
     done: float = math.nan
@@ -51,7 +52,8 @@ class Request:
 
 
 def request_cost(n_particles: int, width: int, height: int, sorted_mode: bool,
-                 entries_per_particle: float = 2.0, tile: int = 16) -> tuple[int, int]:
+                 entries_per_particle: float = 2.0, tile: int = 16,
+                 ordered: bool = False) -> tuple[int, int]:
     """Device bytes of one view: (image, workspace).
 
     The image (12 B per pixel) is held from admission until the request
@@ -60,16 +62,19 @@ def request_cost(n_particles: int, width: int, height: int, sorted_mode: bool,
     a 32 B record and an 8 B span per particle, 4 B per tile-list entry
     (about entries_per_particle entries per particle), a 16 B work item per
     1024 entries and per tile, counts, offsets and cursors (16 B per tile) and
-    fixed buffers (4 MiB).  Sorted views add an 8 B depth record per particle,
-    two 8 B sort keys per entry, and the composite's partial tiles (16 B per
-    pixel of each work item's tile)."""
+    fixed buffers (4 MiB).  Views drawn in list order (sorted, or additive
+    with ordered = True) add two 8 B sort keys per entry and the composite's
+    partial tiles (16 B per pixel of each work item's tile); sorted views also
+    an 8 B depth record per particle."""
     img = 12 * width * height
     tiles = -(-width // tile) * -(-height // tile)
     entries = int(entries_per_particle * n_particles)
     items = entries // 1024 + tiles
     ws = n_particles * (32 + 8) + 4 * entries + 16 * items + 16 * tiles + 4 * MiB
+    if sorted_mode or ordered:
+        ws += 16 * entries + items * tile * tile * 16
     if sorted_mode:
-        ws += n_particles * 8 + 16 * entries + items * tile * tile * 16
+        ws += n_particles * 8
     return img, ws
 
 
@@ -364,11 +369,12 @@ class GpuExecutor:
         if ds.n > batch_particles:
             self.run_each = self._run_each
 
-    def params(self, mode, look):
-        key = (mode, look)
+    def params(self, mode, look, deterministic=False):
+        key = (mode, look, bool(deterministic))
         if key not in self._params:
             pals, looks = self.bank[look]
-            self._params[key] = self.B.make_params(mode, pals, looks)
+            self._params[key] = self.B.make_params(mode, pals, looks,
+                                                   deterministic=int(bool(deterministic)))
         return self._params[key]
 
     def run(self, reqs):
@@ -377,11 +383,11 @@ class GpuExecutor:
         with torch.cuda.stream(self.stream):
             if len(reqs) == 1:
                 r = reqs[0]
-                out, st = self.ctx.spl_render_dataset(self.ds, r.pose, self.params(r.mode, r.look))
+                out, st = self.ctx.spl_render_dataset(self.ds, r.pose, self._prm(r))
                 outs, sts = [out], [st]
             else:
                 outs, sts = self.ctx.spl_render_batch_dataset(
-                    self.ds, [r.pose for r in reqs], [self.params(r.mode, r.look) for r in reqs])
+                    self.ds, [r.pose for r in reqs], [self._prm(r) for r in reqs])
         self.stream.synchronize()
         return outs, sts
 
@@ -390,10 +396,12 @@ class GpuExecutor:
 
         for r in reqs:
             with torch.cuda.stream(self.stream):
-                out, st = self.ctx.spl_render_dataset(self.ds, r.pose,
-                                                      self.params(r.mode, r.look))
+                out, st = self.ctx.spl_render_dataset(self.ds, r.pose, self._prm(r))
             self.stream.synchronize()
             done(r, out, st)
+
+    def _prm(self, r):
+        return self.params(r.mode, r.look, r.deterministic)
 
     def workspace_bytes(self) -> int:
         return self.ctx.workspace_bytes()

@@ -1,6 +1,8 @@
 """Request loop on the GPU: every result rendered in the mix (continuous
 batching, two workers on two streams, Poisson arrivals, mixed image sizes and
-modes) equals the same request rendered alone with one call."""
+modes) equals the same request rendered alone with one call: bit for bit for
+depth-sorted requests and additive requests in the deterministic list order,
+to rounding for the other additive requests."""
 import numpy as np
 import pytest
 
@@ -31,7 +33,9 @@ def _requests(n, seed):
         w, h = sizes[rng.integers(len(sizes))]
         pose = synth.random_poses(1, seed=seed * 100 + k, width=w, height=h)[0]
         mode = 2 if rng.uniform() < 0.2 else 1
-        out.append(serve.Request(k, pose, mode, look=int(rng.integers(3))))
+        look = int(rng.integers(3))
+        det = mode == 1 and rng.uniform() < 0.4
+        out.append(serve.Request(k, pose, mode, look=look, deterministic=det))
     return out
 
 
@@ -46,7 +50,8 @@ def test_results_alone_equal_results_in_the_mix():
     mix = _requests(48, seed=7)
     tagged = set(range(0, 48, 3))  # 16 tagged requests
     keep = lambda r: r.rid in tagged
-    cost = lambda r: serve.request_cost(parts.n, r.pose.width, r.pose.height, r.mode == 2)
+    cost = lambda r: serve.request_cost(parts.n, r.pose.width, r.pose.height, r.mode == 2,
+                                        ordered=r.deterministic)
     srv = serve.Server(lambda w: serve.GpuExecutor(parts, bank), n_workers=2,
                        budget_bytes=6 * sum(cost(mix[0])), max_views=8, cost=cost,
                        keep=keep).start()
@@ -56,7 +61,10 @@ def test_results_alone_equal_results_in_the_mix():
     assert all(r.error is None for r in mix), [r.error for r in mix if r.error]
     assert srv.n_batches < len(mix)  # some requests shared a batch
     assert srv.peak_reserved <= srv.budget
-    alone = [serve.Request(r.rid, r.pose, r.mode, r.look) for r in mix if r.rid in tagged]
+    alone = [serve.Request(r.rid, r.pose, r.mode, r.look, r.deterministic) for r in mix
+             if r.rid in tagged]
+    assert any(a.deterministic for a in alone) and any(a.mode == 1 and not a.deterministic
+                                                       for a in alone)
     ex = serve.GpuExecutor(parts, bank)
     serve.one_per_call(ex, alone)
     ex.close()
@@ -65,8 +73,8 @@ def test_results_alone_equal_results_in_the_mix():
     for a in alone:
         m = by_id[a.rid]
         x, y = m.image.cpu().numpy(), a.image.cpu().numpy()
-        if a.mode == 2:
-            assert np.array_equal(x, y), a.rid
+        if a.mode == 2 or a.deterministic:
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), a.rid
         else:
             assert rel_l2(x, y) < 1e-6, a.rid
         assert m.stats["n_active"] == a.stats["n_active"]

@@ -151,7 +151,7 @@ def test_one_per_call_baseline_and_summary():
 def test_request_cost_model():
     """Image and workspace terms of one view: records, spans and list entries
     grow with the particle count, the composite's partial tiles with the
-    list entries (sorted mode)."""
+    list entries (sorted mode and the deterministic additive order)."""
     n, w, h = 100_000, 64, 32
     img, ws = serve.request_cost(n, w, h, False)
     entries = 2 * n
@@ -161,6 +161,10 @@ def test_request_cost_model():
     img2, ws2 = serve.request_cost(n, w, h, True)
     assert img2 == img
     assert ws2 - ws == n * 8 + 16 * entries + items * 16 * 16 * 16
+    # additive in the deterministic list order: the keys and partial tiles of
+    # the ordered walk, no depth record
+    img3, ws3 = serve.request_cost(n, w, h, False, ordered=True)
+    assert img3 == img and ws3 - ws == 16 * entries + items * 16 * 16 * 16
     # more entries per particle, more workspace
     assert serve.request_cost(n, w, h, False, entries_per_particle=4.0)[1] > ws
     assert serve.request_bytes(n, w, h, False) == img + ws
