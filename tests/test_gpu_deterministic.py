@@ -233,3 +233,48 @@ def test_bad_flag_values_are_refused(env):
     with pytest.raises(B.SplotchError) as e:
         ctx.spl_bin(rec, None, 64, 64, 16, 3.0, 0, 1)  # depth order needs rec2
     assert e.value.status == B.SPL_EINVAL
+
+
+def test_edge_cases_in_index_order(env):
+    """Empty and fully clipped sets, ragged and one-pixel images, one particle
+    larger than the image, normalisation, another truncation radius and the
+    expected-flux check, each against the oracle (or all zero)."""
+    import torch
+
+    B, ctx, R = env
+    look0 = [dict(log10=0, brightness=1.0, lo=0.0, hi=1.0)]
+    pal0 = [synth.palette(0)]
+    cam = synth.blobs_camera(96, 64)
+    empty = particles(np.zeros((0, 3)), h=np.zeros(0))
+    behind = particles([[0.5, 0.5, 5.0], [0.5, 0.5, 3.0]], h=0.1)
+    for ps in (empty, behind):
+        for mode in (0, 1):
+            parts = B.DeviceParticles(ps, "cuda:0", "f32")
+            prm = B.make_params(mode, B.Palettes(pal0), look0, deterministic=1)
+            img, st = _render(B, ctx, parts, cam, prm)
+            assert not img.any() and st["n_active"] == 0
+    big = particles([[0.5, 0.5, 0.5]], h=0.6, intensity=1.0, scalar=0.5)
+    blobs = synth.blobs(6000, seed=27)
+    looks, pals = _looks(blobs)
+    cases = [(big, synth.blobs_camera(192, 160), look0, pal0, {}),
+             (blobs, synth.blobs_camera(100, 70), looks, pals, {}),
+             (blobs, synth.blobs_camera(1, 1), looks, pals, {}),
+             (blobs, synth.blobs_camera(33, 257), looks, pals, dict(tile=32)),
+             (blobs, synth.blobs_camera(128, 128), looks, pals, dict(normalise=1)),
+             (blobs, synth.blobs_camera(128, 128), looks, pals, dict(nu=4.5, sigma_min=0.7,
+                                                                     k_sigma=0.5))]
+    for k, (ps, cam, lk, pl, kw) in enumerate(cases):
+        print(f"edge case {k} in index order", flush=True)
+        parts = B.DeviceParticles(ps, "cuda:0", "f32")
+        prm = B.make_params(1, B.Palettes(pl), lk, deterministic=1, flux_check=1, **kw)
+        img, st = _render(B, ctx, parts, cam, prm)
+        L = R.Looks([dict(rgb=p, **l) for p, l in zip(pl, lk)])
+        rk = {q: v for q, v in kw.items() if q in ("k_sigma", "sigma_min", "nu", "normalise")}
+        ref = R.render(R.Particles(ps), cam, R.params(1, L, **rk))
+        if np.abs(ref).max() == 0:
+            assert not img.any()
+        else:
+            _check(img.astype(np.float64), ref, f"edge case {k}")
+        # the flux check: the raw flux of J against the expected flux
+        np.testing.assert_allclose(st["raw_flux"], st["expected_flux"], rtol=1e-5, atol=1e-30)
+    torch.cuda.synchronize()
