@@ -305,6 +305,11 @@ struct ScanArgs {
   int shift[3], cshift[3], minc[3];
 };
 
+// Bins and fine bins of each view of one scan launch.
+struct ScanViews {
+  int nb[kMaxLaunchViews], n_fine[kMaxLaunchViews];
+};
+
 // One workgroup: each thread sums a run of consecutive bins (entries and the
 // item counts of the three chunkings), the runs are scanned with wave
 // shuffles and one pass over the wave totals, and each thread writes its
@@ -317,14 +322,23 @@ struct ScanArgs {
 // do not fall on one bank.
 __device__ __forceinline__ int scan_pad(int b) { return b + (b >> 5); }
 
+// One workgroup per view v = blockIdx.x: the view's arrays start v vstride
+// words (item offsets 3 v vstride) after the given ones, its totals at tot + v.
 template <bool kLds>
-__global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restrict__ counts,
-                                                       int nb, int n_fine,
-                                                       uint32_t *__restrict__ offsets,
-                                                       uint32_t *__restrict__ cursor, ScanArgs a,
-                                                       uint32_t *__restrict__ item_off,
-                                                       Totals *__restrict__ tot) {
+__global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restrict__ counts0,
+                                                       uint32_t *__restrict__ offsets0,
+                                                       uint32_t *__restrict__ cursor0, ScanArgs a,
+                                                       uint32_t *__restrict__ item_off0,
+                                                       Totals *__restrict__ tot0, size_t vstride,
+                                                       ScanViews sv) {
   constexpr int NW = kScanThreads / 64;
+  const int v = blockIdx.x;
+  const int nb = sv.nb[v], n_fine = sv.n_fine[v];
+  const uint32_t *__restrict__ counts = counts0 + v * vstride;
+  uint32_t *__restrict__ offsets = offsets0 + v * vstride;
+  uint32_t *__restrict__ cursor = cursor0 + v * vstride;
+  uint32_t *__restrict__ item_off = item_off0 + 3 * v * vstride;
+  Totals *__restrict__ tot = tot0 ? tot0 + v : nullptr;
   extern __shared__ uint32_t s_cnt[];
   __shared__ unsigned long long s_w[4][NW];
   __shared__ unsigned int s_max, s_nef, s_nec;
@@ -467,15 +481,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t *__restric
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ counts,
-                                                  const uint32_t *__restrict__ offsets, int nb,
-                                                  int n_fine, int chunk, int cchunk, int minc,
-                                                  const uint32_t *__restrict__ item_off,
-                                                  Item *__restrict__ items,
-                                                  Item *__restrict__ coarse,
-                                                  uint32_t coarse_shift, uint32_t view) {
+// View v = blockIdx.y: arrays v vstride words after the given ones (item
+// offsets 3 v vstride, then the list `list` of that view's three), items at
+// items0 + iv.fine[v], coarse items at coarse0 + iv.coarse[v].
+__global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ counts0,
+                                                  const uint32_t *__restrict__ offsets0,
+                                                  int chunk, int cchunk, int minc,
+                                                  const uint32_t *__restrict__ item_off0, int list,
+                                                  Item *__restrict__ items0,
+                                                  Item *__restrict__ coarse0, size_t vstride,
+                                                  ItemViews iv) {
+  const int v = blockIdx.y;
+  const int nb = iv.nb[v], n_fine = iv.n_fine[v];
   const int b = blockIdx.x * kBlock + threadIdx.x;
   if (b >= nb) return;
+  const uint32_t *__restrict__ counts = counts0 + v * vstride;
+  const uint32_t *__restrict__ offsets = offsets0 + v * vstride;
+  const uint32_t *__restrict__ item_off = item_off0 + 3 * v * vstride + list * (nb + 1);
+  Item *__restrict__ items = items0 + iv.fine[v];
+  Item *__restrict__ coarse = coarse0 + iv.coarse[v];
+  const uint32_t coarse_shift = iv.coarse_shift[v], view = iv.view[v];
   const uint32_t c = counts[b];
   const uint32_t k = items_for(c, b, n_fine, chunk > 0 ? __builtin_ctz((uint32_t)chunk) : -1,
                                cchunk > 0 ? __builtin_ctz((uint32_t)cchunk) : -1, minc);
@@ -572,9 +597,11 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
   return hipSuccess;
 }
 
-hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t *offsets,
-                       uint32_t *cursor, const int chunk[3], const int cchunk[3],
-                       const int min_count[3], uint32_t *item_off, Totals *tot, hipStream_t s) {
+hipError_t launch_scan_views(const uint32_t *counts, int n_views, const int *n_bins,
+                             const int *n_fine, size_t vstride, uint32_t *offsets,
+                             uint32_t *cursor, const int chunk[3], const int cchunk[3],
+                             const int min_count[3], uint32_t *item_off, Totals *tot,
+                             hipStream_t s) {
   ScanArgs a;
   auto shift_of = [](int ch) {
     if (ch <= 0) return -1;
@@ -597,13 +624,50 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
     lds_max = 0;
     (void)hipGetLastError();
   }
-  const int64_t lds = 2 * ((int64_t)n_bins + n_bins / 32 + 1) * (int64_t)sizeof(uint32_t);
-  if (lds + 1024 <= (int64_t)lds_max)
-    hipLaunchKernelGGL(k_scan<true>, dim3(1), dim3(kScanThreads), (size_t)lds, s, counts, n_bins,
-                       n_fine, offsets, cursor, a, item_off, tot);
-  else
-    hipLaunchKernelGGL(k_scan<false>, dim3(1), dim3(kScanThreads), 0, s, counts, n_bins, n_fine,
-                       offsets, cursor, a, item_off, tot);
+  // views in launches of up to kMaxLaunchViews workgroups
+  for (int v0 = 0; v0 < n_views; v0 += kMaxLaunchViews) {
+    const int nv = std::min(kMaxLaunchViews, n_views - v0);
+    ScanViews sv;
+    int max_bins = 0;
+    for (int v = 0; v < nv; ++v) {
+      sv.nb[v] = n_bins[v0 + v];
+      sv.n_fine[v] = n_fine[v0 + v];
+      max_bins = std::max(max_bins, sv.nb[v]);
+    }
+    const size_t o = (size_t)v0 * vstride;
+    Totals *t = tot ? tot + v0 : nullptr;
+    const int64_t lds = 2 * ((int64_t)max_bins + max_bins / 32 + 1) * (int64_t)sizeof(uint32_t);
+    if (lds + 1024 <= (int64_t)lds_max)
+      hipLaunchKernelGGL(k_scan<true>, dim3(nv), dim3(kScanThreads), (size_t)lds, s, counts + o,
+                         offsets + o, cursor + o, a, item_off + 3 * o, t, vstride, sv);
+    else
+      hipLaunchKernelGGL(k_scan<false>, dim3(nv), dim3(kScanThreads), 0, s, counts + o,
+                         offsets + o, cursor + o, a, item_off + 3 * o, t, vstride, sv);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t *offsets,
+                       uint32_t *cursor, const int chunk[3], const int cchunk[3],
+                       const int min_count[3], uint32_t *item_off, Totals *tot, hipStream_t s) {
+  return launch_scan_views(counts, 1, &n_bins, &n_fine, 0, offsets, cursor, chunk, cchunk,
+                           min_count, item_off, tot, s);
+}
+
+hipError_t launch_build_items_views(const uint32_t *counts, const uint32_t *offsets,
+                                    size_t vstride, int chunk, int cchunk, int min_count,
+                                    const uint32_t *item_off, int list, Item *items, Item *coarse,
+                                    const ItemViews &iv, int n_views, hipStream_t s) {
+  if (n_views < 1 || n_views > kMaxLaunchViews) return hipErrorInvalidValue;
+  int max_bins = 0;
+  for (int v = 0; v < n_views; ++v) max_bins = std::max(max_bins, iv.nb[v]);
+  if (max_bins == 0) return hipSuccess;
+  const int g = (max_bins + kBlock - 1) / kBlock;
+  if (!coarse) coarse = items;
+  hipLaunchKernelGGL(k_items, dim3(g, n_views), dim3(kBlock), 0, s, counts, offsets, chunk,
+                     cchunk, min_count, item_off, list, items, coarse, vstride, iv);
   return hipGetLastError();
 }
 
@@ -611,11 +675,15 @@ hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, i
                               int n_fine, int chunk, int cchunk, int min_count,
                               const uint32_t *item_off, Item *items, hipStream_t s, Item *coarse,
                               uint32_t coarse_shift, uint32_t view) {
-  const int g = (n_bins + kBlock - 1) / kBlock;
-  if (!coarse) coarse = items;
-  hipLaunchKernelGGL(k_items, dim3(g), dim3(kBlock), 0, s, counts, offsets, n_bins, n_fine, chunk,
-                     cchunk, min_count, item_off, items, coarse, coarse_shift, view);
-  return hipGetLastError();
+  ItemViews iv;
+  iv.nb[0] = n_bins;
+  iv.n_fine[0] = n_fine;
+  iv.fine[0] = 0;
+  iv.coarse[0] = 0;
+  iv.coarse_shift[0] = coarse_shift;
+  iv.view[0] = view;
+  return launch_build_items_views(counts, offsets, 0, chunk, cchunk, min_count, item_off, 0,
+                                  items, coarse, iv, 1, s);
 }
 
 hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,

@@ -6,6 +6,8 @@
 // absorption-equals-emission mode maps it to 1 - exp(-J).  Reductions are
 // deterministic: fixed grid, per-block FP64 partials, one final block that
 // sums the partials in block order.
+#include <algorithm>
+
 #include "spl_internal.h"
 
 namespace spl {
@@ -37,15 +39,32 @@ __global__ __launch_bounds__(kBlock) void k_fill_f32(float *p, float v, int64_t 
     p[i] = v;
 }
 
+// Clears the images of several views (view blockIdx.y).
+__global__ __launch_bounds__(kBlock) void k_clear_views(ImgViews iv) {
+  float *const p = iv.img[blockIdx.y];
+  const int64_t n = 3 * iv.n_px[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    p[i] = 0.0f;
+}
+
 // Per block: FP64 sums of the final image (3), maxima (3) and sums of the
-// values before the map (3: the additive J), in that order.
-__global__ __launch_bounds__(kBlock) void k_finalise(float *__restrict__ img, int64_t n_px,
-                                                     int aeqe, double *__restrict__ partials) {
+// values before the map (3: the additive J), in that order.  View
+// v = blockIdx.y takes iv.blocks[v] blocks (the rest of its row of the grid
+// exits), its partials at partials0 + v pstride.
+__global__ __launch_bounds__(kBlock) void k_finalise(ImgViews iv, double *__restrict__ partials0,
+                                                     size_t pstride) {
   __shared__ double s_red[kStatPartials][kBlock];
+  const int v = blockIdx.y, nblk = iv.blocks[v];
+  if ((int)blockIdx.x >= nblk) return;  // uniform
+  float *__restrict__ img = iv.img[v];
+  const int64_t n_px = iv.n_px[v];
+  const int aeqe = iv.aeqe[v];
+  double *__restrict__ partials = partials0 + v * pstride;
   double sm[3] = {0.0, 0.0, 0.0}, raw[3] = {0.0, 0.0, 0.0};
   double mx[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
   for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n_px;
-       p += (int64_t)gridDim.x * kBlock) {
+       p += (int64_t)nblk * kBlock) {
     float *o = img + 3 * p;
     float v[3] = {o[0], o[1], o[2]};
 #pragma unroll
@@ -86,10 +105,17 @@ __global__ __launch_bounds__(kBlock) void k_finalise(float *__restrict__ img, in
 }
 
 // stats[0..2] = flux, [3..5] = max per channel, [6] = max over channels,
-// [7..9] = flux before the map; block partials summed in block order.
-__global__ __launch_bounds__(kBlock) void k_reduce_stats(const double *__restrict__ partials,
-                                                         int n_blocks, double *__restrict__ stats) {
+// [7..9] = flux before the map; block partials summed in block order.  One
+// workgroup per view v = blockIdx.x (partials at partials0 + v pstride,
+// iv.blocks[v] of them; stats at stats0 + v sstride).
+__global__ __launch_bounds__(kBlock) void k_reduce_stats(const double *__restrict__ partials0,
+                                                         size_t pstride, ImgViews iv,
+                                                         double *__restrict__ stats0,
+                                                         size_t sstride) {
   __shared__ double s_red[kStatPartials][kBlock];
+  const double *__restrict__ partials = partials0 + blockIdx.x * pstride;
+  const int n_blocks = iv.blocks[blockIdx.x];
+  double *__restrict__ stats = stats0 + blockIdx.x * sstride;
   double sm[3] = {0.0, 0.0, 0.0}, raw[3] = {0.0, 0.0, 0.0};
   double mx[3] = {-__builtin_inf(), -__builtin_inf(), -__builtin_inf()};
   for (int b = threadIdx.x; b < n_blocks; b += kBlock) {
@@ -222,16 +248,47 @@ hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_clear_views(const ImgViews &iv, int n_views, hipStream_t s) {
+  if (n_views < 1 || n_views > kMaxLaunchViews) return hipErrorInvalidValue;
+  int64_t mx = 0;
+  for (int v = 0; v < n_views; ++v) mx = std::max(mx, 3 * iv.n_px[v]);
+  hipLaunchKernelGGL(k_clear_views, dim3(blocks_for(mx / 4 + 1, 4096), n_views), dim3(kBlock), 0,
+                     s, iv);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalise_views(const ImgViews &iv, int n_views, double *partials,
+                                 size_t pstride, hipStream_t s) {
+  if (n_views < 1 || n_views > kMaxLaunchViews) return hipErrorInvalidValue;
+  int mx = 1;
+  for (int v = 0; v < n_views; ++v) mx = std::max(mx, iv.blocks[v]);
+  hipLaunchKernelGGL(k_finalise, dim3(mx, n_views), dim3(kBlock), 0, s, iv, partials, pstride);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats_views(const double *partials, size_t pstride, const ImgViews &iv,
+                                     int n_views, double *stats, size_t sstride, hipStream_t s) {
+  if (n_views < 1 || n_views > kMaxLaunchViews) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_stats, dim3(n_views), dim3(kBlock), 0, s, partials, pstride, iv,
+                     stats, sstride);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalise(float *img, int64_t n_px, int aeqe, double *partials, int n_blocks,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_finalise, dim3(n_blocks), dim3(kBlock), 0, s, img, n_px, aeqe, partials);
-  return hipGetLastError();
+  ImgViews iv;
+  iv.img[0] = img;
+  iv.n_px[0] = n_px;
+  iv.blocks[0] = n_blocks;
+  iv.aeqe[0] = aeqe;
+  return launch_finalise_views(iv, 1, partials, 0, s);
 }
 
 hipError_t launch_reduce_stats(const double *partials, int n_blocks, double *stats,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(kBlock), 0, s, partials, n_blocks, stats);
-  return hipGetLastError();
+  ImgViews iv;
+  iv.blocks[0] = n_blocks;
+  return launch_reduce_stats_views(partials, 0, iv, 1, stats, 0, s);
 }
 
 hipError_t launch_expected_flux(const float *rec, const uint2 *span, int64_t n, int W, int H,

@@ -755,19 +755,22 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   TimedFrame tfr;
   TimedFrame *tf = (c->timing && !c->graphs && begin_timed(c, tfr)) ? &tfr : nullptr;
   mark(tf, 0, s);
+  // the totals and counts of all views cleared at once, every view
+  // projected (and counted), then all views' scans in one launch
   HIPTRY(c, launch_fill_u32((uint32_t *)tot, 0u, (int64_t)nv * sizeof(Totals) / 4, s));
+  HIPTRY(c, launch_fill_u32(counts, 0u, (int64_t)nv * bstride, s));
+  std::vector<int> nbv(nv), nfv(nv);
   for (int v = 0; v < nv; ++v) {
-    const int nb = tk[v].n_tiles + tk[v].n_ctiles;
+    nbv[v] = tk[v].n_tiles + tk[v].n_ctiles;
+    nfv[v] = tk[v].n_tiles;
     float *rv = rec + (size_t)v * n * 8;
     uint2 *sv = span + (size_t)v * n;
-    HIPTRY(c, launch_fill_u32(counts + v * bstride, 0u, nb, s));
     HIPTRY(c, launch_project(pk[v], tk[v], rv, nullptr, sv, 0, tot + v, s, counts + v * bstride));
     if (!project_counts(tk[v]))
       HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, umask + v * mstride, s));
-    HIPTRY(c, launch_scan(counts + v * bstride, nb, tk[v].n_tiles, offsets + v * bstride,
-                          cursor + v * bstride, chunk, cchunk, minc, itemoff + v * 3 * bstride,
-                          tot + v, s));
   }
+  HIPTRY(c, launch_scan_views(counts, nv, nbv.data(), nfv.data(), bstride, offsets, cursor, chunk,
+                              cchunk, minc, itemoff, tot, s));
   mark(tf, 1, s);
   mark(tf, 2, s);
   mark(tf, 3, s);
@@ -846,19 +849,35 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
     mark(tf, 4, q);
     for (int g = 0; g < ng; ++g) {
       const int v0 = g0s[g], v1 = g0s[g + 1];
-      for (int v = v0; v < v1; ++v) {
-        const Totals &T = c->h_btot[v];
-        const int nb = tk[v].n_tiles + tk[v].n_ctiles;
-        if (T.n_items[ks])
-          HIPTRY(c, launch_build_items(counts + v * bstride, offsets + v * bstride, nb,
-                                       tk[v].n_tiles, ichunk, kChunkLarge, 1,
-                                       itemoff + v * 3 * bstride + ks * (nb + 1), itf + fb[v], q,
-                                       itc + cb[v], (uint32_t)T.n_fine_items[ks],
-                                       (uint32_t)(v - v0)));
+      // the work items of the group's views, one launch per kMaxLaunchViews
+      // views (views without items write none)
+      for (int a = v0; a < v1; a += kMaxLaunchViews) {
+        const int b = std::min(v1, a + kMaxLaunchViews);
+        ItemViews iv;
+        for (int v = a; v < b; ++v) {
+          iv.nb[v - a] = nbv[v];
+          iv.n_fine[v - a] = nfv[v];
+          iv.fine[v - a] = (uint32_t)fb[v];
+          iv.coarse[v - a] = (uint32_t)cb[v];
+          iv.coarse_shift[v - a] = (uint32_t)c->h_btot[v].n_fine_items[ks];
+          iv.view[v - a] = (uint32_t)(v - v0);
+        }
+        HIPTRY(c, launch_build_items_views(counts + a * bstride, offsets + a * bstride, bstride,
+                                           ichunk, kChunkLarge, 1, itemoff + 3 * a * bstride, ks,
+                                           itf, itc, iv, b - a, q));
+      }
+      for (int v = v0; v < v1; ++v)
         HIPTRY(c, launch_scatter(span + (size_t)v * n, rec + (size_t)v * n * 8, nullptr, n,
                                  tk[v], cursor + v * bstride, pairs + pb[v], nullptr,
                                  umask + v * mstride, q));
-        HIPTRY(c, launch_fill_f32(outs[v], 0.0f, 3 * (int64_t)tk[v].W * tk[v].H, q));
+      for (int a = v0; a < v1; a += kMaxLaunchViews) {
+        const int b = std::min(v1, a + kMaxLaunchViews);
+        ImgViews iv;
+        for (int v = a; v < b; ++v) {
+          iv.img[v - a] = outs[v];
+          iv.n_px[v - a] = (int64_t)tk[v].W * tk[v].H;
+        }
+        HIPTRY(c, launch_clear_views(iv, b - a, q));
       }
       ViewK *dviews = (ViewK *)c->b_views.p + v0;
       uint32_t *ctr = (uint32_t *)c->b_ctr.p + 4 * g;
@@ -874,13 +893,25 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
                                    ichunk, kChunkLarge, c->n_cu, q));
       mark(tf, 8, q);
       double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
+      // the final map and FP64 reductions of the group's views, one launch
+      // each per kMaxLaunchViews views
+      const size_t pstride = (size_t)kFinBlocks * kStatPartials;
+      for (int a = v0; a < v1; a += kMaxLaunchViews) {
+        const int b = std::min(v1, a + kMaxLaunchViews);
+        ImgViews iv;
+        for (int v = a; v < b; ++v) {
+          const int64_t npx = (int64_t)tk[v].W * tk[v].H;
+          iv.img[v - a] = outs[v];
+          iv.n_px[v - a] = npx;
+          iv.blocks[v - a] = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
+          iv.aeqe[v - a] = prm[v]->mode == SPL_ADD_AEQE;
+        }
+        HIPTRY(c, launch_finalise_views(iv, b - a, fin + a * pstride, pstride, q));
+        HIPTRY(c, launch_reduce_stats_views(fin + a * pstride, pstride, iv, b - a,
+                                            stats + (size_t)kStatWords * a, kStatWords, q));
+      }
       for (int v = v0; v < v1; ++v) {
         const int64_t npx = (int64_t)tk[v].W * tk[v].H;
-        const int fbk = (int)std::min<int64_t>(kFinBlocks, (npx + kBlock - 1) / kBlock);
-        HIPTRY(c, launch_finalise(outs[v], npx, prm[v]->mode == SPL_ADD_AEQE,
-                                  fin + (size_t)v * kFinBlocks * kStatPartials, fbk, q));
-        HIPTRY(c, launch_reduce_stats(fin + (size_t)v * kFinBlocks * kStatPartials, fbk,
-                                      stats + kStatWords * v, q));
         if (prm[v]->normalise)
           HIPTRY(c, launch_normalise(outs[v], npx, stats + kStatWords * v, q));
         if (prm[v]->flux_check)

@@ -190,11 +190,28 @@ __host__ __device__ __forceinline__ int merge_passes(uint32_t c, uint32_t k0) {
 // ---------------------------------------------------------------------------
 // Launch wrappers (each returns hipSuccess or the launch error).
 // ---------------------------------------------------------------------------
+// Launches that serve several views of a batch at once (one launch instead of
+// one per view: the per-view kernels are small and launch-bound) take up to
+// kMaxLaunchViews views, their parameters by value.
+constexpr int kMaxLaunchViews = 64;
+struct ImgViews {
+  float *img[kMaxLaunchViews];
+  int64_t n_px[kMaxLaunchViews];
+  int blocks[kMaxLaunchViews];  // finalisation blocks of the view
+  int aeqe[kMaxLaunchViews];
+};
+struct ItemViews {
+  int nb[kMaxLaunchViews], n_fine[kMaxLaunchViews];
+  uint32_t fine[kMaxLaunchViews], coarse[kMaxLaunchViews];  // item array offsets
+  uint32_t coarse_shift[kMaxLaunchViews], view[kMaxLaunchViews];
+};
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // Copies bytes (a multiple of 4) from device memory into page-locked host
 // memory through its device-side address, with a kernel.
 hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+// Zeroes the images iv.img[v] (3 n_px[v] floats) of n_views views.
+hipError_t launch_clear_views(const ImgViews &iv, int n_views, hipStream_t s);
 
 // With counts != NULL and project_counts(tk), the projection also adds the
 // tile counts of the binning stage into counts (zeroed by the caller).
@@ -222,6 +239,14 @@ hipError_t launch_scan(const uint32_t *counts, int n_bins, int n_fine, uint32_t 
                        uint32_t *cursor, const int chunk[3], const int cchunk[3],
                        const int min_count[3], uint32_t *item_off /* 3 x (n_bins+1) */,
                        Totals *tot, hipStream_t s);
+// The same for n_views views (host arrays n_bins, n_fine), one workgroup each:
+// view v's counts, offsets and cursor start v vstride words after the given
+// ones, its item offsets 3 v vstride words after, its totals at tot + v.
+hipError_t launch_scan_views(const uint32_t *counts, int n_views, const int *n_bins,
+                             const int *n_fine, size_t vstride, uint32_t *offsets,
+                             uint32_t *cursor, const int chunk[3], const int cchunk[3],
+                             const int min_count[3], uint32_t *item_off, Totals *tot,
+                             hipStream_t s);
 // Items of fine bins go to items[item_off[b]], items of large bins to
 // coarse[item_off[b] - coarse_shift]; the view index is stored in the top 8
 // bits of the bin field.
@@ -230,6 +255,14 @@ hipError_t launch_build_items(const uint32_t *counts, const uint32_t *offsets, i
                               const uint32_t *item_off, Item *items, hipStream_t s,
                               Item *coarse = nullptr, uint32_t coarse_shift = 0,
                               uint32_t view = 0);
+// The same for n_views (<= kMaxLaunchViews) views: view v's counts and
+// offsets start v vstride words after the given ones, its item offsets at
+// item_off + 3 v vstride + list (nb + 1); its items go to items + iv.fine[v]
+// and coarse + iv.coarse[v] (shift iv.coarse_shift[v]), tagged iv.view[v].
+hipError_t launch_build_items_views(const uint32_t *counts, const uint32_t *offsets,
+                                    size_t vstride, int chunk, int cchunk, int min_count,
+                                    const uint32_t *item_off, int list, Item *items, Item *coarse,
+                                    const ItemViews &iv, int n_views, hipStream_t s);
 hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2, int64_t n,
                           const TileK &tk, uint32_t *cursor, uint32_t *pairs,
                           unsigned long long *keys, const uint32_t *umask, hipStream_t s);
@@ -287,6 +320,10 @@ hipError_t launch_convert(const void *src, int sdtype, float sscale, void *dst, 
 constexpr int kStatPartials = 9;
 hipError_t launch_finalise(float *img, int64_t n_px, int aeqe, double *partials, int n_blocks,
                            hipStream_t s);
+// The same for n_views views (img, n_px, blocks, aeqe of iv), partials of
+// view v at partials + v pstride.
+hipError_t launch_finalise_views(const ImgViews &iv, int n_views, double *partials,
+                                 size_t pstride, hipStream_t s);
 // Expected flux sum_p E_p kappa_p of the active records rec[0, n) (span
 // not kInactive) into out[0..2]; partials: 3 x n_blocks doubles.
 hipError_t launch_expected_flux(const float *rec, const uint2 *span, int64_t n, int W, int H,
@@ -294,6 +331,9 @@ hipError_t launch_expected_flux(const float *rec, const uint2 *span, int64_t n, 
                                 hipStream_t s);
 hipError_t launch_reduce_stats(const double *partials, int n_blocks, double *stats,
                                hipStream_t s);
+// The same for n_views views (iv.blocks), stats of view v at stats + v sstride.
+hipError_t launch_reduce_stats_views(const double *partials, size_t pstride, const ImgViews &iv,
+                                     int n_views, double *stats, size_t sstride, hipStream_t s);
 hipError_t launch_normalise(float *img, int64_t n_px, const double *stats, hipStream_t s);
 
 }  // namespace spl
