@@ -525,13 +525,9 @@ __global__ __launch_bounds__(kBlock) void k_items(const uint32_t *__restrict__ c
 template <typename K>
 static int64_t bin_pass_grid(K kernel, size_t sh, int64_t n, int nb, int nt = kBlock) {
   const int64_t units = (n + kUnit - 1) / kUnit;
-  int dev = 0, n_cu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, sh) == hipSuccess &&
-      n_cu > 0 && per_cu > 0)
-    return std::min(units, (int64_t)n_cu * per_cu);
-  (void)hipGetLastError();
+  const int n_cu = cached_attribute(hipDeviceAttributeMultiprocessorCount);
+  const int per_cu = cached_occupancy(reinterpret_cast<const void *>(kernel), nt, sh);
+  if (n_cu > 0 && per_cu > 0) return std::min(units, (int64_t)n_cu * per_cu);
   const int64_t cap = nb <= 6144 ? 4096 : (nb <= 12288 ? 2048 : 1024);
   return std::min((n + kChunk - 1) / kChunk, cap);
 }
@@ -618,12 +614,7 @@ hipError_t launch_scan_views(const uint32_t *counts, int n_views, const int *n_b
   }
   // counts and one output array are staged in LDS when they fit beside the
   // kernel's own 1 KB
-  int dev = 0, lds_max = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
-    lds_max = 0;
-    (void)hipGetLastError();
-  }
+  const int lds_max = cached_attribute(hipDeviceAttributeMaxSharedMemoryPerBlock);
   // views in launches of up to kMaxLaunchViews workgroups
   for (int v0 = 0; v0 < n_views; v0 += kMaxLaunchViews) {
     const int nv = std::min(kMaxLaunchViews, n_views - v0);

@@ -839,11 +839,8 @@ hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pa
 // Persistent launches: as many workgroups as the device holds at once.
 template <class K>
 static int resident_grid(K kernel, int threads, int n_cu) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  return per_cu * n_cu;
+  const int per_cu = cached_occupancy(reinterpret_cast<const void *>(kernel), threads, 0);
+  return (per_cu < 1 ? 1 : per_cu) * n_cu;
 }
 
 int splat_views_resident(int tile, int n_cu) {

@@ -66,6 +66,9 @@ struct Arena {
 };
 
 constexpr int kMaxDevices = 64;
+std::mutex g_launch_mu;  // guards the two caches below
+std::map<std::tuple<int, const void *, int, size_t>, int> g_occupancy;
+std::map<std::pair<int, int>, int> g_attribute;
 std::mutex g_scratch_mu;
 void *g_scratch[kMaxDevices] = {};  // device address of `scratch`, per device
 
@@ -77,6 +80,54 @@ struct TimedFrame {
 };
 
 }  // namespace
+
+namespace spl {
+
+int cached_occupancy(const void *kernel, int threads, size_t lds) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const auto key = std::make_tuple(dev, kernel, threads, lds);
+  {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    auto it = g_occupancy.find(key);
+    if (it != g_occupancy.end()) return it->second;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;  // not kept: a later call asks again
+  }
+  std::lock_guard<std::mutex> lk(g_launch_mu);
+  g_occupancy[key] = per_cu;
+  return per_cu;
+}
+
+int cached_attribute(hipDeviceAttribute_t attr) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const auto key = std::make_pair(dev, (int)attr);
+  {
+    std::lock_guard<std::mutex> lk(g_launch_mu);
+    auto it = g_attribute.find(key);
+    if (it != g_attribute.end()) return it->second;
+  }
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, attr, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  std::lock_guard<std::mutex> lk(g_launch_mu);
+  g_attribute[key] = v;
+  return v;
+}
+
+}  // namespace spl
 
 // A resident particle set: one device allocation holding every array.
 struct spl_dataset {
@@ -434,8 +485,11 @@ hipEvent_t take_event(spl_ctx *c) {
     c->event_pool.pop_back();
     return e;
   }
+  // the stage timers only measure time (no data is read through them), so
+  // their events skip the system-scope fence each recording would otherwise
+  // wait for
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 

@@ -205,6 +205,14 @@ struct ItemViews {
   uint32_t fine[kMaxLaunchViews], coarse[kMaxLaunchViews];  // item array offsets
   uint32_t coarse_shift[kMaxLaunchViews], view[kMaxLaunchViews];
 };
+// Launch facts of the current device that do not change while the process
+// runs, queried once and kept (each HIP query costs microseconds, and the
+// launches after a frame's host synchronisation find the device idle until
+// they arrive): workgroups of `kernel` a compute unit holds at `threads`
+// lanes and `lds` bytes of dynamic LDS (0 if the query fails), and a device
+// attribute (0 if the query fails).
+int cached_occupancy(const void *kernel, int threads, size_t lds);
+int cached_attribute(hipDeviceAttribute_t attr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // Copies bytes (a multiple of 4) from device memory into page-locked host
 // memory through its device-side address, with a kernel.
