@@ -187,3 +187,42 @@ def test_batch_mixed_tile_sizes(env, graphs):
         assert st["tile"] == t == st1["tile"]
         assert st["n_pairs"] == st1["n_pairs"]
         assert rel_l2(o.cpu().numpy(), single.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_more_views_than_one_launch_serves(env, graphs):
+    """150 views in one call: the batch's per-view kernels (scans, item
+    builds, image clears, final maps, FP64 reductions) run in launches of up
+    to 64 views, here three (64 + 64 + 22); every view, with its statistics,
+    must equal its single-view render."""
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals = _setup(B, n=60_000, seed=54)
+    parts = B.DeviceParticles(ps, "cuda:0")
+    P = B.Palettes(pals)
+    sizes = [(64, 48), (96, 64), (40, 72), (128, 96), (33, 17)]
+    poses = [synth.random_poses(1, seed=700 + k, width=sizes[k % 5][0],
+                                height=sizes[k % 5][1])[0] for k in range(150)]
+    prms = [B.make_params(1 if k % 3 else 0, P, looks, tile=16, large_cut=-1.0,
+                          normalise=int(k % 7 == 0), flux_check=int(k % 11 == 0))
+            for k in range(150)]
+    print(f"150 views graphs={graphs}", flush=True)
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, graphs)
+    outs, sts = ctx.spl_render_batch(parts, poses, prms)
+    ctx.spl_set_option(B.SPL_OPT_GRAPHS, 0)
+    torch.cuda.synchronize()
+    for k, (pose, prm, o, st) in enumerate(zip(poses, prms, outs, sts)):
+        single, st1 = ctx.spl_render(parts, pose, prm)
+        torch.cuda.synchronize()
+        got, want = o.cpu().numpy().astype(np.float64), single.cpu().numpy().astype(np.float64)
+        if np.abs(want).max() == 0:
+            assert np.abs(got).max() == 0, k
+            continue
+        assert rel_l2(got, want) < 1e-6, k
+        assert st["n_active"] == st1["n_active"] and st["n_pairs"] == st1["n_pairs"], k
+        np.testing.assert_allclose(st["flux"], st1["flux"], rtol=1e-5, err_msg=str(k))
+        np.testing.assert_allclose(st["max"], st1["max"], rtol=1e-5, err_msg=str(k))
+        if prm.flux_check:
+            np.testing.assert_allclose(st["expected_flux"], st1["expected_flux"], rtol=1e-9,
+                                       err_msg=str(k))
