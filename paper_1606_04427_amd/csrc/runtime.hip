@@ -817,11 +817,25 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   for (int v = 0; v < nv; ++v) {
     nbv[v] = tk[v].n_tiles + tk[v].n_ctiles;
     nfv[v] = tk[v].n_tiles;
+  }
+  for (int v = 0; v < nv;) {
+    // two views per pass where both count in the projection: each particle's
+    // attributes are then read once for the pair
+    if (v + 1 < nv && project_pair_ok(pk[v], tk[v], pk[v + 1], tk[v + 1])) {
+      float *const rp[2] = {rec + (size_t)v * n * 8, rec + (size_t)(v + 1) * n * 8};
+      uint2 *const sp[2] = {span + (size_t)v * n, span + (size_t)(v + 1) * n};
+      Totals *const tp[2] = {tot + v, tot + v + 1};
+      uint32_t *const cp[2] = {counts + v * bstride, counts + (v + 1) * bstride};
+      HIPTRY(c, launch_project_pair(pk + v, tk + v, rp, sp, tp, cp, s));
+      v += 2;
+      continue;
+    }
     float *rv = rec + (size_t)v * n * 8;
     uint2 *sv = span + (size_t)v * n;
     HIPTRY(c, launch_project(pk[v], tk[v], rv, nullptr, sv, 0, tot + v, s, counts + v * bstride));
     if (!project_counts(tk[v]))
       HIPTRY(c, launch_count(sv, rv, n, tk[v], counts + v * bstride, umask + v * mstride, s));
+    ++v;
   }
   HIPTRY(c, launch_scan_views(counts, nv, nbv.data(), nfv.data(), bstride, offsets, cursor, chunk,
                               cchunk, minc, itemoff, tot, s));

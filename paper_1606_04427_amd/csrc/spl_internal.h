@@ -228,6 +228,14 @@ bool project_counts(const TileK &tk);
 hipError_t launch_project(const ProjK &pk, const TileK &tk, float *rec, float *rec2,
                           uint2 *span, int write_inactive, Totals *tot, hipStream_t s,
                           uint32_t *counts = nullptr);
+// Two additive views of the same particles in one pass (each particle's
+// attributes read once), with their tile counts (both project_counts): the
+// batch path's pairs of views.  project_pair_ok tells whether two views
+// qualify.
+bool project_pair_ok(const ProjK &a, const TileK &ta, const ProjK &b, const TileK &tb);
+hipError_t launch_project_pair(const ProjK pk[2], const TileK tk[2], float *const rec[2],
+                               uint2 *const span[2], Totals *const tot[2],
+                               uint32_t *const counts[2], hipStream_t s);
 hipError_t launch_span_from_records(const float *rec, int64_t n, const TileK &tk, uint2 *span,
                                     Totals *tot, hipStream_t s);
 hipError_t launch_scalar_range(const ProjK &pk, int n_species, int log10, double *out_minmax,
