@@ -45,7 +45,8 @@ __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v);
 // over the spans.  V views of the same particles (V = 2 for pairs of views of
 // a batch): each particle's attributes are read once and projected for every
 // view, each view with its own records, spans, totals and histogram (view v's
-// at hist + A.hoff[v]).  Views of one launch share the particle arrays of
+// bins numbered from A.hoff[v] on: 32-bit bins for one view, two 16-bit bins
+// per LDS word for a pair).  Views of one launch share the particle arrays of
 // A.P[0]; with V > 1 none is depth-sorted (no absorption is read).
 template <int V>
 struct ProjArgs {
