@@ -23,10 +23,18 @@ __global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t *p, uint32_t v, in
 // Small device-to-host read-back: one workgroup copies 32-bit words into
 // page-locked host memory mapped into the device's address space.  Kept off
 // the copy engines, so it never queues behind a large host-to-device copy on
-// another stream.
+// another stream.  With a completion word (flag): every lane makes its own
+// copied words visible at system scope, then, after the workgroup barrier,
+// lane 0 stores seq into flag, so a host that sees seq there also sees the
+// words.
 __global__ __launch_bounds__(kBlock) void k_readback(const uint32_t *__restrict__ src,
-                                                     uint32_t *__restrict__ dst, int words) {
+                                                     uint32_t *__restrict__ dst, int words,
+                                                     uint32_t *flag, uint32_t seq) {
   for (int i = threadIdx.x; i < words; i += kBlock) dst[i] = src[i];
+  if (!flag) return;
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ void k_fill_f64(double *p, int n) {
@@ -235,10 +243,12 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s) {
-  if (bytes == 0) return hipSuccess;
+hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s,
+                           void *flag_mapped, uint32_t seq) {
+  if (bytes == 0 && !flag_mapped) return hipSuccess;
   hipLaunchKernelGGL(k_readback, dim3(1), dim3(kBlock), 0, s, static_cast<const uint32_t *>(src),
-                     static_cast<uint32_t *>(dst_mapped), (int)(bytes / 4));
+                     static_cast<uint32_t *>(dst_mapped), (int)(bytes / 4),
+                     static_cast<uint32_t *>(flag_mapped), seq);
   return hipGetLastError();
 }
 

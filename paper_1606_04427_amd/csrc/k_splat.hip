@@ -850,10 +850,12 @@ int splat_views_resident(int tile, int n_cu) {
 
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
-                              uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s) {
-  hipLaunchKernelGGL(k_splat_large_views,
-                     dim3(resident_grid(k_splat_large_views, kLargeThreads, n_cu)),
-                     dim3(kLargeThreads), 0, s, views, large, n_large, next_large, cchunk);
+                              uint32_t *next_large, int chunk, int cchunk, int n_cu,
+                              bool any_large, hipStream_t s) {
+  if (any_large)
+    hipLaunchKernelGGL(k_splat_large_views,
+                       dim3(resident_grid(k_splat_large_views, kLargeThreads, n_cu)),
+                       dim3(kLargeThreads), 0, s, views, large, n_large, next_large, cchunk);
   if (tile == 16)
     hipLaunchKernelGGL((k_splat_add_views<16>),
                        dim3(resident_grid(k_splat_add_views<16>, kBlock, n_cu)), dim3(kBlock), 0,

@@ -10,6 +10,7 @@
 // every list and item buffer is sized exactly; no kernel can overflow a
 // buffer.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -149,6 +150,11 @@ struct spl_ctx {
   double *h_stats = nullptr;
   void *m_tot = nullptr;     // ... and its device-side addresses, written by
   void *m_stats = nullptr;   // the read-back kernel
+  // read-back completion word (page-locked, device-side address m_flag): the
+  // read-back kernel writes the call's sequence number there after the data
+  uint32_t *h_flag = nullptr;
+  void *m_flag = nullptr;
+  uint32_t rb_seq = 0;
   int64_t bytes = 0;
   // autotuner choices: per (n, W, H, mode, camera pose), and the most
   // recent choice per (n, W, H, mode) for poses that were not tuned
@@ -530,6 +536,32 @@ void resolve_timing(spl_ctx *c, bool wait) {
   c->pending.swap(keep);
 }
 
+// Reads `bytes` of device memory at src back into page-locked host memory
+// (dst_mapped: its device-side address) and waits until they are there: the
+// read-back kernel writes them, then, after a system-scope fence, this
+// call's sequence number into h_flag, which the host watches (a stream
+// synchronisation would add its own wake-up latency while the device waits
+// for the host's next launches).  After kSpinMicros without the number the
+// host blocks on the stream instead (a long frame, or a failed launch whose
+// error the synchronisation then reports).
+constexpr int kSpinMicros = 20000;
+
+spl_status readback_wait(spl_ctx *c, const void *src, void *dst_mapped, size_t bytes,
+                         hipStream_t s) {
+  const uint32_t seq = ++c->rb_seq;
+  HIPTRY(c, launch_readback(src, dst_mapped, bytes, s, c->m_flag, seq));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) == seq) return SPL_OK;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kSpinMicros)) break;
+    __builtin_ia32_pause();
+  }
+  HIPTRY(c, hipStreamSynchronize(s));
+  if (__atomic_load_n(c->h_flag, __ATOMIC_ACQUIRE) != seq)
+    return fail(c, SPL_EDEVICE, "read-back of %zu bytes did not arrive", bytes);
+  return SPL_OK;
+}
+
 // The end of a frame: the absorption = emission map (additive J before it),
 // FP64 flux and maximum per channel, optional division by the maximum.
 spl_status finish_image(spl_ctx *c, float *img, int64_t npx, int mode, int normalise,
@@ -566,8 +598,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   const int minc[3] = {1, 1, kSortChunk + 1};
   HIPTRY(c, launch_scan(counts, nb, tk.n_tiles, offsets, cursor, chunk, cchunk, minc, item_off, tot, s));
   mark(tf, 3, s);
-  HIPTRY(c, launch_readback(tot, c->m_tot, sizeof(Totals), s));
-  HIPTRY(c, hipStreamSynchronize(s));
+  TRY(readback_wait(c, tot, c->m_tot, sizeof(Totals), s));
   if (c->timing) resolve_timing(c, false);
   const Totals T = *c->h_tot;
   if (T.n_pairs >= 0xffffffffull)
@@ -842,8 +873,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
   mark(tf, 1, s);
   mark(tf, 2, s);
   mark(tf, 3, s);
-  HIPTRY(c, launch_readback(tot, c->m_btot, sizeof(Totals) * nv, s));
-  HIPTRY(c, hipStreamSynchronize(s));
+  TRY(readback_wait(c, tot, c->m_btot, sizeof(Totals) * nv, s));
   // item length: the long items when there are enough of them for every
   // resident workgroup of the persistent splat
   int ks = 0;
@@ -958,7 +988,7 @@ spl_status render_views(spl_ctx *c, const spl_particles *p, int nv, const ProjK 
       mark(tf, 6, q);
       mark(tf, 7, q);
       HIPTRY(c, launch_splat_views(tk[0].tile, dviews, itf, ctr, ctr + 2, itc, ctr + 1, ctr + 3,
-                                   ichunk, kChunkLarge, c->n_cu, q));
+                                   ichunk, kChunkLarge, c->n_cu, gcoarse[g] > 0, q));
       mark(tf, 8, q);
       double *fin = (double *)c->b_fin.p, *stats = (double *)c->b_stats.p;
       // the final map and FP64 reductions of the group's views, one launch
@@ -1527,16 +1557,21 @@ spl_status spl_create(int device, spl_ctx **out) {
     c->n_cu = ncu;
   if (hipHostMalloc((void **)&c->h_tot, sizeof(Totals), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_stats, kStatWords * sizeof(double), hipHostMallocDefault) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipHostMalloc((void **)&c->h_flag, 64, hipHostMallocDefault) != hipSuccess) {
     if (c->h_tot) (void)hipHostFree(c->h_tot);
+    if (c->h_stats) (void)hipHostFree(c->h_stats);
     delete c;
     return SPL_ENOMEM;
   }
+  *c->h_flag = 0;
   if (hipHostGetDevicePointer(&c->m_tot, c->h_tot, 0) != hipSuccess ||
-      hipHostGetDevicePointer(&c->m_stats, c->h_stats, 0) != hipSuccess) {
+      hipHostGetDevicePointer(&c->m_stats, c->h_stats, 0) != hipSuccess ||
+      hipHostGetDevicePointer(&c->m_flag, c->h_flag, 0) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipHostFree(c->h_tot);
     (void)hipHostFree(c->h_stats);
+    (void)hipHostFree(c->h_flag);
     delete c;
     return SPL_EDEVICE;
   }
@@ -1583,6 +1618,7 @@ void spl_destroy(spl_ctx *c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   if (c->h_tot) (void)hipHostFree(c->h_tot);
   if (c->h_stats) (void)hipHostFree(c->h_stats);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
   if (c->h_btot) (void)hipHostFree(c->h_btot);
   if (c->h_views) (void)hipHostFree(c->h_views);
   if (c->h_ctr) (void)hipHostFree(c->h_ctr);

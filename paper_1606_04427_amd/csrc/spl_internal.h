@@ -215,8 +215,11 @@ int cached_occupancy(const void *kernel, int threads, size_t lds);
 int cached_attribute(hipDeviceAttribute_t attr);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 // Copies bytes (a multiple of 4) from device memory into page-locked host
-// memory through its device-side address, with a kernel.
-hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s);
+// memory through its device-side address, with a kernel; with flag_mapped
+// (the device-side address of a page-locked word), then writes seq there,
+// after the copied words are visible to the host.
+hipError_t launch_readback(const void *src, void *dst_mapped, size_t bytes, hipStream_t s,
+                           void *flag_mapped = nullptr, uint32_t seq = 0);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
 // Zeroes the images iv.img[v] (3 n_px[v] floats) of n_views views.
 hipError_t launch_clear_views(const ImgViews &iv, int n_views, hipStream_t s);
@@ -306,9 +309,12 @@ hipError_t launch_splat_large(const Item *items, int n_items, const uint32_t *pa
 // items first, then fine items; n_* and next_* are device counters.
 // Workgroups of the persistent additive splat the device holds at once.
 int splat_views_resident(int tile, int n_cu);
+// any_large: whether the views have large-particle items at all (their
+// persistent launch is skipped otherwise).
 hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, const uint32_t *n_fine,
                               uint32_t *next_fine, const Item *large, const uint32_t *n_large,
-                              uint32_t *next_large, int chunk, int cchunk, int n_cu, hipStream_t s);
+                              uint32_t *next_large, int chunk, int cchunk, int n_cu,
+                              bool any_large, hipStream_t s);
 // keys: the buffer the scatter wrote; keys_b: the merge passes' other buffer
 // (each list is read from the one its merge passes end in, sort_chunk = k0).
 // rec2 NULL: no absorption, the ordered additive sum, added into img (the
