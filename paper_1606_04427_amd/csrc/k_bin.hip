@@ -188,8 +188,8 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
   // (wraps above the window's top when bin < lo)
   auto in_win = [&](uint32_t bin) { return bin - (uint32_t)lo < (uint32_t)nbw; };
   // local counts of all the workgroup's chunks, then one global reservation
-  // per bin (the order inside a bin is free: additive lists are summed,
-  // keyed ones are sorted next, by depth or by index)
+  // per bin (the order inside a bin is free: additive lists are summed or
+  // sorted on the index next, keyed ones are sorted on depth next)
   for (int i = threadIdx.x; i < nbw; i += NT) hist[i] = 0;
   __syncthreads();
   {
@@ -262,8 +262,7 @@ __global__ __launch_bounds__(NT) void k_scatter(const uint2 *__restrict__ span,
       const int key = single ? off + d.ty0 * ntx + d.tx0 : -1;
       const bool mine = single && in_win((uint32_t)key);
       unsigned long long key_hi = 0;
-      // (no depths: the key is the index alone, the stable order)
-      if (kKeys && act && rec2) key_hi = (unsigned long long)__float_as_uint(rec2[k].y) << 32;
+      if (kKeys && act) key_hi = (unsigned long long)__float_as_uint(rec2[k].y) << 32;
       int head_of;
       const int len = wave_runs(single, key, head_of);
       uint32_t rb = 0;

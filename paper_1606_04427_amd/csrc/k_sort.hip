@@ -2,7 +2,9 @@
 // (Sect. 2.1: the transfer equation makes compositing order-dependent).
 // Keys are 64-bit: the IEEE bits of the (positive) view depth in the high
 // word and the particle index in the low word, so ascending keys are
-// ascending (depth, index) and every key is unique.
+// ascending (depth, index) and every key is unique.  The same kernels sort
+// 32-bit keys, the particle indices alone, for the lists in ascending index
+// (the stable order of the additive frames drawn in list order).
 //
 //  k_sort_chunks  one workgroup per list chunk of <= 4096 keys: bitonic sort
 //                 with up to 8 keys per lane of 512 in registers.  A list
@@ -24,8 +26,8 @@ constexpr int kMergeOut = 2048;  // outputs per workgroup = 256 lanes x 8
 __device__ __forceinline__ int padded(int pos) { return pos + (pos >> 4); }
 
 // Compare-exchange stage with partners J < E apart inside one thread's keys.
-template <int J, int E>
-__device__ __forceinline__ void reg_stage(unsigned long long (&v)[E], int t, int k) {
+template <int J, int E, typename K>
+__device__ __forceinline__ void reg_stage(K (&v)[E], int t, int k) {
   if constexpr (J < E) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -33,7 +35,7 @@ __device__ __forceinline__ void reg_stage(unsigned long long (&v)[E], int t, int
         // ascending pairs swap when b < a, descending ones when not (equal
         // keys are only padding, so swapping them changes nothing)
         const bool up = ((t * E + e) & k) == 0;
-        const unsigned long long a = v[e], b = v[e + J];
+        const K a = v[e], b = v[e + J];
         const bool sw = (b < a) == up;
         v[e] = sw ? b : a;
         v[e + J] = sw ? a : b;
@@ -44,6 +46,17 @@ __device__ __forceinline__ void reg_stage(unsigned long long (&v)[E], int t, int
 
 // Partner key of lane ^ m for m < 32: DPP lane permutes inside quads for
 // m = 1, 2, LDS swizzles (no address operand) otherwise.
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  if constexpr (M == 1) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xf, 0xf, false);
+  } else if constexpr (M == 2) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xf, 0xf, false);
+  } else {
+    constexpr int pat = 0x1f | (M << 10);  // bit-mask mode: and 31, xor M
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, pat);
+  }
+}
 template <int M>
 __device__ __forceinline__ unsigned long long xor_lane(unsigned long long v) {
   const int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
@@ -68,14 +81,13 @@ __device__ __forceinline__ unsigned long long xor_lane(unsigned long long v) {
 // 64 E away sit in the same wave and are read with a lane shuffle; farther
 // ones go through LDS.  Loads and stores pass through LDS so that global
 // accesses stay coalesced.
-template <int E, int NT>
-__device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys, uint32_t b0,
-                                           int n, unsigned long long *s) {
+template <int E, int NT, typename K>
+__device__ __forceinline__ void sort_chunk(K *__restrict__ keys, uint32_t b0, int n, K *s) {
   constexpr int NP = NT * E;
   const int t = threadIdx.x;
-  for (int p = t; p < NP; p += NT) s[padded(p)] = (p < n) ? keys[b0 + p] : ~0ull;
+  for (int p = t; p < NP; p += NT) s[padded(p)] = (p < n) ? keys[b0 + p] : ~(K)0;
   __syncthreads();
-  unsigned long long v[E];
+  K v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = s[padded(t * E + e)];
 #pragma unroll 1
@@ -98,17 +110,17 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
           auto cx = [&](auto partner) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-              const unsigned long long w = partner(v[e]);
+              const K w = partner(v[e]);
               v[e] = ((w < v[e]) == keep_min) ? w : v[e];
             }
           };
           switch (m) {
-            case 1: cx([](unsigned long long x) { return xor_lane<1>(x); }); break;
-            case 2: cx([](unsigned long long x) { return xor_lane<2>(x); }); break;
-            case 4: cx([](unsigned long long x) { return xor_lane<4>(x); }); break;
-            case 8: cx([](unsigned long long x) { return xor_lane<8>(x); }); break;
-            case 16: cx([](unsigned long long x) { return xor_lane<16>(x); }); break;
-            default: cx([](unsigned long long x) { return __shfl_xor(x, 32); }); break;
+            case 1: cx([](K x) { return xor_lane<1>(x); }); break;
+            case 2: cx([](K x) { return xor_lane<2>(x); }); break;
+            case 4: cx([](K x) { return xor_lane<4>(x); }); break;
+            case 8: cx([](K x) { return xor_lane<8>(x); }); break;
+            case 16: cx([](K x) { return xor_lane<16>(x); }); break;
+            default: cx([](K x) { return __shfl_xor(x, 32); }); break;
           }
         } else {
           __syncthreads();
@@ -117,7 +129,7 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
           __syncthreads();
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const unsigned long long w = s[padded((t ^ m) * E + e)];
+            const K w = s[padded((t ^ m) * E + e)];
             v[e] = ((w < v[e]) == keep_min) ? w : v[e];
           }
         }
@@ -135,11 +147,12 @@ __device__ __forceinline__ void sort_chunk(unsigned long long *__restrict__ keys
 // workgroups per CU, and 512-lane ones bring twice the waves of 256-lane
 // ones (at the price of one more stage through LDS per merge level).
 constexpr int kSortThreads = 512;
-__global__ __launch_bounds__(kSortThreads) void k_sort_chunks(unsigned long long *__restrict__ keys,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_chunks(K *__restrict__ keys,
                                                               const Item *__restrict__ items) {
   constexpr int NT = kSortThreads;
   static_assert(NT * 8 == kSortChunk, "a chunk is 8 keys per lane");
-  __shared__ unsigned long long s[kSortChunk + kSortChunk / 16];
+  __shared__ K s[kSortChunk + kSortChunk / 16];
   const Item it = items[blockIdx.x];
   const int n = (int)(it.z - it.y);
   if (n <= NT)
@@ -156,8 +169,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_chunks(unsigned long long
 // of the merge path's crossing of diagonal `diag`.  One wave tests 64 evenly
 // spaced candidates per round and keeps the bracket where the predicate turns,
 // so a search over L candidates takes log64(L) rounds of global loads.
-__device__ __forceinline__ int64_t wave_merge_split(const unsigned long long *__restrict__ A,
-                                                    const unsigned long long *__restrict__ B,
+template <typename K>
+__device__ __forceinline__ int64_t wave_merge_split(const K *__restrict__ A,
+                                                    const K *__restrict__ B,
                                                     int64_t diag, int64_t lo, int64_t hi) {
   const int lane = __lane_id();
   while (hi > lo) {  // uniform across the wave
@@ -183,14 +197,15 @@ __device__ __forceinline__ int64_t wave_merge_split(const unsigned long long *__
 // between are staged in LDS with coalesced loads, each lane merges 8
 // outputs from LDS after a binary search there, and the merged range is
 // written back with coalesced stores.
-__global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long *__restrict__ src,
-                                                       unsigned long long *__restrict__ dst,
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_merge_pass(const K *__restrict__ src,
+                                                       K *__restrict__ dst,
                                                        const Item *__restrict__ items,
                                                        const uint32_t *__restrict__ offsets,
                                                        const uint32_t *__restrict__ counts,
                                                        int64_t L) {
-  __shared__ unsigned long long s_k[kMergeOut];
-  __shared__ unsigned long long s_o[kMergeOut];  // merged outputs, stored coalesced
+  __shared__ K s_k[kMergeOut];
+  __shared__ K s_o[kMergeOut];  // merged outputs, stored coalesced
   __shared__ int64_t s_split[2];
   const Item it = items[blockIdx.x];
   const int64_t s0 = offsets[it.x];
@@ -201,8 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
   const int64_t ps = (d0 / (2 * L)) * (2 * L);
   const int64_t la = min(L, n - ps);
   const int64_t lb = max((int64_t)0, min(L, n - ps - L));
-  const unsigned long long *A = src + s0 + ps;
-  const unsigned long long *B = A + L;
+  const K *A = src + s0 + ps;
+  const K *B = A + L;
   const int wave = threadIdx.x >> 6;
   if (wave < 2) {
     const int64_t diag = (wave == 0 ? d0 : d1) - ps;
@@ -219,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
   const int tot = na + nb;
   const int dl = 8 * (int)threadIdx.x;
   if (dl < tot) {
-    const unsigned long long *As = s_k, *Bs = s_k + na;
+    const K *As = s_k, *Bs = s_k + na;
     int lo = max(0, dl - nb), hi = min(dl, na);
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
@@ -231,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
     int i = lo, j = dl - lo;
     const int cnt = min(8, tot - dl);
     for (int o = 0; o < cnt; ++o) {
-      unsigned long long v;
+      K v;
       if (j >= nb || (i < na && As[i] < Bs[j]))
         v = As[i++];
       else
@@ -240,12 +255,13 @@ __global__ __launch_bounds__(kBlock) void k_merge_pass(const unsigned long long 
     }
   }
   __syncthreads();
-  unsigned long long *out = dst + s0 + d0;
+  K *out = dst + s0 + d0;
   for (int k = threadIdx.x; k < tot; k += kBlock) out[k] = s_o[k];
 }
 
-__global__ __launch_bounds__(kBlock) void k_copy_items(const unsigned long long *__restrict__ src,
-                                                       unsigned long long *__restrict__ dst,
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_copy_items(const K *__restrict__ src,
+                                                       K *__restrict__ dst,
                                                        const Item *__restrict__ items,
                                                        const uint32_t *__restrict__ counts,
                                                        uint32_t k0) {
@@ -272,28 +288,59 @@ hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32
   return hipGetLastError();
 }
 
+template <typename K>
+static hipError_t sort_chunks(K *keys, const Item *items, int n_items, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_chunks<K>, dim3(n_items), dim3(kSortThreads), 0, s, keys, items);
+  return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t merge_pass(const K *src, K *dst, const Item *items, int n_items,
+                             const uint32_t *offsets, const uint32_t *counts, int run,
+                             hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_pass<K>, dim3(n_items), dim3(kBlock), 0, s, src, dst, items, offsets,
+                     counts, (int64_t)run);
+  return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t copy_items(const K *src, K *dst, const Item *items, int n_items,
+                             const uint32_t *counts, uint32_t k0, hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_items<K>, dim3(n_items), dim3(kBlock), 0, s, src, dst, items, counts,
+                     k0);
+  return hipGetLastError();
+}
+
 hipError_t launch_sort_chunks(unsigned long long *keys, const Item *items, int n_items,
                               hipStream_t s) {
-  if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort_chunks, dim3(n_items), dim3(kSortThreads), 0, s, keys, items);
-  return hipGetLastError();
+  return sort_chunks(keys, items, n_items, s);
+}
+hipError_t launch_sort_chunks(uint32_t *keys, const Item *items, int n_items, hipStream_t s) {
+  return sort_chunks(keys, items, n_items, s);
 }
 
 hipError_t launch_merge_pass(const unsigned long long *src, unsigned long long *dst,
                              const Item *items, int n_items, const uint32_t *offsets,
                              const uint32_t *counts, int run, hipStream_t s) {
-  if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_merge_pass, dim3(n_items), dim3(kBlock), 0, s, src, dst, items, offsets,
-                     counts, (int64_t)run);
-  return hipGetLastError();
+  return merge_pass(src, dst, items, n_items, offsets, counts, run, s);
+}
+hipError_t launch_merge_pass(const uint32_t *src, uint32_t *dst, const Item *items, int n_items,
+                             const uint32_t *offsets, const uint32_t *counts, int run,
+                             hipStream_t s) {
+  return merge_pass(src, dst, items, n_items, offsets, counts, run, s);
 }
 
 hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *dst,
                              const Item *items, int n_items, const uint32_t *counts, uint32_t k0,
                              hipStream_t s) {
-  if (n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_copy_items, dim3(n_items), dim3(kBlock), 0, s, src, dst, items, counts, k0);
-  return hipGetLastError();
+  return copy_items(src, dst, items, n_items, counts, k0, s);
+}
+hipError_t launch_copy_items(const uint32_t *src, uint32_t *dst, const Item *items, int n_items,
+                             const uint32_t *counts, uint32_t k0, hipStream_t s) {
+  return copy_items(src, dst, items, n_items, counts, k0, s);
 }
 
 }  // namespace spl

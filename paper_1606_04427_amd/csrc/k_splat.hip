@@ -534,10 +534,12 @@ __global__ __launch_bounds__(kLargeThreads) void k_splat_large_views(
 // T *= T_piece.  The pieces of one batch fill at most NQ + 31 slots: the
 // (group, micro-tile) pairs of the walk form a staircase, so group + micro-tile
 // numbers them.
-template <int T, bool kAbs>
+// (KT: 64-bit (depth, index) keys with absorption, 32-bit indices without)
+template <int T, bool kAbs, typename KT = typename std::conditional<kAbs, unsigned long long,
+                                                                    uint32_t>::type>
 __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ items,
-                                                      const unsigned long long *__restrict__ keys,
-                                                      const unsigned long long *__restrict__ keys_b,
+                                                      const KT *__restrict__ keys,
+                                                      const KT *__restrict__ keys_b,
                                                       uint32_t sort_chunk,
                                                       const float4 *__restrict__ rec,
                                                       const float2 *__restrict__ rec2,
@@ -574,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
   const uint32_t cnt_tile = counts[it.x];
   const bool multi = cnt_tile > (uint32_t)chunk;
   // the buffer the list's merge passes left it in
-  const unsigned long long *const src = (merge_passes(cnt_tile, sort_chunk) & 1) ? keys_b : keys;
+  const KT *const src = (merge_passes(cnt_tile, sort_chunk) & 1) ? keys_b : keys;
   // list building: 16-lane groups; walk: 8-lane groups, lane (lx, ly) of a
   // group takes the micro-tile pixels (lx, ly) and (lx, ly + 2)
   const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15, gw = grp & 3;
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_composite(const Item *__restrict__ i
     const uint32_t k = base + tid;
     MaskT mask = 0;
     if (k < it.z) {
-      const uint32_t pid = (uint32_t)(src[k] & 0xffffffffull);
+      const uint32_t pid = (uint32_t)(src[k] & (KT)0xffffffffu);
       const float4 r0 = rec[2 * (size_t)pid];
       const float4 r1 = rec[2 * (size_t)pid + 1];
       // (listed records are finite with sigma > 0)
@@ -870,7 +872,7 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
 }
 
 hipError_t launch_composite(int tile, const Item *items, int n_items,
-                            const unsigned long long *keys, const unsigned long long *keys_b,
+                            const void *keys, const void *keys_b,
                             uint32_t sort_chunk, const float *rec, const float *rec2,
                             const uint32_t *counts, int chunk, const TileK &tk, float *img,
                             float *partial, hipStream_t s) {
@@ -878,15 +880,19 @@ hipError_t launch_composite(int tile, const Item *items, int n_items,
   const float4 *r = reinterpret_cast<const float4 *>(rec);
   const float2 *r2 = reinterpret_cast<const float2 *>(rec2);
   float4 *pp = reinterpret_cast<float4 *>(partial);
-  auto go = [&](auto kernel) {
-    hipLaunchKernelGGL(kernel, dim3(n_items), dim3(kBlock), 0, s, items, keys, keys_b, sort_chunk,
-                       r, r2, counts, chunk, tk, img, pp);
+  const auto *k64 = static_cast<const unsigned long long *>(keys);
+  const auto *k64b = static_cast<const unsigned long long *>(keys_b);
+  const auto *k32 = static_cast<const uint32_t *>(keys);
+  const auto *k32b = static_cast<const uint32_t *>(keys_b);
+  auto go = [&](auto kernel, auto ka, auto kb) {
+    hipLaunchKernelGGL(kernel, dim3(n_items), dim3(kBlock), 0, s, items, ka, kb, sort_chunk, r, r2,
+                       counts, chunk, tk, img, pp);
   };
-  // without rec2 (no absorption): the ordered additive sum
+  // without rec2 (no absorption): the ordered additive sum over index lists
   if (tile == 16)
-    r2 ? go(k_composite<16, true>) : go(k_composite<16, false>);
+    r2 ? go(k_composite<16, true>, k64, k64b) : go(k_composite<16, false>, k32, k32b);
   else if (tile == 32)
-    r2 ? go(k_composite<32, true>) : go(k_composite<32, false>);
+    r2 ? go(k_composite<32, true>, k64, k64b) : go(k_composite<32, false>, k32, k32b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -607,11 +607,14 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     if (T.n_items[k] > 0x7fffffffull)
       return fail(c, SPL_EUNSUPPORTED, "too many work items (%llu)", T.n_items[k]);
 
-  if (ordered) {
+  // depth order: 64-bit (depth bits, index) keys in two buffers; the stable
+  // order: the 32-bit index lists and a second buffer for the merges
+  if (sorted) {
     TRY(ensure(c, c->keysA, T.n_pairs * 8));
     TRY(ensure(c, c->keysB, T.n_pairs * 8));
   } else {
     TRY(ensure(c, c->pairs, T.n_pairs * 4));
+    if (ordered) TRY(ensure(c, c->keysB, T.n_pairs * 4));
   }
   for (int k = 0; k < 3; ++k) {
     if (chunk[k] == 0) continue;
@@ -624,7 +627,7 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   unsigned long long *keysB = (unsigned long long *)c->keysB.p;
   mark(tf, 4, s);
   HIPTRY(c, launch_scatter(span, f.rec, f.rec2, f.n, tk, cursor, (uint32_t *)c->pairs.p,
-                           ordered ? keysA : nullptr, umask, s));
+                           sorted ? keysA : nullptr, umask, s));
   mark(tf, 5, s);
   const Item *items0 = (const Item *)c->items[0].p;
   int passes = 0;
@@ -640,11 +643,19 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
                                kChunkSplat, tk, f.out, s));
     mark(tf, 8, s);
   } else {
-    HIPTRY(c, launch_sort_chunks(keysA, (const Item *)c->items[1].p, (int)T.n_items[1], s));
+    uint32_t *idxA = (uint32_t *)c->pairs.p, *idxB = (uint32_t *)c->keysB.p;
+    const Item *it1 = (const Item *)c->items[1].p, *it2 = (const Item *)c->items[2].p;
+    if (sorted)
+      HIPTRY(c, launch_sort_chunks(keysA, it1, (int)T.n_items[1], s));
+    else
+      HIPTRY(c, launch_sort_chunks(idxA, it1, (int)T.n_items[1], s));
     for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {
-      HIPTRY(c, launch_merge_pass(passes % 2 ? keysB : keysA, passes % 2 ? keysA : keysB,
-                                  (const Item *)c->items[2].p, (int)T.n_items[2], offsets, counts,
-                                  (int)L, s));
+      if (sorted)
+        HIPTRY(c, launch_merge_pass(passes % 2 ? keysB : keysA, passes % 2 ? keysA : keysB, it2,
+                                    (int)T.n_items[2], offsets, counts, (int)L, s));
+      else
+        HIPTRY(c, launch_merge_pass(passes % 2 ? idxB : idxA, passes % 2 ? idxA : idxB, it2,
+                                    (int)T.n_items[2], offsets, counts, (int)L, s));
       ++passes;
     }
     mark(tf, 6, s);
@@ -652,7 +663,8 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     mark(tf, 7, s);
     const int ni = (int)T.n_items[0];
     TRY(ensure(c, c->partial, (size_t)ni * tk.tile * tk.tile * 16));
-    HIPTRY(c, launch_composite(tk.tile, items0, ni, keysA, keysB, (uint32_t)kSortChunk, f.rec, f.rec2, counts, kChunkSplat, tk,
+    HIPTRY(c, launch_composite(tk.tile, items0, ni, sorted ? (const void *)keysA : idxA,
+                               sorted ? (const void *)keysB : idxB, (uint32_t)kSortChunk, f.rec, f.rec2, counts, kChunkSplat, tk,
                                f.out, (float *)c->partial.p, s));
     HIPTRY(c, launch_composite_merge(tk.tile, sorted, items0, ni, counts, kChunkSplat, tk,
                                      (const float *)c->partial.p, f.out, s));
@@ -673,17 +685,18 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
     B[1] = f.counted ? 0.0 : n * 8.0 + 4.0 * nb;
     B[2] = 4.0 * nb * 3.0;
     B[3] = 16.0 * (double)(T.n_items[0] + T.n_items[1] + T.n_items[2]);
-    B[4] = n * 8.0 + pairs * (ordered ? 8.0 : 4.0);
+    B[4] = n * 8.0 + pairs * (sorted ? 8.0 : 4.0);
     // chunk sort: every key read and written once; each merge pass: the
     // keys of the merged lists
-    B[5] = ordered ? pairs * 16.0 + (double)T.n_merge_keys * 16.0 : 0.0;
+    const double kb = sorted ? 16.0 : 8.0;
+    B[5] = ordered ? pairs * kb + (double)T.n_merge_keys * kb : 0.0;
     if (!ordered) {
       B[6] = 12.0 * npx + large * 36.0 +
              24.0 * std::min((double)npx, (double)T.n_coarse_nonempty * kLargeTile * kLargeTile);
       B[7] = fine * 36.0 + 24.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
     } else {
       B[6] = 12.0 * npx;
-      B[7] = pairs * (sorted ? 48.0 : 40.0) +
+      B[7] = pairs * (sorted ? 48.0 : 36.0) +
              12.0 * std::min((double)npx, (double)T.n_fine_nonempty * t2);
     }
     B[8] = (f.mode == SPL_ADD_AEQE ? 24.0 : 12.0) * npx + (f.normalise ? 24.0 * npx : 0.0);
@@ -1744,18 +1757,38 @@ spl_status spl_bin(spl_ctx *c, int64_t n, const float *rec, const float *rec2, i
     HIPTRY(c, hipStreamSynchronize(s));
     return SPL_OK;
   }
-  TRY(ensure(c, c->keysA, T.n_pairs * 8));
-  TRY(ensure(c, c->keysB, T.n_pairs * 8));
   for (int k = 1; k < 3; ++k) {
     TRY(ensure(c, c->items[k], T.n_items[k] * sizeof(Item)));
     if (T.n_items[k])
       HIPTRY(c, launch_build_items(counts, offsets, nb, nb, chunk[k], 0, minc[k],
                                    item_off + k * (nb + 1), (Item *)c->items[k].p, s));
   }
+  if (by_depth == 2) {
+    // the stable order: the index lists sorted in place (the merge passes'
+    // second buffer in the workspace)
+    TRY(ensure(c, c->keysB, T.n_pairs * 4));
+    uint32_t *B2 = (uint32_t *)c->keysB.p;
+    HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, nullptr, n, tk,
+                             (uint32_t *)c->cursor.p, pairs, nullptr, umask, s));
+    HIPTRY(c, launch_sort_chunks(pairs, (const Item *)c->items[1].p, (int)T.n_items[1], s));
+    int passes = 0;
+    for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {
+      HIPTRY(c, launch_merge_pass(passes % 2 ? B2 : pairs, passes % 2 ? pairs : B2,
+                                  (const Item *)c->items[2].p, (int)T.n_items[2], offsets, counts,
+                                  (int)L, s));
+      ++passes;
+    }
+    if (passes > 0)
+      HIPTRY(c, launch_copy_items(B2, pairs, (const Item *)c->items[2].p, (int)T.n_items[2],
+                                  counts, (uint32_t)kSortChunk, s));
+    HIPTRY(c, hipStreamSynchronize(s));
+    return SPL_OK;
+  }
+  TRY(ensure(c, c->keysA, T.n_pairs * 8));
+  TRY(ensure(c, c->keysB, T.n_pairs * 8));
   unsigned long long *A = (unsigned long long *)c->keysA.p, *B = (unsigned long long *)c->keysB.p;
-  // keys: depth bits and index, or the index alone (by_depth = 2)
-  HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, by_depth == 1 ? rec2 : nullptr, n, tk,
-                           (uint32_t *)c->cursor.p, nullptr, A, umask, s));
+  HIPTRY(c, launch_scatter((const uint2 *)c->span.p, rec, rec2, n, tk, (uint32_t *)c->cursor.p,
+                           nullptr, A, umask, s));
   HIPTRY(c, launch_sort_chunks(A, (const Item *)c->items[1].p, (int)T.n_items[1], s));
   int passes = 0;
   for (int64_t L = kSortChunk; L < (int64_t)T.max_count; L *= 2) {

@@ -286,11 +286,17 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
                           const TileK &tk, uint32_t *cursor, uint32_t *pairs,
                           unsigned long long *keys, const uint32_t *umask, hipStream_t s);
 
+// The list sorts take 64-bit (depth bits, index) keys or 32-bit indices (the
+// stable order).
 hipError_t launch_sort_chunks(unsigned long long *keys, const Item *items, int n_items,
                               hipStream_t s);
+hipError_t launch_sort_chunks(uint32_t *keys, const Item *items, int n_items, hipStream_t s);
 hipError_t launch_merge_pass(const unsigned long long *src, unsigned long long *dst,
                              const Item *items, int n_items, const uint32_t *offsets,
                              const uint32_t *counts, int run, hipStream_t s);
+hipError_t launch_merge_pass(const uint32_t *src, uint32_t *dst, const Item *items, int n_items,
+                             const uint32_t *offsets, const uint32_t *counts, int run,
+                             hipStream_t s);
 hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32_t *pids,
                                hipStream_t s);
 // Copies the items of the lists whose merge passes end in the second buffer
@@ -298,6 +304,8 @@ hipError_t launch_keys_to_pids(const unsigned long long *keys, int64_t n, uint32
 hipError_t launch_copy_items(const unsigned long long *src, unsigned long long *dst,
                              const Item *items, int n_items, const uint32_t *counts, uint32_t k0,
                              hipStream_t s);
+hipError_t launch_copy_items(const uint32_t *src, uint32_t *dst, const Item *items, int n_items,
+                             const uint32_t *counts, uint32_t k0, hipStream_t s);
 
 hipError_t launch_splat_add(int tile, const Item *items, int n_items, const uint32_t *pairs,
                             const float *rec, const uint32_t *counts, int chunk,
@@ -317,10 +325,11 @@ hipError_t launch_splat_views(int tile, const ViewK *views, const Item *fine, co
                               bool any_large, hipStream_t s);
 // keys: the buffer the scatter wrote; keys_b: the merge passes' other buffer
 // (each list is read from the one its merge passes end in, sort_chunk = k0).
-// rec2 NULL: no absorption, the ordered additive sum, added into img (the
-// depth-sorted composite, with rec2, writes img).
+// With rec2: 64-bit (depth bits, index) keys, the depth-sorted composite,
+// which writes img.  rec2 NULL: 32-bit indices in ascending order, no
+// absorption, the ordered additive sum, added into img.
 hipError_t launch_composite(int tile, const Item *items, int n_items,
-                            const unsigned long long *keys, const unsigned long long *keys_b,
+                            const void *keys, const void *keys_b,
                             uint32_t sort_chunk, const float *rec, const float *rec2, const uint32_t *counts, int chunk,
                             const TileK &tk, float *img, float *partial, hipStream_t s);
 // absorb: as rec2 != NULL in the composite it follows.
