@@ -538,15 +538,34 @@ def stream_leg(args, torch, B, ctx, ps, pose, prm, parts):
 
     copy = time_it(copies)
     del srcs, dsts
+    ref = ctx.spl_render_stream(host, chunk, pose, prm, stats=False)[0].cpu().numpy()
     host.close()
     # the overlap saves copy + resident - streamed against copying, then
     # rendering; at most the render time can hide under the copies
     overlap = copy + resident - streamed
+    # the same frame from BF16 attributes in host memory (rounded to nearest
+    # even here, by the caller): 19 bytes per particle over the link instead
+    # of 25; its error against the FP32 frame
+    def bf16_bits(a):
+        u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+        return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+    hb = B.PinnedParticles(ps, {"h": bf16_bits(ps.h), "intensity": bf16_bits(ps.intensity),
+                                "scalar": bf16_bits(ps.scalar)}, B.SPL_BF16)
+    streamed_bf16 = time_it(lambda: ctx.spl_render_stream(hb, chunk, pose, prm, out=img,
+                                                           stats=False))
+    got = ctx.spl_render_stream(hb, chunk, pose, prm, stats=False)[0].cpu().numpy()
+    hb.close()
+    err = float(np.linalg.norm((got - ref).astype(np.float64)) /
+                max(float(np.linalg.norm(ref.astype(np.float64))), 1e-300))
     return {"chunk_particles": chunk, "chunks": -(-ps.n // chunk), "bytes_copied": nbytes,
             "streamed_ms": streamed, "resident_ms": resident, "copies_alone_ms": copy,
             "copy_GBps": nbytes / (copy * 1e-3) / 1e9, "overlap_ms": overlap,
             "render_hidden_fraction": overlap / resident if resident > 0 else 0.0,
-            "particles_per_s": ps.n / (streamed * 1e-3)}
+            "particles_per_s": ps.n / (streamed * 1e-3),
+            "bf16": {"bytes_copied": ps.n * (12 + 6 + 1), "streamed_ms": streamed_bf16,
+                     "particles_per_s": ps.n / (streamed_bf16 * 1e-3),
+                     "rel_l2_vs_f32": err}}
 
 
 def bandwidth_probe(args, torch, B, ctx, n):

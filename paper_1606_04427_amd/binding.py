@@ -259,9 +259,12 @@ class DeviceParticles(Dataset):
 
 class PinnedParticles:
     """Host copies of a particle set in page-locked memory (spl_host_alloc),
-    the input of out-of-core rendering (spl_render_stream)."""
+    the input of out-of-core rendering (spl_render_stream).  attrs: optional
+    stored smoothing length, intensity and scalar arrays (dict with keys h,
+    intensity, scalar, in the layout of attr_dtype, e.g. BF16 bit patterns as
+    uint16) to use instead of the set's FP32 values; the scales stay 1."""
 
-    def __init__(self, ps):
+    def __init__(self, ps, attrs=None, attr_dtype=SPL_F32):
         self.L = lib()
         self.blocks = []
 
@@ -279,14 +282,20 @@ class PinnedParticles:
         st = spl_particles()
         st.n = int(ps.x.shape[0])
         st.x, st.y, st.z = pin(ps.x, np.float32), pin(ps.y, np.float32), pin(ps.z, np.float32)
-        st.h = pin(ps.h, np.float32)
-        st.intensity = pin(ps.intensity, np.float32)
-        st.scalar = pin(ps.scalar, np.float32)
-        st.attr_dtype = SPL_F32
+        if attrs is None:
+            st.h = pin(ps.h, np.float32)
+            st.intensity = pin(ps.intensity, np.float32)
+            st.scalar = pin(ps.scalar, np.float32)
+            st.attr_dtype = SPL_F32
+        else:
+            st.h = pin(attrs["h"], attrs["h"].dtype)
+            st.intensity = pin(attrs["intensity"], attrs["intensity"].dtype)
+            st.scalar = pin(attrs["scalar"], attrs["scalar"].dtype)
+            st.attr_dtype = attr_dtype
         st.h_scale = st.i_scale = st.s_scale = st.c_scale = 1.0
         st.species = pin(ps.species, np.uint8)
         st.absorption = None
-        st.rgb = pin(getattr(ps, "rgb", None), np.float32)
+        st.rgb = pin(getattr(ps, "rgb", None), np.float32) if attrs is None else None
         self.st = st
         self.n = st.n
 
