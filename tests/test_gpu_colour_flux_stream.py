@@ -205,3 +205,37 @@ def test_stream_of_an_empty_set(env):
                                     B.make_params(1, B.Palettes(pals), looks))
     torch.cuda.synchronize()
     assert float(img.abs().sum()) == 0.0 and st["n_active"] == 0
+
+
+def test_streamed_frame_from_bf16_host_attributes(env):
+    """Out-of-core frame whose host arrays hold BF16 attributes (rounded to
+    nearest even on the host): the same stored bits as a BF16 data set, so
+    the streamed image equals that data set's resident render to rounding,
+    and the oracle on the FP32 originals within the BF16 bar."""
+    import torch
+
+    B, ctx, R = env
+    ps, looks, pals = _set(300_000, 95, absorption=False)
+    P = B.Palettes(pals)
+    prm = B.make_params(1, P, looks, tile=16, large_cut=32.0)
+    pose = synth.random_poses(1, seed=452, width=384, height=256, dist_range=(0.6, 1.2))[0]
+    print("stream bf16 host attributes", flush=True)
+    ds = B.Dataset(ctx, ps, "bf16")
+    res, st_res = ctx.spl_render_dataset(ds, pose, prm)
+
+    def bits(a):
+        u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+        return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+    host = B.PinnedParticles(ps, {"h": bits(ps.h), "intensity": bits(ps.intensity),
+                                  "scalar": bits(ps.scalar)}, B.SPL_BF16)
+    img, st = ctx.spl_render_stream(host, 70_000, pose, prm)  # 5 chunks, ragged
+    torch.cuda.synchronize()
+    host.close()
+    got = img.cpu().numpy().astype(np.float64)
+    assert st["n_active"] == st_res["n_active"] and st["n_pairs"] == st_res["n_pairs"]
+    assert rel_l2(got, res.cpu().numpy()) < 1e-6
+    L = R.Looks([dict(rgb=p, **l) for p, l in zip(pals, looks)])
+    want = R.render(R.Particles(ps), pose, R.params(1, L))
+    assert rel_l2(got, want) < TOL["bf16"]
+    ds.close()
