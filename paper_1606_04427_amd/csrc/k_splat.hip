@@ -349,8 +349,10 @@ __device__ __forceinline__ void splat_add_item(const Item it, const uint32_t *__
   }
 }
 
+// Eight workgroups per CU with 16 px tiles; the 32 px tiles' micro-tile
+// lists take four times the LDS, which holds them to four.
 template <int T>
-__global__ __launch_bounds__(kBlock, 8) void k_splat_add(const Item *__restrict__ items,
+__global__ __launch_bounds__(kBlock, T == 16 ? 8 : 4) void k_splat_add(const Item *__restrict__ items,
                                                       const uint32_t *__restrict__ pairs,
                                                       const float4 *__restrict__ rec,
                                                       const uint32_t *__restrict__ counts,
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_splat_add(const Item *__restrict_
 // Persistent form for many views: workgroups take (view, tile chunk) items
 // from a device counter until the queue is empty; every workgroup exits.
 template <int T>
-__global__ __launch_bounds__(kBlock, 8) void k_splat_add_views(const ViewK *__restrict__ views,
+__global__ __launch_bounds__(kBlock, T == 16 ? 8 : 4) void k_splat_add_views(const ViewK *__restrict__ views,
                                                             const Item *__restrict__ items,
                                                             const uint32_t *__restrict__ n_items,
                                                             uint32_t *__restrict__ next,
