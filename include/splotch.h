@@ -267,7 +267,8 @@ spl_status spl_render_dataset(spl_ctx *ctx, const spl_dataset *ds, const spl_cam
  * particle the frame needs 40 bytes (48 in sorted mode), checked before any
  * work is enqueued (at most about 3.3M and 2.8M particles); the lists, known
  * after the count, need 4 bytes per (particle, tile) entry (16 in sorted
- * mode), so at 1.5 entries per particle about 2.9M and 1.8M particles fit.
+ * mode, 8 in the deterministic additive order), so at 1.5 entries per
+ * particle about 2.9M and 1.8M particles fit.
  * Every call on one device shares that device's array and finds the previous
  * call's contents there (the frame clears what must start at zero): calls
  * that overlap on one device, from any context, thread or stream, race and

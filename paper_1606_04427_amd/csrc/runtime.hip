@@ -480,7 +480,7 @@ struct Frame {
   bool flux_check = false;       // expected flux of the records (additive modes)
   bool clear = true;             // zero the image first (else add into it)
   bool finish = true;            // final map, FP64 reductions, normalisation
-  bool ordered = false;          // keyed lists sorted, drawn by the composite walk
+  bool ordered = false;          // lists sorted on the index, drawn by the composite walk
 };
 
 // ---- stage timers ---------------------------------------------------------
@@ -579,7 +579,8 @@ spl_status render_lists(spl_ctx *c, const Frame &f, spl_stats *st, hipStream_t s
   const TileK &tk = f.tk;
   const int nb = tk.n_tiles + tk.n_ctiles;
   const bool sorted = f.mode == SPL_SORTED;
-  // sorted mode, and the additive modes in list order (keys = index alone)
+  // sorted mode (64-bit depth keys), and the additive modes in the stable
+  // order (the 32-bit index lists sorted on the index)
   const bool ordered = sorted || f.ordered;
   const int64_t npx = (int64_t)tk.W * tk.H;
   uint32_t *counts = (uint32_t *)c->counts.p, *offsets = (uint32_t *)c->offsets.p,
