@@ -433,6 +433,10 @@ def run_additive(args, torch, B):
     ctx.close()
     if not args.no_serving:
         out["serving"] = serving_leg(args, torch, B)
+    if not args.no_batched_leg:
+        t = time.time()
+        out["batched_200M"] = batched_leg(args, torch, B)
+        log(f"batched 200M leg in {time.time() - t:.1f} s")
     if not args.no_cpu_baseline:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(ps, poses, looks, pals, args.cpu_sample or 5_000_000,
@@ -471,6 +475,27 @@ def deterministic_leg(args, torch, B, ctx, parts, poses, pal_d, looks, imgs, fre
             "vs_unordered_one_view_per_call": free_ms / ms_per_step,
             "bit_identical_repeats": same, "rel_l2_vs_unordered": err,
             "stages": stage_table(B, ms, by, frames)}
+
+
+def batched_leg(args, torch, B):
+    """The batched reduced-precision configuration in the default run: 200M
+    particles with BF16 attributes, 64 views alternating 4096^2 and 1024^2 in
+    one call, the tile and cut per image size the batched workload's own
+    tuning picks (16 px, no large path at 4096^2; 16 px, 64 px cut at
+    1024^2), 2 timed steps; error against the FP64 oracle on two views of a
+    1M-particle subsample."""
+    import copy
+
+    a = copy.copy(args)
+    a.n, a.dtypes, a.steps, a.views, a.error_views = 0, "bf16", 2, 64, 2
+    out = run_batched(a, torch, B, fixed={4096: (16, -1.0), 1024: (16, 64.0)})
+    v = out["variants"]["bf16"]
+    return {"workload": out["config"]["workload"], "dtype": "bf16",
+            "particle_views_per_s": out["value"], "ms_per_step": out["ms_per_step"],
+            "batched_graph": v["batched_graph"], "per_view_calls": v["per_view"],
+            "stages_ms_per_step": v["stages_ms_per_step"],
+            "error_vs_fp64_oracle_1M_subsample": v["error_vs_fp64_oracle_1M_subsample"],
+            "tile_cut_by_size": v["tile_cut_by_size"]}
 
 
 def sorted_leg(args, torch, B, ctx):
@@ -775,7 +800,8 @@ def run_sorted(args, torch, B):
 
 
 # ----------------------------------------------------------------------------
-def run_batched(args, torch, B):
+def run_batched(args, torch, B, fixed=None):
+    """fixed: {image width: (tile, cut)} to use instead of tuning."""
     from oracle import splref as R
     from paper_1606_04427_amd import synth
 
@@ -801,7 +827,11 @@ def run_batched(args, torch, B):
         torch.cuda.synchronize()
         prms = [prm] * len(poses)
         tuned, trials = {}, {}
-        if not args.no_autotune:
+        if fixed:
+            tuned = dict(fixed)
+            prms = [B.make_params(B.SPL_ADD_AEQE, pal_d, looks, tile=tuned[p.width][0],
+                                  large_cut=tuned[p.width][1]) for p in poses]
+        elif not args.no_autotune:
             # one tuning per image size; the library applies the latest choice
             # for an image size to the poses it did not tune
             for p in (big[0], small[0]):
@@ -1078,6 +1108,8 @@ def main():
                     help="additive: skip the serving sub-record")
     ap.add_argument("--no-sorted-leg", action="store_true",
                     help="additive: skip the depth-sorted sub-record")
+    ap.add_argument("--no-batched-leg", action="store_true",
+                    help="additive: skip the 200M-particle, 64-view BF16 batched sub-record")
     ap.add_argument("--no-deterministic-leg", action="store_true",
                     help="additive: skip the list-order (bit-identical) frames")
     ap.add_argument("--no-graph-replay", action="store_true",
