@@ -437,6 +437,10 @@ def run_additive(args, torch, B):
         t = time.time()
         out["batched_200M"] = batched_leg(args, torch, B)
         log(f"batched 200M leg in {time.time() - t:.1f} s")
+    if not args.no_orbit_leg:
+        t = time.time()
+        out["orbit"] = orbit_leg(args, torch, B)
+        log(f"orbit leg in {time.time() - t:.1f} s")
     if not args.no_cpu_baseline:
         t = time.time()
         out["cpu_baseline"] = cpu_baseline(ps, poses, looks, pals, args.cpu_sample or 5_000_000,
@@ -475,6 +479,19 @@ def deterministic_leg(args, torch, B, ctx, parts, poses, pal_d, looks, imgs, fre
             "vs_unordered_one_view_per_call": free_ms / ms_per_step,
             "bit_identical_repeats": same, "rel_l2_vs_unordered": err,
             "stages": stage_table(B, ms, by, frames)}
+
+
+def orbit_leg(args, torch, B):
+    """The orbit animation in the default run: 55M particles, 100-frame orbit
+    at 1024^2 per batched call (1 warm-up, 2 timed steps, the library's tile
+    and cut), and the 6-pose far-to-near sweep one view per call."""
+    import copy
+
+    a = copy.copy(args)
+    a.n, a.steps, a.warmup, a.no_autotune, a.no_cpu_baseline = 0, 2, 1, True, True
+    out = run_orbit(a, torch, B)
+    return {"workload": out["config"]["workload"], "particles_per_s": out["value"],
+            "ms_per_frame": out["ms_per_frame"], "sweep": out["sweep"]}
 
 
 def batched_leg(args, torch, B):
@@ -1108,6 +1125,8 @@ def main():
                     help="additive: skip the serving sub-record")
     ap.add_argument("--no-sorted-leg", action="store_true",
                     help="additive: skip the depth-sorted sub-record")
+    ap.add_argument("--no-orbit-leg", action="store_true",
+                    help="additive: skip the 55M-particle orbit animation sub-record")
     ap.add_argument("--no-batched-leg", action="store_true",
                     help="additive: skip the 200M-particle, 64-view BF16 batched sub-record")
     ap.add_argument("--no-deterministic-leg", action="store_true",
