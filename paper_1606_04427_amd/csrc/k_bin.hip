@@ -558,13 +558,15 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
     hipLaunchKernelGGL(k_count, dim3((int)g), dim3(kBlock), sh, s, span, r, n, tk, counts);
     return hipGetLastError();
   }
-  // packed 16-bit bins: one 512-lane window up to 2 kLdsBins bins (64 KB),
-  // else equal windows of at most 2 kBigBins bins in the CU's whole LDS (one
-  // pass over the spans each); when the scatter will need three or more
-  // windows (where that pays) the first pass also builds the unit masks
+  // packed 16-bit bins in 1024-lane workgroups: one window up to 2 kLdsBins
+  // bins (64 KB, two workgroups per CU; 16384 bins 0.062 -> 0.056 ms at 10M
+  // against 512 lanes), else equal windows of at most 2 kBigBins bins in the
+  // CU's whole LDS (one pass over the spans each); when the scatter will need
+  // three or more windows (where that pays) the first pass also builds the
+  // unit masks
   const bool big = nb > 2 * kLdsBins;
   const int cap = big ? 2 * kBigBins : 2 * kLdsBins;
-  const int nt = big ? kBigThreads : 2 * kBlock;
+  const int nt = kBigThreads;
   const int n_win = (nb + cap - 1) / cap;
   const int per = (((nb + n_win - 1) / n_win) + 1) & ~1;
   const int64_t units = (n + kUnit - 1) / kUnit;
@@ -585,8 +587,7 @@ hipError_t launch_count(const uint2 *span, const float *rec, int64_t n, const Ti
                          umask, (int)(lo == 0 && umask != nullptr));
       return hipGetLastError();
     };
-    const hipError_t e = big ? launch(k_count_packed<kBigThreads>)
-                             : launch(k_count_packed<2 * kBlock>);
+    const hipError_t e = launch(k_count_packed<kBigThreads>);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -698,17 +699,14 @@ hipError_t launch_scatter(const uint2 *span, const float *rec, const float *rec2
                          pairs, keys, umask);
       return hipGetLastError();
     };
-    // a histogram above 32 KB leaves few workgroups per CU: 512 lanes each
-    // keep more waves resident; above 64 KB one 1024-lane workgroup per CU
-    hipError_t e;
-    if (nbw > kLdsBins)
-      e = keys ? launch(k_scatter<true, kBigThreads>, kBigThreads)
-               : launch(k_scatter<false, kBigThreads>, kBigThreads);
-    else if (nbw > kLdsBins / 2)
-      e = keys ? launch(k_scatter<true, 2 * kBlock>, 2 * kBlock)
-               : launch(k_scatter<false, 2 * kBlock>, 2 * kBlock);
-    else
-      e = keys ? launch(k_scatter<true, kBlock>, kBlock) : launch(k_scatter<false, kBlock>, kBlock);
+    // 1024-lane workgroups in every window: two per CU up to 64 KB of bins,
+    // one above.  Each workgroup reserves its slots with one global atomic
+    // per non-empty bin, so fewer, wider workgroups issue fewer of them (10M
+    // particles: 4352 bins 0.108 -> 0.100 ms per view against 256-lane
+    // workgroups, 16384 bins 0.196 -> 0.153 ms against 512 lanes; one
+    // 1024-lane workgroup per CU was slower than two, 0.136 ms at 4352 bins)
+    const hipError_t e = keys ? launch(k_scatter<true, kBigThreads>, kBigThreads)
+                              : launch(k_scatter<false, kBigThreads>, kBigThreads);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
