@@ -188,6 +188,18 @@ struct spl_ctx {
 
 namespace {
 
+// Page-locked host memory that the read-back kernel writes while the host
+// watches it: fine-grained (coherent), so the device's stores go to host
+// memory instead of waiting in a device cache for a write-back; the default
+// (coarse-grained) kind if the runtime refuses that.
+hipError_t watched_host_alloc(void **p, size_t bytes) {
+  if (hipHostMalloc(p, bytes, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess)
+    return hipSuccess;
+  (void)hipGetLastError();
+  *p = nullptr;
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
 spl_status fail(spl_ctx *c, spl_status code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 spl_status fail(spl_ctx *c, spl_status code, const char *fmt, ...) {
   if (c) {
@@ -537,13 +549,13 @@ void resolve_timing(spl_ctx *c, bool wait) {
 }
 
 // Reads `bytes` of device memory at src back into page-locked host memory
-// (dst_mapped: its device-side address) and waits until they are there: the
-// read-back kernel writes them, then, after a system-scope fence, this
-// call's sequence number into h_flag, which the host watches (a stream
-// synchronisation would add its own wake-up latency while the device waits
-// for the host's next launches).  After kSpinMicros without the number the
-// host blocks on the stream instead (a long frame, or a failed launch whose
-// error the synchronisation then reports).
+// (dst_mapped: its device-side address; fine-grained, as h_flag) and waits
+// until they are there: the read-back kernel writes them, then, after a
+// system-scope fence, this call's sequence number into h_flag, which the
+// host watches (a stream synchronisation would add its own wake-up latency
+// while the device waits for the host's next launches).  After kSpinMicros
+// without the number the host blocks on the stream instead (a long frame, or
+// a failed launch whose error the synchronisation then reports).
 constexpr int kSpinMicros = 20000;
 
 spl_status readback_wait(spl_ctx *c, const void *src, void *dst_mapped, size_t bytes,
@@ -802,7 +814,7 @@ spl_status ensure_host(spl_ctx *c, int views) {
   c->h_ctr = nullptr;
   c->h_bstats = nullptr;
   c->h_cap = 0;
-  if (hipHostMalloc((void **)&c->h_btot, sizeof(Totals) * views, hipHostMallocDefault) != hipSuccess ||
+  if (watched_host_alloc((void **)&c->h_btot, sizeof(Totals) * views) != hipSuccess ||
       hipHostMalloc((void **)&c->h_views, sizeof(ViewK) * views, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_ctr, 2 * sizeof(uint32_t) * views, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->h_bstats, kStatWords * sizeof(double) * views,
@@ -1569,10 +1581,10 @@ spl_status spl_create(int device, spl_ctx **out) {
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
     c->n_cu = ncu;
-  if (hipHostMalloc((void **)&c->h_tot, sizeof(Totals), hipHostMallocDefault) != hipSuccess ||
+  if (watched_host_alloc((void **)&c->h_tot, sizeof(Totals)) != hipSuccess ||
       hipHostMalloc((void **)&c->h_stats, kStatWords * sizeof(double), hipHostMallocDefault) !=
           hipSuccess ||
-      hipHostMalloc((void **)&c->h_flag, 64, hipHostMallocDefault) != hipSuccess) {
+      watched_host_alloc((void **)&c->h_flag, 64) != hipSuccess) {
     if (c->h_tot) (void)hipHostFree(c->h_tot);
     if (c->h_stats) (void)hipHostFree(c->h_stats);
     delete c;
