@@ -44,6 +44,13 @@ FP32_PEAK_TFLOPS = 157.3
 # distance, the truncation test, three colour multiply-adds counted as two
 # operations each) plus one exponential, counted as one operation
 FLOPS_PER_UPDATE = 12.0
+# Operations per pixel update of the depth-sorted composite: the additive
+# count of 11, the optical depth a w (1), the degree-5 polynomial for
+# phi(x) = (1 - exp(-x)) / x (five multiply-adds, 10), exp(-x) - 1 from it
+# (1), the weight T w phi (2) and the transmittance update (one
+# multiply-add, 2), plus the Gaussian's exponential (1).  Optical depths of
+# 1/2 and more take an exponential and a reciprocal instead of the polynomial.
+FLOPS_PER_COMPOSITE_UPDATE = 28.0
 METRIC = "particles/s + HBM GB/s per frame; p50/p99 latency on mixed-view stream"
 KERNEL_OF_STAGE = {"splat": "k_splat_add", "project": "k_project", "large_splat": "k_splat_large",
                    "scatter": "k_scatter", "count": "k_count", "finalise": "k_finalise",
@@ -187,7 +194,7 @@ def stage_table(B, ms, by, frames):
     return out
 
 
-def roofline_for(B, ms, by, launches, updates_per_launch=None):
+def roofline_for(B, ms, by, launches, updates_per_launch=None, flops_per_update=FLOPS_PER_UPDATE):
     """Roofline of the dominant stage; `launches` is the number of launches
     the accumulated stage times cover (frames for one view per call, steps
     for the batched call)."""
@@ -200,12 +207,12 @@ def roofline_for(B, ms, by, launches, updates_per_launch=None):
     if name == "splat" and updates_per_frame:
         # the splat evaluates a Gaussian per pixel of each particle's box: its
         # bound is the vector ALU, not HBM
-        achieved = FLOPS_PER_UPDATE * updates_per_frame / (per_launch * 1e-3) / 1e12
+        achieved = flops_per_update * updates_per_frame / (per_launch * 1e-3) / 1e12
         return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
                 "kernel": KERNEL_OF_STAGE[name], "ms_per_launch": per_launch,
                 "updates_per_launch": updates_per_frame,
-                "flops_per_update": FLOPS_PER_UPDATE,
+                "flops_per_update": flops_per_update,
                 "hbm_GBps": by[dom] / (ms[dom] * 1e-3) / 1e9,
                 "hbm_frac": by[dom] / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                 "bytes_per_launch": by[dom] / max(frames, 1)}
@@ -532,7 +539,12 @@ def sorted_leg(args, torch, B, ctx):
 
     elapsed, ms, by, frames = timed_steps(ctx, step, args.steps, args.warmup, torch)
     st = ctx.spl_render_dataset(parts, pose, prm, out=img)[1]
-    roof = roofline_for(B, ms, by, frames)
+    # outside the timed region: the pixel updates the composite evaluates (every
+    # listed particle's clipped box; sorted mode has no large-particle cut)
+    rec, _ = ctx.spl_project(parts, pose, prm)
+    updates, _ = box_pixels(rec.cpu().numpy(), pose.width, pose.height, 0.0)
+    del rec
+    roof = roofline_for(B, ms, by, frames, updates, FLOPS_PER_COMPOSITE_UPDATE)
     if roof["kernel"] == "k_splat_add":
         roof["kernel"] = "k_composite"  # the sorted mode's splat stage
     parts.close()
@@ -799,12 +811,15 @@ def run_sorted(args, torch, B):
     ms_per_step = 1e3 * elapsed / args.steps
     value = args.steps * ps.n / elapsed
     st = ctx.spl_render(parts, pose, prm, out=img)[1]
+    rec, _ = ctx.spl_project(parts, pose, prm)
+    updates, _ = box_pixels(rec.cpu().numpy(), pose.width, pose.height, 0.0)
+    del rec
     log(f"{args.steps} steps in {elapsed:.3f} s, {ms_per_step:.2f} ms/step, {value:.3e} particles/s")
     out = base_record(args, value, ms_per_step, "f32", {
         "workload": "Soneira-Peebles clustered set, 10M particles with absorption U[0.01,0.5], "
                     "2048x2048, depth-sorted transfer, FP32", "n_particles": ps.n,
         "image": [2048, 2048], "poses": 1, "tile": st["tile"]})
-    roof = roofline_for(B, ms, by, frames)
+    roof = roofline_for(B, ms, by, frames, updates, FLOPS_PER_COMPOSITE_UPDATE)
     if roof["kernel"] == "k_splat_add":
         roof["kernel"] = "k_composite"  # the sorted mode's splat stage
     out.update({"roofline": roof, "stages": stage_table(B, ms, by, frames),

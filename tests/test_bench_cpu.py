@@ -53,6 +53,18 @@ def test_splat_dominant_is_priced_against_the_fp32_vector_peak():
     assert r["traffic"] is None
 
 
+def test_composite_is_priced_with_its_own_operation_count():
+    # the depth-sorted composite: 28 operations per update (the additive 12
+    # plus the optical depth, the polynomial for phi, the weight and the
+    # transmittance update)
+    ms, by = _times(splat=(3.0, 3 * 8e8))
+    r = bench.roofline_for(B, ms, by, 3, 5e8, bench.FLOPS_PER_COMPOSITE_UPDATE)
+    assert bench.FLOPS_PER_COMPOSITE_UPDATE == 28.0
+    assert r["bound"] == "alu" and r["flops_per_update"] == 28.0
+    assert r["achieved"] == pytest.approx(28.0 * 5e8 / 1e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+
+
 def test_other_dominant_stage_is_priced_against_hbm():
     # the host gap is never the dominant kernel, however long it is
     ms, by = _times(host_gap_items=(100.0, 0.0), scatter=(10.0, 4e10), splat=(2.0, 1e9))
