@@ -7,7 +7,6 @@ path: if the library is missing or fails to load, every call raises.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 
 import numpy as np
