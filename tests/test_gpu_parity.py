@@ -316,6 +316,32 @@ def test_binning_bit_exact_in_windows(env, tile, rule):
             assert np.array_equal(np.sort(t | p.astype(np.uint64)), np.sort(t | rp.astype(np.uint64)))
 
 
+@pytest.mark.parametrize("W,H", [(128, 64), (2731, 3), (128, 128), (145, 113), (256, 128),
+                                 (331, 99), (256, 160), (6827, 6), (320, 256), (3901, 21)])
+def test_binning_bit_exact_at_window_limits(env, W, H):
+    """1 px tiles on both sides of each limit of the binning's launch shapes:
+    8192 bins (the count's packed bins from here), 16384 (one 64 KB scatter
+    window), 32768 (one 64 KB window of packed count bins), 40960 (one scatter
+    window in the CU's whole LDS) and 81920 (one such window of packed count
+    bins; one bin more and the scatter takes three windows and the per-unit
+    band masks)."""
+    B, ctx, R = env
+    ps, poses = _sp_case(30000, W=W, H=H, absorption=True)
+    looks, pals = _looks(ps, n_species=2, brightness=0.05)
+    rec, rec2, _ = _records(env, ps, poses[0], 2, looks, pals)
+    for by_depth in (False, True):
+        c, o, p = ctx.spl_bin(rec, rec2, W, H, 1, 3.0, 0, by_depth)
+        c, o, p = c.cpu().numpy().view(np.uint32), o.cpu().numpy().view(np.uint32), p.cpu().numpy().view(np.uint32)
+        rc, ro, rp = R.bin_records(rec.cpu().numpy(), rec2.cpu().numpy(), W, H, 1, 3.0, 0, by_depth)
+        assert len(c) == W * H
+        assert np.array_equal(c, rc) and np.array_equal(o, ro)
+        if by_depth:
+            assert np.array_equal(p, rp)
+        else:
+            t = np.repeat(np.arange(len(rc), dtype=np.uint64), rc.astype(np.int64)) << np.uint64(32)
+            assert np.array_equal(np.sort(t | p.astype(np.uint64)), np.sort(t | rp.astype(np.uint64)))
+
+
 def test_paper_rule_hand_case_on_device(env):
     import json
     import os
