@@ -101,7 +101,7 @@ class Server:
     frees device memory at once)."""
 
     def __init__(self, make_executor, n_workers: int = 2, budget_bytes: int = 64 << 30,
-                 max_views: int = 16, cost=None, keep=None, clock=time.perf_counter):
+                 max_views: int = 4, cost=None, keep=None, clock=time.perf_counter):
         if n_workers < 1 or max_views < 1 or budget_bytes <= 0:
             raise ValueError("n_workers, max_views and budget_bytes must be positive")
         self.make_executor = make_executor
