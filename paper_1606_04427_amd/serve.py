@@ -98,7 +98,10 @@ class Server:
     executor's trim(), if it has one) and tells the other workers, which then
     do the same, so the head always runs eventually.  keep(request) decides
     whether the image is kept on the request after completion (dropping it
-    frees device memory at once)."""
+    frees device memory at once).  max_views bounds a batch: a request that
+    arrives as a batch starts waits for all of it, so small batches keep the
+    tail latency down (at 100M particles, 4 views gave a p99 of about 90 ms at
+    full load against about 150 ms with 8 or 16, for the same throughput)."""
 
     def __init__(self, make_executor, n_workers: int = 2, budget_bytes: int = 64 << 30,
                  max_views: int = 4, cost=None, keep=None, clock=time.perf_counter):
