@@ -497,6 +497,7 @@ def orbit_leg(args, torch, B):
     a.n, a.steps, a.warmup, a.no_autotune, a.no_cpu_baseline = 0, 2, 1, True, True
     out = run_orbit(a, torch, B)
     return {"workload": out["config"]["workload"], "particles_per_s": out["value"],
+            "batch_workspace_gib": out["config"]["batch_workspace_gib"],
             "ms_per_frame": out["ms_per_frame"], "sweep": out["sweep"]}
 
 
@@ -514,6 +515,7 @@ def batched_leg(args, torch, B):
     out = run_batched(a, torch, B, fixed={4096: (16, -1.0), 1024: (16, 64.0)})
     v = out["variants"]["bf16"]
     return {"workload": out["config"]["workload"], "dtype": "bf16",
+            "batch_workspace_gib": out["config"]["batch_workspace_gib"],
             "particle_views_per_s": out["value"], "ms_per_step": out["ms_per_step"],
             "batched_graph": v["batched_graph"], "per_view_calls": v["per_view"],
             "stages_ms_per_step": v["stages_ms_per_step"],
@@ -686,6 +688,7 @@ def run_orbit(args, torch, B):
     looks, pals = looks_for(ps)
     dev = "cuda:0"
     ctx = B.Context(0)
+    ctx.spl_set_option(B.SPL_OPT_BATCH_BYTES, args.batch_gib << 30)
     parts = B.DeviceParticles(ps, dev)
     prm = B.make_params(B.SPL_ADD_AEQE, B.Palettes(pals, dev), looks)
     if not args.no_autotune:
@@ -734,7 +737,8 @@ def run_orbit(args, torch, B):
         "workload": f"orbit animation: Soneira-Peebles clustered set, {ps.n} particles, 2 species, "
                     "100-frame orbit at 1024x1024 per step in one batched call, additive "
                     "absorption=emission, FP32; plus a 6-pose far-to-near sweep",
-        "n_particles": ps.n, "image": [1024, 1024], "frames_per_step": len(orbit)})
+        "n_particles": ps.n, "image": [1024, 1024], "frames_per_step": len(orbit),
+        "batch_workspace_gib": args.batch_gib})
     out.update({"ms_per_frame": 1e3 * elapsed / frames, "sweep": rows})
     ctx.close()
     if not args.no_cpu_baseline:
@@ -854,6 +858,7 @@ def run_batched(args, torch, B, fixed=None):
     results = {}
     for dt_name in args.dtypes.split(","):
         ctx = B.Context(0)
+        ctx.spl_set_option(B.SPL_OPT_BATCH_BYTES, args.batch_gib << 30)
         parts = B.DeviceParticles(ps, dev, dt_name)
         torch.cuda.synchronize()
         prms = [prm] * len(poses)
@@ -965,7 +970,7 @@ def run_batched(args, torch, B, fixed=None):
         "workload": f"Soneira-Peebles clustered set, {ps.n} particles, {len(poses)} views "
                     "alternating 4096^2 and 1024^2, additive absorption=emission, reduced-"
                     "precision attributes, batched launches", "n_particles": ps.n,
-        "views": len(poses)})
+        "views": len(poses), "batch_workspace_gib": args.batch_gib})
     out["variants"] = results
     return out
 
@@ -1152,6 +1157,10 @@ def main():
     ap.add_argument("--dtypes", default="bf16,f16,f32",
                     help="batched: attribute dtypes (the first gives the value; FP32 is the comparison)")
     ap.add_argument("--views", type=int, default=64, help="batched: views per step")
+    ap.add_argument("--batch-gib", type=int, default=160,
+                    help="batched and orbit: GiB of per-view workspace one batched call may "
+                         "hold (SPL_OPT_BATCH_BYTES; the library's default is 48): fewer, longer "
+                         "persistent launches")
     ap.add_argument("--error-views", type=int, default=4, help="batched: views checked")
     ap.add_argument("--requests", type=int, default=150, help="serving: requests per run")
     ap.add_argument("--warm-requests", type=int, default=20)
